@@ -1,0 +1,264 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only builds inputs: grid sizes, per-voxel Lame fields, boundary
+condition tables, constraint node sets with prescribed values, obstacle
+parameters and solver settings.  It performs none of the solver's arithmetic
+(no gradients, transforms, Green operator, projections or acceleration), so
+both the CPU oracle and the GPU path can consume the same arrays.
+
+Units are voxel units (h = 1).  Node (i, j, k) sits at integer position
+(x, y, z) = (i, j, k); voxel (i, j, k) spans [i, i+1] x [j, j+1] x [k, k+1].
+Field layout is [z][y][x] (x fastest); vector fields are [3][z][y][x].
+
+Boundary conditions follow the per-face, per-component description of the
+paper (Section 3.2.1): bc[comp][axis][face] with face 0 at x_J = 0 and face 1
+at x_J = n_J, and the codes below.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+BC_N, BC_D, BC_P = 0, 1, 2
+BASE_SEED = 260726082
+
+
+def lame(E, nu):
+    """Isotropic Lame constants (lambda, mu) from Young's modulus and Poisson ratio."""
+    E = np.asarray(E, dtype=np.float64)
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+@dataclass
+class Strong:
+    """Strong nodal constraints: u[comp[k]] at node[k] = value[k] (Section 4.1)."""
+    node: np.ndarray          # int64 (i, j, k) triples, shape [m, 3]
+    comp: np.ndarray          # int8, shape [m]
+    value: np.ndarray         # float64, shape [m]
+    set_id: int = 0
+
+
+@dataclass
+class Average:
+    """Kinematic relation: mean of u[comp] over a 4- or 8-node support = value (eq 10)."""
+    support: np.ndarray       # int64 node triples, shape [m, k, 3], k in {4, 8}
+    comp: np.ndarray          # int8, shape [m]
+    value: np.ndarray         # float64, shape [m]
+    set_id: int = 0
+
+
+@dataclass
+class Sphere:
+    """Rigid spherical obstacle (Section 5): centre, radius, potential-contact face."""
+    center: np.ndarray        # float64 [3] (x, y, z)
+    radius: float
+    face: int                 # axis*2 + side; the contact face of the block
+
+
+@dataclass
+class Problem:
+    name: str
+    n: tuple                  # voxels (nx, ny, nz)
+    lam: np.ndarray           # float64 [nz, ny, nx]
+    mu: np.ndarray            # float64 [nz, ny, nx]
+    bc: np.ndarray            # int8 [3, 3, 2]
+    strong: List[Strong] = field(default_factory=list)
+    average: List[Average] = field(default_factory=list)
+    sphere: Optional[Sphere] = None
+    r0_factor: float = 1.0    # reference medium = factor * (max lambda, max mu)
+    tol: float = 1e-6
+    acv: str = "P"            # "NONE", "U" or "P"
+    acv_period: int = 2
+    max_iter: int = 2000
+    meta: dict = field(default_factory=dict)
+
+
+def _nodes_box(xs, ys, zs):
+    g = np.stack(np.meshgrid(np.asarray(xs), np.asarray(ys), np.asarray(zs), indexing="ij"), -1)
+    return g.reshape(-1, 3).astype(np.int64)
+
+
+def bc_table(default=BC_N):
+    return np.full((3, 3, 2), default, dtype=np.int8)
+
+
+# ---------------------------------------------------------------------------
+# Random two-phase microstructures (non-overlapping spheres)
+# ---------------------------------------------------------------------------
+
+def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries=100000):
+    """Place non-overlapping spheres uniformly in the cell until the voxelised
+    inclusion fraction reaches phi_target.  Returns (mask [nz,ny,nx] bool, phi)."""
+    nx, ny, nz = n
+    L = float(min(n))
+    mask = np.zeros((nz, ny, nx), dtype=bool)
+    centers, radii = [], []
+    total = nx * ny * nz
+    count = 0
+    for _ in range(max_tries):
+        if count >= phi_target * total:
+            break
+        r = rng.uniform(rmin_frac * L, rmax_frac * L)
+        c = rng.uniform([0.0, 0.0, 0.0], [nx, ny, nz])
+        ok = True
+        for cc, rr in zip(centers, radii):
+            if np.sum((cc - c) ** 2) < (rr + r) ** 2:
+                ok = False
+                break
+        if not ok:
+            continue
+        centers.append(c)
+        radii.append(r)
+        lo = np.maximum(np.floor(c - r).astype(int), 0)
+        hi = np.minimum(np.ceil(c + r).astype(int) + 1, [nx, ny, nz])
+        xs = np.arange(lo[0], hi[0]) + 0.5
+        ys = np.arange(lo[1], hi[1]) + 0.5
+        zs = np.arange(lo[2], hi[2]) + 0.5
+        d2 = ((zs[:, None, None] - c[2]) ** 2 + (ys[None, :, None] - c[1]) ** 2
+              + (xs[None, None, :] - c[0]) ** 2)
+        sub = mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        newly = (d2 < r * r) & ~sub
+        count += int(newly.sum())
+        sub |= d2 < r * r
+    return mask, count / total
+
+
+def two_phase_lame(mask, contrast, nu=0.3):
+    E = np.where(mask, contrast, 1.0)
+    return lame(E, nu)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def c1_inclusion_patch():
+    """16^3 block, spherical inclusion, top patch pressed through strong constraints."""
+    n = (16, 16, 16)
+    nx, ny, nz = n
+    zc, yc, xc = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    incl = (xc - 8) ** 2 + (yc - 8) ** 2 + (zc - 8) ** 2 < 16.0
+    lam, mu = lame(np.where(incl, 400.0, 200.0), 0.3)
+    bc = bc_table(BC_N)
+    bc[2, 2, 0] = BC_D                        # u_z = 0 on the bottom face
+    patch = _nodes_box(range(4, 13), range(4, 13), [16])
+    top = Strong(patch, np.full(len(patch), 2, np.int8), np.full(len(patch), -0.16), set_id=0)
+    pins = Strong(np.array([[8, 8, 0], [8, 8, 0], [16, 8, 0], [8, 16, 0]], np.int64),
+                  np.array([0, 1, 1, 0], np.int8), np.zeros(4), set_id=1)
+    return Problem("C1", n, lam, mu, bc, strong=[top, pins], r0_factor=1.0, tol=1e-8,
+                   meta={"inclusion_voxels": int(incl.sum())})
+
+
+def c2_compact_tension(n=(256, 256, 16), notch_len=64, notch_h=4, radius=8.0, offset=48, disp=None):
+    """Plate with a zero-stiffness notch and two pin-loaded cylinders (CT-like)."""
+    nx, ny, nz = n
+    lam, mu = lame(np.ones((nz, ny, nx)), 0.3)
+    y0 = ny // 2 - notch_h // 2
+    lam[:, y0:y0 + notch_h, :notch_len] = 0.0
+    mu[:, y0:y0 + notch_h, :notch_len] = 0.0
+    bc = bc_table(BC_N)
+    bc[2, 2, 0] = BC_D
+    bc[2, 2, 1] = BC_D
+    if disp is None:
+        disp = 1e-3 * nx
+    xc = notch_len / 2.0
+    sets = []
+    for sid, (yc, val) in enumerate([(ny // 2 + offset, +disp), (ny // 2 - offset, -disp)]):
+        ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="ij")
+        sel = (ii - xc) ** 2 + (jj - yc) ** 2 <= radius * radius
+        ij = np.stack([ii[sel], jj[sel]], -1)
+        nodes = np.concatenate([np.concatenate([ij, np.full((len(ij), 1), k)], 1) for k in range(nz + 1)])
+        sets.append(Strong(nodes.astype(np.int64), np.full(len(nodes), 1, np.int8),
+                           np.full(len(nodes), val), set_id=sid))
+    return Problem("C2", n, lam, mu, bc, strong=sets, r0_factor=0.5, tol=1e-6)
+
+
+def c3_indentation(n=(256, 256, 128), R=96.0, d_over_R=0.002, E=1.0, nu=0.3):
+    """Block fixed at the bottom, traction-free elsewhere, rigid sphere on the top face."""
+    nx, ny, nz = n
+    lam, mu = lame(np.full((nz, ny, nx), E), nu)
+    bc = bc_table(BC_N)
+    bc[:, 2, 0] = BC_D
+    d = d_over_R * R
+    sph = Sphere(np.array([nx / 2.0, ny / 2.0, nz + R - d]), R, face=5)
+    return Problem("C3", n, lam, mu, bc, sphere=sph, r0_factor=5.0, tol=1e-6,
+                   meta={"E": E, "nu": nu, "d": d})
+
+
+def random_cell(seed, n=None, edges=(32, 48, 64, 96, 128), with_patches=True):
+    """Two-phase cell with random DTT face BCs and local Dirichlet patches."""
+    rng = np.random.default_rng(seed)
+    if n is None:
+        n = tuple(int(rng.choice(edges)) for _ in range(3))
+    L = min(n)
+    phi = rng.uniform(0.1, 0.4)
+    mask, phi_got = random_spheres(rng, n, phi)
+    contrast = float(np.exp(rng.uniform(np.log(2.0), np.log(100.0))))
+    lam, mu = two_phase_lame(mask, contrast)
+    while True:
+        bc = (rng.random((3, 3, 2)) < 0.5).astype(np.int8)   # 1 = D, 0 = N
+        if all(bc[c].any() for c in range(3)):
+            break
+    strong = []
+    if with_patches:
+        npatch = int(rng.integers(1, 5))
+        used = []
+        for p in range(npatch):
+            for _ in range(100):
+                s = int(rng.integers(4, 17))
+                axis = int(rng.integers(0, 3))
+                side = int(rng.integers(0, 2))
+                comps = [c for c in range(3) if bc[c, axis, side] == BC_N]
+                if not comps:
+                    continue
+                ta, tb = [a for a in range(3) if a != axis]
+                if s + 1 > min(n[ta], n[tb]) - 1:
+                    continue
+                oa = int(rng.integers(1, n[ta] - s))
+                ob = int(rng.integers(1, n[tb] - s))
+                box = (axis, side, oa, ob, s)
+                clash = any(u[0] == axis and u[1] == side and not (oa + s < u[2] or u[2] + u[4] < oa
+                                                                  or ob + s < u[3] or u[3] + u[4] < ob)
+                            for u in used)
+                if clash:
+                    continue
+                used.append(box)
+                idx = np.zeros((s * s, 3), np.int64)
+                aa, bb = np.meshgrid(np.arange(oa, oa + s), np.arange(ob, ob + s), indexing="ij")
+                idx[:, ta] = aa.ravel()
+                idx[:, tb] = bb.ravel()
+                idx[:, axis] = 0 if side == 0 else n[axis]
+                for c in comps:
+                    val = rng.uniform(-1.0, 1.0) * 1e-3 * L / np.sqrt(3.0)
+                    strong.append(Strong(idx.copy(), np.full(len(idx), c, np.int8),
+                                         np.full(len(idx), val), set_id=len(strong)))
+                break
+    return Problem(f"cell{seed}", n, lam, mu, bc, strong=strong, r0_factor=1.0, tol=1e-6,
+                   meta={"phi": phi_got, "contrast": contrast})
+
+
+def c4_batch(count=64, base_seed=BASE_SEED):
+    return [random_cell(base_seed + c) for c in range(count)]
+
+
+def m256_metric(n=(256, 256, 256), seed=BASE_SEED + 5_000_000, phi=0.25, contrast=10.0):
+    """256^3 two-phase block: bottom fixed, top 16x16 node patch pressed down."""
+    rng = np.random.default_rng(seed)
+    mask, phi_got = random_spheres(rng, n, phi)
+    lam, mu = two_phase_lame(mask, contrast)
+    nx, ny, nz = n
+    bc = bc_table(BC_N)
+    bc[:, 2, 0] = BC_D
+    cx, cy = nx // 2, ny // 2
+    patch = _nodes_box(range(cx - 8, cx + 8), range(cy - 8, cy + 8), [nz])
+    top = Strong(patch, np.full(len(patch), 2, np.int8), np.full(len(patch), -1e-3 * nz))
+    return Problem("M256", n, lam, mu, bc, strong=[top], r0_factor=1.0, tol=0.0,
+                   meta={"phi": phi_got, "contrast": contrast})
+
+
+def scaled(problem_fn, n, **kw):
+    return problem_fn(n=n, **kw)
