@@ -1,0 +1,196 @@
+/*
+ * fftc -- constrained DTT/FFT elasticity solver for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libfftc.so.  The library solves the displacement-based fixed point of
+ * Gelebart & Amouzou-Adoun ("Constrained minimization problems and FFT-based
+ * solvers", Section 3.1.2, eq 3) on a regular voxel grid with the TETRA2 scheme,
+ * boundary conditions per face and per component applied through discrete
+ * trigonometric transforms (Section 3.2, Tables 1-3, eq 7), local kinematic
+ * constraints through Lagrange-multiplier projections (Section 4, Algorithm 1,
+ * eq 9-14), unilateral contact with a rigid sphere through an active set
+ * (Section 5.1, Algorithm 2, eq 24-28) and depth-4 Anderson acceleration.
+ *
+ * Conventions
+ *  - Every call returns an int status (FFTC_OK = 0, errors negative); nothing
+ *    aborts or throws across the ABI; fftc_last_error() returns a message.
+ *  - Grid: n[3] = voxels (nx, ny, nz), h = 1.  Nodes per axis N_J = n_J + 1, or
+ *    n_J on a periodic axis.  Node (i, j, k) has flat index i + N_x (j + N_y k).
+ *    Vector node fields are component-planar [3][N_z][N_y][N_x], x fastest;
+ *    voxel fields are [n_z][n_y][n_x].
+ *  - Pointers named *_dev are device pointers, borrowed for the duration of the
+ *    call.  Pointers named *_host are host pointers.  Set-up calls copy what
+ *    they need.
+ *  - Device memory: the caller owns the workspace (size from
+ *    fftc_workspace_bytes) and binds it with a HIP stream; all device work of a
+ *    handle is enqueued on that stream.  The library allocates no device memory.
+ *  - Values at the ABI are FP64.  precision selects the arithmetic of the
+ *    iteration: FFTC_FP64, or FFTC_FP32 (FP32 fields, stresses, transforms and
+ *    Green solve; FP64 norms, convergence test, Anderson Gram matrix and least
+ *    squares, reactions and contact forces).
+ *  - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef FFTC_H
+#define FFTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define FFTC_OK 0
+#define FFTC_E_ARG (-1)         /* invalid argument (sizes, indices, duplicates)   */
+#define FFTC_E_BC (-2)          /* inconsistent boundary table or constraint on an
+                                   eliminated (antisymmetric) DOF with value != 0  */
+#define FFTC_E_OVERLAP (-3)     /* overlapping average supports on one component   */
+#define FFTC_E_WORKSPACE (-4)   /* workspace missing or too small                   */
+#define FFTC_E_NOCONV (-5)      /* max_iter reached; the last iterate is returned   */
+#define FFTC_E_NAN (-6)         /* non-finite input or iterate                      */
+#define FFTC_E_UNSUPPORTED (-7) /* feature or axis length not supported             */
+#define FFTC_E_STATE (-8)       /* call out of order (e.g. solve before stiffness)  */
+#define FFTC_E_HIP (-9)         /* HIP runtime error                                */
+
+/* precision */
+#define FFTC_FP64 0
+#define FFTC_FP32 1
+
+/* boundary codes, bc[comp][axis][face] (Section 3.2.1, Table 1) */
+#define FFTC_BC_NEUMANN 0
+#define FFTC_BC_DIRICHLET 1
+#define FFTC_BC_PERIODIC 2
+
+/* convergence acceleration (Algorithm 1: ACV_U, ACV_P) */
+#define FFTC_ACV_NONE 0
+#define FFTC_ACV_U 1
+#define FFTC_ACV_P 2
+
+typedef struct fftc_problem* fftc_h;
+
+typedef struct {
+  double tol;          /* equilibrium tolerance of eq (5); 0 disables the exit test  */
+  int32_t max_iter;    /* iterations before FFTC_E_NOCONV                           */
+  int32_t acv;         /* FFTC_ACV_*                                                 */
+  int32_t depth;       /* Anderson depth; must be 4                                  */
+  int32_t period;      /* acceleration period mod_ACV (>= 1)                         */
+  double update_gate;  /* contact: residual below which the active set may change   */
+} fftc_solver_cfg;
+
+typedef struct {
+  int32_t status;             /* FFTC_OK, FFTC_E_NOCONV or FFTC_E_NAN              */
+  int32_t iterations;         /* Green solves performed                            */
+  double residual;            /* eq (5) at the returned displacement               */
+  int32_t contact_updates;    /* active-set updates (contact)                      */
+  int32_t anderson_restarts;  /* restarts caused by a changed active set           */
+  int32_t contact_nodes;      /* |C| at the end                                    */
+  int32_t pad;
+  double force_mean_stress;   /* contact: -A0 <sigma_aa> (Section 5.4)              */
+  double force_contact;       /* contact: sum of normal contact reactions           */
+  double mean_stress[6];      /* <sigma>: xx, yy, zz, yz, xz, xy                   */
+} fftc_report;
+
+/* Create a problem on n[3] voxels.  Errors: FFTC_E_ARG (n_J < 2), FFTC_E_UNSUPPORTED
+ * (axis length with a prime factor > 5, or precision unknown). */
+int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision);
+void fftc_destroy(fftc_h h);
+
+/* Boundary table bc_host[comp*6 + axis*2 + face] (Section 3.2.1, Table 1; Section 3.2.2,
+ * Table 2 gives the transform of each (component, axis)).  Periodic must hold on both
+ * faces of an axis for all components, else FFTC_E_BC.  Must precede constraints. */
+int fftc_set_bc(fftc_h h, const int8_t* bc_host);
+
+/* Reference medium of Paux et al. (Section 3.2.3): R0:grad u = lam0 (grad u o I) + 2 mu0 grad u.
+ * Requires mu0 > 0 and lam0 + 2 mu0 > 0 (FFTC_E_ARG).  Default: max(lam), max(mu) of the
+ * stiffness field. */
+int fftc_set_reference(fftc_h h, double lam0, double mu0);
+
+/* Reference medium as a multiple of the stiffness field: (lam0, mu0) = factor * (max lam,
+ * max mu), evaluated by fftc_set_stiffness (the default, factor 1). */
+int fftc_set_reference_factor(fftc_h h, double factor);
+
+/* Strong nodal constraints u[comp[k]](node[k]) = value[k] (Section 4.1, eq 8-9).
+ * node_host: m triples (i, j, k).  set_id groups DOFs for reaction totals (0..63).
+ * Errors: FFTC_E_ARG (index out of range, DOF constrained twice), FFTC_E_BC (nonzero
+ * value on an eliminated DOF; zero values there are dropped). */
+int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node_host, const int8_t* comp_host,
+                       const double* value_host, int32_t set_id);
+
+/* Kinematic relations: mean of u[comp[r]] over the k nodes of support r equals value[r]
+ * (Section 4.2.1, eq 10-14; k = 8 voxel corners or k = 4 face corners).  support_host:
+ * m*k triples.  Errors: FFTC_E_ARG, FFTC_E_BC (support node eliminated for comp),
+ * FFTC_E_OVERLAP (a DOF in two supports or also strongly constrained). */
+int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support_host,
+                     const int8_t* comp_host, const double* value_host, int32_t set_id);
+
+/* Rigid sphere obstacle (Section 5): every node of face (axis*2 + side) is a potential
+ * contact node.  Errors: FFTC_E_ARG (radius <= 0, face out of range, periodic axis). */
+int fftc_set_sphere(fftc_h h, const double center_host[3], double radius, int32_t face);
+
+/* Solver settings; defaults {1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2}. */
+int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg);
+
+/* Device workspace needed by the current set-up (grid, precision, constraints). */
+int fftc_workspace_bytes(fftc_h h, size_t* bytes);
+
+/* Bind caller-owned device memory (256-byte aligned) and the HIP stream (hipStream_t,
+ * NULL = default stream).  Uploads tables and constraints.  FFTC_E_WORKSPACE if small. */
+int fftc_bind_workspace(fftc_h h, void* ws_dev, size_t bytes, void* stream);
+
+/* Per-voxel isotropic stiffness, FP64 device arrays [nz][ny][nx] (paper eq 1: sigma =
+ * C : eps).  lam = mu = 0 marks void voxels.  Errors: FFTC_E_NAN (non-finite),
+ * FFTC_E_ARG (mu < 0 or 3 lam + 2 mu < 0), FFTC_E_STATE (no workspace). */
+int fftc_set_stiffness(fftc_h h, const double* lam_dev, const double* mu_dev);
+
+/* Algorithm 1.  u_dev: FP64 [3][Nz][Ny][Nx]; on entry the initial guess unless
+ * zero_start != 0, on return the last iterate (after the final equilibrium test).
+ * With a sphere set, each call is one load increment of Algorithm 2 (start from u_dev,
+ * initial active set from the gaps, active-set updates inside the iteration).
+ * Returns FFTC_OK, FFTC_E_NOCONV or FFTC_E_NAN (also in rep->status). */
+int fftc_solve(fftc_h h, double* u_dev, int32_t zero_start, fftc_report* rep);
+
+/* Move the sphere centre (next increment of Algorithm 2). */
+int fftc_move_sphere(fftc_h h, const double center_host[3]);
+
+/* Reactions of the last solve (Section 4.1.3: physical nodal force 2^-b p, sign of eq 8):
+ * per_dof_host[m_strong] in the order the strong DOFs were added (dropped zero DOFs
+ * excluded), per_relation_host[m_average], totals_host[nsets*3].  Any pointer may be NULL. */
+int fftc_get_reactions(fftc_h h, double* per_dof_host, double* per_relation_host,
+                       double* totals_host, int32_t nsets);
+int fftc_num_constraints(fftc_h h, int64_t* n_strong, int64_t* n_average);
+
+/* Active set of the last contact solve: mask_host[face nodes] (1 = in C), normal reaction
+ * f_nc and gap per face node (face nodes in flat order of the two in-plane axes). */
+int fftc_get_contact(fftc_h h, uint8_t* mask_host, double* fnc_host, double* gap_host);
+int fftc_num_face_nodes(fftc_h h, int64_t* count);
+
+/* Stage entry points (one step of the iteration on caller data, for testing):
+ * residual: from u, the boundary-weighted residual after proj_P and p~ = p - div(R0:grad u)
+ *   (Algorithm 1, stress / divergence / projection / reference term), plus
+ *   sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.  p_dev or ptil_dev may be NULL.
+ * green: u = DT^-1(M^-1 DT(ptil)) (eq 3 right part with the transforms of Table 2).
+ * Arrays are FP64 device node fields. */
+int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* ptil_dev,
+                        double* sums_host);
+int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev);
+
+const char* fftc_status_str(int status);
+const char* fftc_last_error(fftc_h h);
+
+/* Fixed-count iterations: enqueue exactly `iters` further iterations of the current solve on the
+ * handle's stream without an exit test and without host synchronisation (the fields, Anderson
+ * history and counters continue from the previous fftc_solve).  The caller synchronises the
+ * stream.  Used to time the hot loop. */
+int fftc_iterate(fftc_h h, int32_t iters);
+
+/* Per-stage timing: runs `iters` more iterations (no exit test) after a solve and returns the
+ * mean time in ms of each stage, measured with HIP events on the handle's stream:
+ * [0] residual pass, [1] average-relation projection + control, [2] Anderson store/Gram/LS,
+ * [3] x forward DTT (+ Anderson combination), [4] y forward DTT, [5] z forward DTT + Green +
+ * z inverse DTT, [6] y inverse DTT, [7] x inverse DTT, [8] proj_U.  The fields keep evolving. */
+int fftc_profile_stages(fftc_h h, int32_t iters, double* ms_host, int32_t nstages);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

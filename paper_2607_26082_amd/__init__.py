@@ -1,0 +1,337 @@
+"""Python binding of libfftc (constrained DTT/FFT elasticity solver for MI355X).
+
+The functions below carry the names of the C ABI declared in include/fftc.h and only
+marshal arguments (ctypes); every step of the solver runs in the HIP library.  PyTorch
+supplies device memory and the stream.  The `Solver` class is a convenience wrapper
+that creates a handle from a problem description (see workloads.Problem).
+
+The library must be built (paper_2607_26082_amd/build.py); importing this module on a
+machine without it raises ImportError -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfftc.so")
+
+FFTC_OK = 0
+FFTC_E_ARG, FFTC_E_BC, FFTC_E_OVERLAP, FFTC_E_WORKSPACE = -1, -2, -3, -4
+FFTC_E_NOCONV, FFTC_E_NAN, FFTC_E_UNSUPPORTED, FFTC_E_STATE, FFTC_E_HIP = -5, -6, -7, -8, -9
+FFTC_FP64, FFTC_FP32 = 0, 1
+FFTC_ACV_NONE, FFTC_ACV_U, FFTC_ACV_P = 0, 1, 2
+
+STAGES = ("residual", "weak+control", "anderson", "dtt_x_fwd", "dtt_y_fwd", "dtt_z_green",
+          "dtt_y_inv", "dtt_x_inv", "proj_u")
+
+
+class fftc_solver_cfg(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("acv", C.c_int32),
+                ("depth", C.c_int32), ("period", C.c_int32), ("update_gate", C.c_double)]
+
+
+class fftc_report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("residual", C.c_double),
+                ("contact_updates", C.c_int32), ("anderson_restarts", C.c_int32),
+                ("contact_nodes", C.c_int32), ("pad", C.c_int32),
+                ("force_mean_stress", C.c_double), ("force_contact", C.c_double),
+                ("mean_stress", C.c_double * 6)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "fftc_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32]),
+    "fftc_destroy": (None, [_P]),
+    "fftc_set_bc": (C.c_int, [_P, C.POINTER(C.c_int8)]),
+    "fftc_set_reference": (C.c_int, [_P, C.c_double, C.c_double]),
+    "fftc_set_reference_factor": (C.c_int, [_P, C.c_double]),
+    "fftc_add_dirichlet": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
+                                     C.POINTER(C.c_double), C.c_int32]),
+    "fftc_add_average": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
+                                   C.POINTER(C.c_double), C.c_int32]),
+    "fftc_set_sphere": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, C.c_int32]),
+    "fftc_move_sphere": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "fftc_set_solver": (C.c_int, [_P, C.POINTER(fftc_solver_cfg)]),
+    "fftc_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "fftc_bind_workspace": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "fftc_set_stiffness": (C.c_int, [_P, _P, _P]),
+    "fftc_solve": (C.c_int, [_P, _P, C.c_int32, C.POINTER(fftc_report)]),
+    "fftc_get_reactions": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_int32]),
+    "fftc_num_constraints": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "fftc_get_contact": (C.c_int, [_P, C.POINTER(C.c_uint8), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fftc_num_face_nodes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "fftc_stage_residual": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "fftc_stage_green": (C.c_int, [_P, _P, _P]),
+    "fftc_iterate": (C.c_int, [_P, C.c_int32]),
+    "fftc_profile_stages": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), C.c_int32]),
+    "fftc_status_str": (C.c_char_p, [C.c_int]),
+    "fftc_last_error": (C.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libfftc.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfftc.so not built at {LIB_PATH}; run paper_2607_26082_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return tuple(_SIGS)
+
+
+class FftcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _dev(t):
+    return C.c_void_p(int(t.data_ptr())) if t is not None else None
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers, named after the C entry points
+# ---------------------------------------------------------------------------
+
+def fftc_create(n, precision=FFTC_FP64):
+    lib = load()
+    h = C.c_void_p()
+    arr = (C.c_int32 * 3)(*[int(v) for v in n])
+    rc = lib.fftc_create(C.byref(h), arr, int(precision))
+    if rc != FFTC_OK:
+        raise FftcError(rc, "fftc_create: " + lib.fftc_status_str(rc).decode())
+    return h
+
+
+def fftc_destroy(h):
+    load().fftc_destroy(h)
+
+
+def _check(h, rc, what, allow=()):
+    if rc != FFTC_OK and rc not in allow:
+        lib = load()
+        raise FftcError(rc, f"{what}: {lib.fftc_status_str(rc).decode()}: {lib.fftc_last_error(h).decode()}")
+    return rc
+
+
+def fftc_set_bc(h, bc):
+    a = np.ascontiguousarray(np.asarray(bc, np.int8).reshape(18))
+    return _check(h, load().fftc_set_bc(h, _ptr(a, C.c_int8)), "fftc_set_bc")
+
+
+def fftc_set_reference(h, lam0, mu0):
+    return _check(h, load().fftc_set_reference(h, float(lam0), float(mu0)), "fftc_set_reference")
+
+
+def fftc_set_reference_factor(h, factor):
+    return _check(h, load().fftc_set_reference_factor(h, float(factor)), "fftc_set_reference_factor")
+
+
+def fftc_add_dirichlet(h, node, comp, value, set_id=0):
+    node = np.ascontiguousarray(np.asarray(node, np.int64).reshape(-1, 3))
+    comp = np.ascontiguousarray(np.asarray(comp, np.int8).ravel())
+    value = np.ascontiguousarray(np.asarray(value, np.float64).ravel())
+    return _check(h, load().fftc_add_dirichlet(h, len(comp), _ptr(node, C.c_int64), _ptr(comp, C.c_int8),
+                                               _ptr(value, C.c_double), int(set_id)), "fftc_add_dirichlet")
+
+
+def fftc_add_average(h, support, comp, value, set_id=0):
+    comp = np.ascontiguousarray(np.asarray(comp, np.int8).ravel())
+    sup = np.ascontiguousarray(np.asarray(support, np.int64).reshape(len(comp), -1, 3))
+    value = np.ascontiguousarray(np.asarray(value, np.float64).ravel())
+    return _check(h, load().fftc_add_average(h, len(comp), sup.shape[1], _ptr(sup, C.c_int64),
+                                             _ptr(comp, C.c_int8), _ptr(value, C.c_double), int(set_id)),
+                  "fftc_add_average")
+
+
+def fftc_set_sphere(h, center, radius, face):
+    c = np.ascontiguousarray(np.asarray(center, np.float64))
+    return _check(h, load().fftc_set_sphere(h, _ptr(c, C.c_double), float(radius), int(face)), "fftc_set_sphere")
+
+
+def fftc_move_sphere(h, center):
+    c = np.ascontiguousarray(np.asarray(center, np.float64))
+    return _check(h, load().fftc_move_sphere(h, _ptr(c, C.c_double)), "fftc_move_sphere")
+
+
+def fftc_set_solver(h, tol=1e-6, max_iter=2000, acv=FFTC_ACV_P, depth=4, period=2, update_gate=1e-2):
+    cfg = fftc_solver_cfg(float(tol), int(max_iter), int(acv), int(depth), int(period), float(update_gate))
+    return _check(h, load().fftc_set_solver(h, C.byref(cfg)), "fftc_set_solver")
+
+
+def fftc_workspace_bytes(h):
+    b = C.c_size_t()
+    _check(h, load().fftc_workspace_bytes(h, C.byref(b)), "fftc_workspace_bytes")
+    return int(b.value)
+
+
+def fftc_bind_workspace(h, ws, nbytes, stream):
+    return _check(h, load().fftc_bind_workspace(h, _dev(ws), int(nbytes), C.c_void_p(stream)),
+                  "fftc_bind_workspace")
+
+
+def fftc_set_stiffness(h, lam_dev, mu_dev):
+    return _check(h, load().fftc_set_stiffness(h, _dev(lam_dev), _dev(mu_dev)), "fftc_set_stiffness")
+
+
+def fftc_solve(h, u_dev, zero_start=True):
+    rep = fftc_report()
+    rc = load().fftc_solve(h, _dev(u_dev), 1 if zero_start else 0, C.byref(rep))
+    _check(h, rc, "fftc_solve", allow=(FFTC_E_NOCONV, FFTC_E_NAN))
+    return rc, rep
+
+
+def fftc_get_reactions(h, nsets):
+    lib = load()
+    ns, nw = C.c_int64(), C.c_int64()
+    lib.fftc_num_constraints(h, C.byref(ns), C.byref(nw))
+    per = np.zeros(max(ns.value, 1)); rel = np.zeros(max(nw.value, 1)); tot = np.zeros((max(nsets, 1), 3))
+    _check(h, lib.fftc_get_reactions(h, _ptr(per, C.c_double), _ptr(rel, C.c_double), _ptr(tot, C.c_double),
+                                     int(nsets)), "fftc_get_reactions")
+    return per[:ns.value], rel[:nw.value], tot[:nsets]
+
+
+def fftc_get_contact(h):
+    lib = load()
+    m = C.c_int64()
+    lib.fftc_num_face_nodes(h, C.byref(m))
+    mask = np.zeros(m.value, np.uint8); fnc = np.zeros(m.value); gap = np.zeros(m.value)
+    _check(h, lib.fftc_get_contact(h, _ptr(mask, C.c_uint8), _ptr(fnc, C.c_double), _ptr(gap, C.c_double)),
+           "fftc_get_contact")
+    return mask, fnc, gap
+
+
+def fftc_stage_residual(h, u_dev, p_dev=None, ptil_dev=None):
+    sums = np.zeros(2)
+    _check(h, load().fftc_stage_residual(h, _dev(u_dev), _dev(p_dev), _dev(ptil_dev), _ptr(sums, C.c_double)),
+           "fftc_stage_residual")
+    return sums
+
+
+def fftc_stage_green(h, ptil_dev, u_dev):
+    return _check(h, load().fftc_stage_green(h, _dev(ptil_dev), _dev(u_dev)), "fftc_stage_green")
+
+
+def fftc_iterate(h, iters):
+    return _check(h, load().fftc_iterate(h, int(iters)), "fftc_iterate")
+
+
+def fftc_profile_stages(h, iters):
+    ms = np.zeros(len(STAGES))
+    _check(h, load().fftc_profile_stages(h, int(iters), _ptr(ms, C.c_double), len(STAGES)), "fftc_profile_stages")
+    return dict(zip(STAGES, ms))
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Solver:
+    """One problem on the current CUDA (HIP) device: handle + torch-owned workspace."""
+
+    def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
+                 precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda"):
+        import torch
+        self.torch = torch
+        self.n = tuple(int(v) for v in n)
+        self.precision = FFTC_FP64 if precision == "fp64" else FFTC_FP32
+        self.h = fftc_create(self.n, self.precision)
+        bc = np.asarray(bc, np.int8).reshape(3, 3, 2)
+        fftc_set_bc(self.h, bc)
+        periodic = [bool((bc[:, J, :] == 2).all()) for J in range(3)]
+        self.N = tuple(self.n[J] + (0 if periodic[J] else 1) for J in range(3))
+        self.nsets = 1
+        for s in strong:
+            fftc_add_dirichlet(self.h, s.node, s.comp, s.value, s.set_id)
+            self.nsets = max(self.nsets, s.set_id + 1)
+        for a in average:
+            fftc_add_average(self.h, a.support, a.comp, a.value, a.set_id)
+            self.nsets = max(self.nsets, a.set_id + 1)
+        if sphere is not None:
+            fftc_set_sphere(self.h, sphere.center, sphere.radius, sphere.face)
+        fftc_set_reference_factor(self.h, r0_factor)
+        fftc_set_solver(self.h, tol=tol, max_iter=max_iter,
+                        acv={"NONE": FFTC_ACV_NONE, "U": FFTC_ACV_U, "P": FFTC_ACV_P}[acv],
+                        period=period, update_gate=gate)
+        nbytes = fftc_workspace_bytes(self.h)
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + nbytes]
+        self.stream = torch.cuda.current_stream(self.device)
+        fftc_bind_workspace(self.h, self.ws_view, nbytes, self.stream.cuda_stream)
+        lam_t = torch.as_tensor(np.ascontiguousarray(lam, np.float64), device=self.device)
+        mu_t = torch.as_tensor(np.ascontiguousarray(mu, np.float64), device=self.device)
+        self.stream.synchronize()
+        fftc_set_stiffness(self.h, lam_t, mu_t)
+        self.u = torch.zeros((3, self.N[2], self.N[1], self.N[0]), dtype=torch.float64, device=self.device)
+
+    @classmethod
+    def from_problem(cls, prob, precision="fp64", **kw):
+        kw.setdefault("tol", prob.tol)
+        kw.setdefault("max_iter", prob.max_iter)
+        kw.setdefault("acv", prob.acv)
+        kw.setdefault("period", prob.acv_period)
+        return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.sphere,
+                   prob.r0_factor, precision=precision, **kw)
+
+    def solve(self, zero_start=True):
+        rc, rep = fftc_solve(self.h, self.u, zero_start)
+        return rc, rep
+
+    def move_sphere(self, center):
+        fftc_move_sphere(self.h, center)
+
+    def reactions(self):
+        return fftc_get_reactions(self.h, self.nsets)
+
+    def contact(self):
+        return fftc_get_contact(self.h)
+
+    def stage_residual(self, u):
+        t = self.torch
+        u_t = t.as_tensor(np.ascontiguousarray(u, np.float64), device=self.device)
+        p = t.empty_like(u_t); pt = t.empty_like(u_t)
+        sums = fftc_stage_residual(self.h, u_t, p, pt)
+        return p.cpu().numpy(), pt.cpu().numpy(), sums
+
+    def stage_green(self, ptil):
+        t = self.torch
+        p_t = t.as_tensor(np.ascontiguousarray(ptil, np.float64), device=self.device)
+        u = t.empty_like(p_t)
+        fftc_stage_green(self.h, p_t, u)
+        return u.cpu().numpy()
+
+    def iterate(self, iters):
+        fftc_iterate(self.h, iters)
+
+    def profile(self, iters):
+        return fftc_profile_stages(self.h, iters)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                fftc_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

@@ -1,0 +1,958 @@
+// Host runtime and C ABI of libfftc: validation, plans (boundary table -> transform
+// types, twiddles, symbol tables), workspace carving, and the device-driven iteration.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/fftc.h"
+#include "fftc_internal.h"
+#include "fftc_launch.h"
+
+using namespace fftc;
+
+struct fftc_problem {
+  int n[3] = {0, 0, 0}, N[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
+  int precision = FFTC_FP64;
+  long long Nn = 0, Nv = 0;
+  int8_t bc[18];
+  int type[3][3];
+  int aface = 0;
+  double lam0 = 0, mu0 = 0, r0_factor = 1.0;
+  int ref_mode = 0;  // 0 = factor of max stiffness, 1 = explicit
+  // constraints
+  std::vector<long long> s_node;
+  std::vector<int8_t> s_comp;
+  std::vector<double> s_val;
+  std::vector<int> s_set;
+  std::vector<long long> w_nodes;
+  int w_k = 0;
+  std::vector<int8_t> w_comp;
+  std::vector<double> w_val;
+  std::vector<int> w_set;
+  std::unordered_set<long long> dof_used;  // comp * Nn + node
+  // sphere
+  int has_sphere = 0;
+  double center[3] = {0, 0, 0}, radius = 0;
+  int face = 5;
+  fftc_solver_cfg cfg{1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2};
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int bound = 0, stiff_set = 0;
+  void* fld[10];  // u, X, S0..3, R0..3
+  void* lam = nullptr;
+  void* mu = nullptr;
+  uint8_t* mask = nullptr;
+  double *part = nullptr, *gpart = nullptr, *wpart = nullptr, *wreact = nullptr, *cosT = nullptr;
+  double *sreact = nullptr, *chk = nullptr, *fnc = nullptr, *gap = nullptr;
+  DevState* st = nullptr;
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  long long* d_snode = nullptr;
+  int8_t* d_scomp = nullptr;
+  double* d_sval = nullptr;
+  long long* d_wnodes = nullptr;
+  int8_t* d_wcomp = nullptr;
+  double* d_wval = nullptr;
+  uint8_t *C = nullptr, *V0 = nullptr, *V1 = nullptr;
+  long long nface = 0;
+  int b1 = 0, b2 = 1;
+  AxisPlan ap[3];
+  int ept = 8, nblk_res = 1, maxN = 1;
+  Geo g;
+  std::string err;
+  DevState last{};
+  std::vector<double> react_strong, react_weak;
+  int profiling = 0;
+};
+
+namespace {
+
+const size_t kAlign = 256;
+
+int fail(fftc_problem* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                             \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) return fail(h, FFTC_E_HIP, std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+bool factor_ok(int n, std::vector<int>& rad) {
+  rad.clear();
+  int m = n;
+  while (m % 4 == 0) { rad.push_back(4); m /= 4; }
+  while (m % 2 == 0) { rad.push_back(2); m /= 2; }
+  while (m % 3 == 0) { rad.push_back(3); m /= 3; }
+  while (m % 5 == 0) { rad.push_back(5); m /= 5; }
+  return m == 1 && (int)rad.size() <= kMaxRadices;
+}
+
+int sym_of(int code) { return code == FFTC_BC_DIRICHLET ? 1 : (code == FFTC_BC_NEUMANN ? 0 : 2); }  // 1 = A
+
+// Table 2: symmetries on the two faces -> transform
+int type_of(int s0, int s1) {
+  if (s0 == 2) return T_DFT;
+  if (s0 == 0 && s1 == 0) return T_DCT1;
+  if (s0 == 0 && s1 == 1) return T_DCT3;
+  if (s0 == 1 && s1 == 1) return T_DST1;
+  return T_DST3;
+}
+
+double theta_of(int type, int n, int idx) {
+  switch (type) {
+    case T_DCT1:
+    case T_DST1: return M_PI * idx / n;
+    case T_DCT3:
+    case T_DST3: return M_PI * (idx + 0.5) / n;
+    default: {
+      int k = std::min(idx, n - idx);
+      return 2.0 * M_PI * k / n;
+    }
+  }
+}
+
+long long node_flat(const fftc_problem* h, long long i, long long j, long long k) {
+  return i + (long long)h->N[0] * (j + (long long)h->N[1] * k);
+}
+
+bool node_antisym(const fftc_problem* h, int c, const long long xyz[3]) {
+  for (int J = 0; J < 3; ++J) {
+    if (h->periodic[J]) continue;
+    if (xyz[J] == 0 && ((h->aface >> (c * 6 + J * 2)) & 1)) return true;
+    if (xyz[J] == h->n[J] && ((h->aface >> (c * 6 + J * 2 + 1)) & 1)) return true;
+  }
+  return false;
+}
+
+void build_plan(fftc_problem* h) {
+  h->aface = 0;
+  for (int J = 0; J < 3; ++J) h->periodic[J] = (h->bc[0 * 6 + J * 2] == FFTC_BC_PERIODIC);
+  for (int c = 0; c < 3; ++c)
+    for (int J = 0; J < 3; ++J) {
+      const int s0 = sym_of(h->bc[c * 6 + J * 2]), s1 = sym_of(h->bc[c * 6 + J * 2 + 1]);
+      h->type[c][J] = type_of(s0, s1);
+      if (s0 == 1) h->aface |= 1 << (c * 6 + J * 2);
+      if (s1 == 1) h->aface |= 1 << (c * 6 + J * 2 + 1);
+    }
+  for (int J = 0; J < 3; ++J) h->N[J] = h->n[J] + (h->periodic[J] ? 0 : 1);
+  h->Nn = (long long)h->N[0] * h->N[1] * h->N[2];
+}
+
+template <typename T>
+size_t tsize() { return sizeof(T); }
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    size_t off = total;
+    total += (bytes + kAlign - 1) / kAlign * kAlign;
+    return off;
+  }
+};
+
+// carve the workspace; with base == nullptr only computes the size
+size_t carve(fftc_problem* h, char* base) {
+  Layout L;
+  const size_t ts = h->precision == FFTC_FP64 ? 8 : 4;
+  const size_t f3 = ts * 3 * (size_t)h->Nn;
+  size_t off[64];
+  int q = 0;
+  for (int i = 0; i < 10; ++i) off[q++] = L.take(f3);
+  off[q++] = L.take(ts * h->Nv);
+  off[q++] = L.take(ts * h->Nv);
+  off[q++] = L.take((size_t)h->Nn);
+  off[q++] = L.take(sizeof(double) * kPartStride * 2048);
+  off[q++] = L.take(sizeof(double) * 10 * 2048);
+  off[q++] = L.take(sizeof(DevState));
+  const size_t mw = h->w_comp.size(), ms = h->s_comp.size();
+  off[q++] = L.take(sizeof(double) * (mw + 1));
+  off[q++] = L.take(sizeof(double) * (mw + 1));
+  int maxN = std::max(h->N[0], std::max(h->N[1], h->N[2]));
+  off[q++] = L.take(sizeof(double) * 9 * maxN);
+  for (int J = 0; J < 3; ++J) off[q++] = L.take(2 * ts * 4 * (size_t)h->n[J]);
+  off[q++] = L.take(8 * (ms + 1));
+  off[q++] = L.take(ms + 1);
+  off[q++] = L.take(8 * (ms + 1));
+  off[q++] = L.take(8 * (h->w_nodes.size() + 1));
+  off[q++] = L.take(mw + 1);
+  off[q++] = L.take(8 * (mw + 1));
+  long long nface = 1;
+  if (h->has_sphere) {
+    const int a = h->face / 2;
+    int bb[2], t = 0;
+    for (int J = 0; J < 3; ++J)
+      if (J != a) bb[t++] = J;
+    nface = (long long)h->N[bb[0]] * h->N[bb[1]];
+  }
+  off[q++] = L.take(nface);
+  off[q++] = L.take(nface);
+  off[q++] = L.take(nface);
+  off[q++] = L.take(8 * nface);
+  off[q++] = L.take(8 * nface);
+  off[q++] = L.take(8 * (ms + 1));
+  off[q++] = L.take(sizeof(double) * 3 * 1024);
+  if (base) {
+    q = 0;
+    for (int i = 0; i < 10; ++i) h->fld[i] = base + off[q++];
+    h->lam = base + off[q++];
+    h->mu = base + off[q++];
+    h->mask = (uint8_t*)(base + off[q++]);
+    h->part = (double*)(base + off[q++]);
+    h->gpart = (double*)(base + off[q++]);
+    h->st = (DevState*)(base + off[q++]);
+    h->wpart = (double*)(base + off[q++]);
+    h->wreact = (double*)(base + off[q++]);
+    h->cosT = (double*)(base + off[q++]);
+    for (int J = 0; J < 3; ++J) h->tw[J] = base + off[q++];
+    h->d_snode = (long long*)(base + off[q++]);
+    h->d_scomp = (int8_t*)(base + off[q++]);
+    h->d_sval = (double*)(base + off[q++]);
+    h->d_wnodes = (long long*)(base + off[q++]);
+    h->d_wcomp = (int8_t*)(base + off[q++]);
+    h->d_wval = (double*)(base + off[q++]);
+    h->C = (uint8_t*)(base + off[q++]);
+    h->V0 = (uint8_t*)(base + off[q++]);
+    h->V1 = (uint8_t*)(base + off[q++]);
+    h->fnc = (double*)(base + off[q++]);
+    h->gap = (double*)(base + off[q++]);
+    h->sreact = (double*)(base + off[q++]);
+    h->chk = (double*)(base + off[q++]);
+    h->nface = nface;
+    h->maxN = maxN;
+  }
+  return L.total;
+}
+
+void set_stencil(fftc_problem* h) {
+  for (int c = 0; c < 3; ++c) {
+    double cj[3];
+    for (int J = 0; J < 3; ++J) cj[J] = 2.0 * h->mu0 + (J == c ? h->lam0 : 0.0);
+    h->g.st[c][0] = cj[0] + cj[1] + cj[2];
+    h->g.st[c][1] = (cj[2] - cj[0] - cj[1]) / 4.0;
+    h->g.st[c][2] = (cj[1] - cj[0] - cj[2]) / 4.0;
+    h->g.st[c][3] = (cj[0] - cj[1] - cj[2]) / 4.0;
+  }
+}
+
+template <typename T>
+Bufs<T> bufs(fftc_problem* h) {
+  Bufs<T> B;
+  B.u = (T*)h->fld[0];
+  B.X = (T*)h->fld[1];
+  for (int q = 0; q < 4; ++q) {
+    B.S[q] = (T*)h->fld[2 + q];
+    B.R[q] = (T*)h->fld[6 + q];
+  }
+  B.lam = (const T*)h->lam;
+  B.mu = (const T*)h->mu;
+  B.mask = h->mask;
+  return B;
+}
+
+ContactDev contact_dev(fftc_problem* h) {
+  ContactDev ct{};
+  ct.on = h->has_sphere;
+  ct.axis = h->face / 2;
+  ct.side = h->face % 2;
+  ct.b1 = h->b1;
+  ct.b2 = h->b2;
+  ct.nface = h->nface;
+  for (int c = 0; c < 3; ++c) ct.center[c] = h->center[c];
+  ct.radius = h->radius;
+  ct.C = h->C;
+  ct.V[0] = h->V0;
+  ct.V[1] = h->V1;
+  ct.fnc = h->fnc;
+  ct.gap = h->gap;
+  return ct;
+}
+
+StrongDev strong_dev(fftc_problem* h) {
+  StrongDev s{(long long)h->s_comp.size(), h->d_snode, h->d_scomp, h->d_sval};
+  return s;
+}
+
+WeakDev weak_dev(fftc_problem* h) {
+  WeakDev w{(long long)h->w_comp.size(), h->w_k, h->d_wnodes, h->d_wcomp, h->d_wval, h->wpart, h->wreact};
+  return w;
+}
+
+template <typename T>
+DttArgs<T> dtt_args(fftc_problem* h, int axis, int mode, int force) {
+  DttArgs<T> a{};
+  a.g = h->g;
+  a.axis = axis;
+  a.mode = mode;
+  a.src = SRC_BUF;
+  a.ap = h->ap[axis];
+  for (int c = 0; c < 3; ++c) a.types[c] = h->type[c][axis];
+  a.buf = (T*)h->fld[0];
+  a.in = (T*)h->fld[0];
+  a.B = bufs<T>(h);
+  a.store_s = 0;
+  a.st = h->st;
+  a.force = force;
+  a.cosT = h->cosT;
+  a.maxN = h->maxN;
+  for (int c = 0; c < 3; ++c) {
+    const double d = h->g.st[c][0];
+    const double e = fabs(h->g.st[c][1]) + fabs(h->g.st[c][2]) + fabs(h->g.st[c][3]);
+    a.thr[c] = 1e-12 * (d + 4.0 * e);
+  }
+  return a;
+}
+
+// Green step on the working buffers: u <- DT^-1(M^-1 DT(src)), forward x source chosen by caller
+struct StageTimer;
+template <typename T>
+void enqueue_green(fftc_problem* h, int src, const T* in, int store_s, int force, StageTimer* tm = nullptr);
+
+struct StageTimer {
+  hipEvent_t ev[16];
+  int n = 0;
+  bool on = false;
+  void mark(hipStream_t s) {
+    if (on && n < 16) hipEventRecord(ev[n++], s);
+  }
+};
+
+template <typename T>
+void enqueue_iteration(fftc_problem* h, StageTimer* tm = nullptr) {
+  Bufs<T> B = bufs<T>(h);
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  const StrongDev sd = strong_dev(h);
+  const long long n3 = 3 * h->Nn;
+  hipStream_t s = h->stream;
+  if (h->cfg.acv == FFTC_ACV_U) {
+    Bufs<T> Bu = B;
+    Bu.X = B.u;  // residual store on the displacement
+    launch_flags_combine<T>(B, n3, h->st, 0, s);
+    launch_anderson<T>(Bu, n3, h->st, h->gpart, h->nblk_res, s);
+    launch_flags_combine<T>(B, n3, h->st, 1, s);
+  }
+  if (tm) tm->mark(s);
+  launch_residual<T>(h->g, B, ct, h->st, h->part, h->nblk_res, 0, 0, s);
+  if (tm) tm->mark(s);
+  launch_weak<T>(h->g, B, w, h->st, 0, s);
+  launch_control(h->st, h->part, h->nblk_res, h->wpart, w.m, ct, s);
+  if (tm) tm->mark(s);
+  if (h->cfg.acv == FFTC_ACV_P) launch_anderson<T>(B, n3, h->st, h->gpart, h->nblk_res, s);
+  if (tm) tm->mark(s);
+  enqueue_green<T>(h, h->cfg.acv == FFTC_ACV_P ? SRC_ANDERSON : SRC_BUF, B.X, h->cfg.acv == FFTC_ACV_P, 0, tm);
+  launch_proj<T>(h->g, B.u, w, ct, sd, h->st, 1, 0, s);
+  if (tm) tm->mark(s);
+}
+
+template <typename T>
+void enqueue_green(fftc_problem* h, int src, const T* in, int store_s, int force, StageTimer* tm) {
+  DttArgs<T> a = dtt_args<T>(h, 0, PASS_FWD, force);
+  a.src = src;
+  a.in = in;
+  a.store_s = store_s;
+  launch_dtt<T>(a, h->ept, h->stream);
+  if (tm) tm->mark(h->stream);
+  a = dtt_args<T>(h, 1, PASS_FWD, force);
+  launch_dtt<T>(a, h->ept, h->stream);
+  if (tm) tm->mark(h->stream);
+  a = dtt_args<T>(h, 2, PASS_FWD_GREEN_INV, force);
+  launch_dtt<T>(a, h->ept, h->stream);
+  if (tm) tm->mark(h->stream);
+  a = dtt_args<T>(h, 1, PASS_INV, force);
+  launch_dtt<T>(a, h->ept, h->stream);
+  if (tm) tm->mark(h->stream);
+  a = dtt_args<T>(h, 0, PASS_INV, force);
+  launch_dtt<T>(a, h->ept, h->stream);
+  if (tm) tm->mark(h->stream);
+}
+
+// Times each stage of `iters` further iterations with HIP events on the handle's stream.
+// Stages: residual, weak+control, anderson, dtt x fwd, dtt y fwd, dtt z fwd+green+inv,
+// dtt y inv, dtt x inv, projections.  Requires a prior solve (state and fields live).
+template <typename T>
+int profile_t(fftc_problem* h, int iters, double* ms, int nst) {
+  hipStream_t s = h->stream;
+  StageTimer tm;
+  tm.on = true;
+  for (int q = 0; q < 16; ++q) HIPCHK(h, hipEventCreate(&tm.ev[q]));
+  std::vector<double> acc(16, 0.0);
+  // keep the state running
+  DevState hs{};
+  HIPCHK(h, hipMemcpyAsync(&hs, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  hs.done = 0;
+  hs.status = 0;
+  hs.max_iter = hs.it + iters + 8;
+  hs.tol = 0.0;
+  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  int nmark = 0;
+  for (int it = 0; it < iters; ++it) {
+    tm.n = 0;
+    enqueue_iteration<T>(h, &tm);
+    HIPCHK(h, hipStreamSynchronize(s));
+    nmark = tm.n;
+    for (int q = 0; q + 1 < tm.n; ++q) {
+      float e = 0.f;
+      HIPCHK(h, hipEventElapsedTime(&e, tm.ev[q], tm.ev[q + 1]));
+      acc[q] += e;
+    }
+  }
+  for (int q = 0; q < 16; ++q) hipEventDestroy(tm.ev[q]);
+  for (int q = 0; q < nst; ++q) ms[q] = (q + 1 < nmark) ? acc[q] / iters : 0.0;
+  return FFTC_OK;
+}
+
+template <typename T>
+int solve_t(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
+  Bufs<T> B = bufs<T>(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(B.u, 0, sizeof(T) * n3, s));
+  else launch_convert<double, T>(u_dev, B.u, n3, s);
+  launch_zero_amask<T>(h->g, B.u, s);
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  const StrongDev sd = strong_dev(h);
+  // initial proj_U (and the initial active set from the gaps)
+  if (ct.on) launch_contact_init<T>(h->g, B.u, ct, s);
+  launch_proj<T>(h->g, B.u, w, ct, sd, h->st, 0, 1, s);
+  DevState hs{};
+  hs.tol = h->cfg.tol;
+  hs.gate = h->cfg.update_gate;
+  hs.max_iter = h->cfg.max_iter;
+  hs.period = h->cfg.period;
+  hs.acv = h->cfg.acv;
+  hs.contact = h->has_sphere;
+  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  int chunk = 4;
+  DevState out{};
+  for (;;) {
+    for (int t = 0; t < chunk; ++t) enqueue_iteration<T>(h);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(&out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (out.done) break;
+    chunk = std::min(64, chunk * 2);
+  }
+  h->last = out;
+  // reactions of the returned iterate
+  launch_reactions<T>(h->g, B, sd, h->sreact, s);
+  if (u_dev) launch_convert<T, double>(B.u, u_dev, n3, s);
+  h->react_strong.assign(h->s_comp.size(), 0.0);
+  h->react_weak.assign(h->w_comp.size(), 0.0);
+  if (!h->react_strong.empty())
+    HIPCHK(h, hipMemcpyAsync(h->react_strong.data(), h->sreact, 8 * h->react_strong.size(), hipMemcpyDeviceToHost, s));
+  if (!h->react_weak.empty())
+    HIPCHK(h, hipMemcpyAsync(h->react_weak.data(), h->wreact, 8 * h->react_weak.size(), hipMemcpyDeviceToHost, s));
+  double force_c = 0.0;
+  int nC = 0;
+  std::vector<double> cf(2 * 64, 0.0);
+  if (ct.on) {
+    launch_contact_force<T>(h->g, B.u, ct, h->chk, 64, s);
+    HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (ct.on) {
+    double fs = 0.0, cnt = 0.0;
+    for (int b = 0; b < 64; ++b) {
+      fs += cf[2 * b];
+      cnt += cf[2 * b + 1];
+    }
+    force_c = -((h->face % 2) ? 1.0 : -1.0) * fs;
+    nC = (int)cnt;
+  }
+  int status = out.status == ST_CONVERGED ? FFTC_OK : (out.status == ST_NAN ? FFTC_E_NAN : FFTC_E_NOCONV);
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    rep->status = status;
+    rep->iterations = out.it;
+    rep->residual = out.residual;
+    rep->contact_updates = out.updates;
+    rep->anderson_restarts = out.restarts;
+    const double nv = (double)h->Nv;
+    for (int q = 0; q < 6; ++q) rep->mean_stress[q] = out.ms[q] / nv;
+    if (ct.on) {
+      const int a = h->face / 2;
+      double A0 = 1.0;
+      for (int J = 0; J < 3; ++J)
+        if (J != a) A0 *= h->n[J];
+      rep->force_mean_stress = -A0 * rep->mean_stress[a];
+      rep->force_contact = force_c;
+      rep->contact_nodes = nC;
+    }
+  }
+  if (out.status == ST_NAN) return fail(h, FFTC_E_NAN, "non-finite iterate");
+  if (out.status != ST_CONVERGED) return fail(h, FFTC_E_NOCONV, "maximum number of iterations reached");
+  return FFTC_OK;
+}
+
+template <typename T>
+int stage_residual_t(fftc_problem* h, const double* u_dev, double* p_dev, double* ptil_dev, double* sums) {
+  Bufs<T> B = bufs<T>(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  launch_convert<double, T>(u_dev, B.u, n3, s);
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  DevState hs{};
+  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  for (int pass = 0; pass < 2; ++pass) {
+    double* dst = pass == 0 ? ptil_dev : p_dev;
+    if (!dst) continue;
+    launch_residual<T>(h->g, B, ct, h->st, h->part, h->nblk_res, 1, pass, s);
+    launch_weak<T>(h->g, B, w, h->st, 1, s);
+    launch_convert<T, double>(B.X, dst, n3, s);
+  }
+  if (sums) {
+    if (!ptil_dev && !p_dev) {
+      launch_residual<T>(h->g, B, ct, h->st, h->part, h->nblk_res, 1, 0, s);
+      launch_weak<T>(h->g, B, w, h->st, 1, s);
+    }
+    std::vector<double> part((size_t)h->nblk_res * kPartStride), wp(w.m + 1);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->part, 8 * part.size(), hipMemcpyDeviceToHost, s));
+    if (w.m) HIPCHK(h, hipMemcpyAsync(wp.data(), h->wpart, 8 * w.m, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    double a0 = 0, a1 = 0;
+    for (int b = 0; b < h->nblk_res; ++b) {
+      a0 += part[b * kPartStride + 0];
+      a1 += part[b * kPartStride + 1];
+    }
+    for (long long r = 0; r < w.m; ++r) a0 += wp[r];
+    sums[0] = a0;
+    sums[1] = a1;
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  return FFTC_OK;
+}
+
+template <typename T>
+int stage_green_t(fftc_problem* h, const double* ptil_dev, double* u_dev) {
+  Bufs<T> B = bufs<T>(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  launch_convert<double, T>(ptil_dev, B.X, n3, s);
+  enqueue_green<T>(h, SRC_BUF, B.X, 0, 1);
+  launch_convert<T, double>(B.u, u_dev, n3, s);
+  HIPCHK(h, hipStreamSynchronize(s));
+  return FFTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision) {
+  if (!out || !n) return FFTC_E_ARG;
+  *out = nullptr;
+  if (precision != FFTC_FP64 && precision != FFTC_FP32) return FFTC_E_UNSUPPORTED;
+  for (int J = 0; J < 3; ++J)
+    if (n[J] < 2 || n[J] > 4096) return FFTC_E_ARG;
+  fftc_problem* h = new (std::nothrow) fftc_problem();
+  if (!h) return FFTC_E_ARG;
+  for (int J = 0; J < 3; ++J) {
+    h->n[J] = n[J];
+    std::vector<int> rad;
+    if (!factor_ok(n[J], rad)) {
+      delete h;
+      return FFTC_E_UNSUPPORTED;
+    }
+    h->ap[J].n = n[J];
+    h->ap[J].nrad = (int)rad.size();
+    for (size_t q = 0; q < rad.size(); ++q) h->ap[J].rad[q] = rad[q];
+  }
+  h->precision = precision;
+  h->ept = precision == FFTC_FP64 ? 8 : 16;
+  memset(h->bc, FFTC_BC_NEUMANN, sizeof(h->bc));
+  build_plan(h);
+  h->Nv = (long long)n[0] * n[1] * n[2];
+  *out = h;
+  return FFTC_OK;
+}
+
+void fftc_destroy(fftc_h h) { delete h; }
+
+int fftc_set_bc(fftc_h h, const int8_t* bc) {
+  if (!h || !bc) return FFTC_E_ARG;
+  if (h->bound) return fail(h, FFTC_E_STATE, "boundary table must be set before binding the workspace");
+  if (!h->s_comp.empty() || !h->w_comp.empty()) return fail(h, FFTC_E_STATE, "set the boundary table before constraints");
+  for (int q = 0; q < 18; ++q)
+    if (bc[q] < 0 || bc[q] > 2) return fail(h, FFTC_E_ARG, "boundary code out of range");
+  for (int J = 0; J < 3; ++J) {
+    int np = 0;
+    for (int c = 0; c < 3; ++c)
+      for (int f = 0; f < 2; ++f) np += bc[c * 6 + J * 2 + f] == FFTC_BC_PERIODIC;
+    if (np != 0 && np != 6) return fail(h, FFTC_E_BC, "periodicity must hold on both faces of an axis for all components");
+  }
+  memcpy(h->bc, bc, 18);
+  build_plan(h);
+  return FFTC_OK;
+}
+
+int fftc_set_reference(fftc_h h, double lam0, double mu0) {
+  if (!h) return FFTC_E_ARG;
+  if (!(mu0 > 0.0) || !(lam0 + 2.0 * mu0 > 0.0) || !isfinite(lam0) || !isfinite(mu0))
+    return fail(h, FFTC_E_ARG, "reference medium needs mu0 > 0 and lam0 + 2 mu0 > 0");
+  h->lam0 = lam0;
+  h->mu0 = mu0;
+  h->ref_mode = 1;
+  if (h->bound) set_stencil(h);
+  return FFTC_OK;
+}
+
+int fftc_set_reference_factor(fftc_h h, double factor) {
+  if (!h) return FFTC_E_ARG;
+  if (!(factor > 0.0) || !isfinite(factor)) return fail(h, FFTC_E_ARG, "reference factor must be positive");
+  h->r0_factor = factor;
+  h->ref_mode = 0;
+  return FFTC_OK;
+}
+
+int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value,
+                       int32_t set_id) {
+  if (!h || m < 0 || (m > 0 && (!node || !comp || !value))) return FFTC_E_ARG;
+  if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
+  if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
+  std::vector<long long> keys;
+  for (int64_t e = 0; e < m; ++e) {
+    const long long xyz[3] = {node[3 * e], node[3 * e + 1], node[3 * e + 2]};
+    for (int J = 0; J < 3; ++J)
+      if (xyz[J] < 0 || xyz[J] >= h->N[J]) return fail(h, FFTC_E_ARG, "constraint node out of range");
+    if (comp[e] < 0 || comp[e] > 2) return fail(h, FFTC_E_ARG, "component out of range");
+    if (!isfinite(value[e])) return fail(h, FFTC_E_ARG, "non-finite prescribed value");
+    if (node_antisym(h, comp[e], xyz)) {
+      if (value[e] != 0.0) return fail(h, FFTC_E_BC, "nonzero value on a DOF held at 0 by a Dirichlet face");
+      continue;
+    }
+    const long long flat = node_flat(h, xyz[0], xyz[1], xyz[2]);
+    const long long key = comp[e] * h->Nn + flat;
+    if (h->dof_used.count(key) || std::find(keys.begin(), keys.end(), key) != keys.end())
+      return fail(h, FFTC_E_ARG, "DOF constrained twice");
+    keys.push_back(key);
+  }
+  size_t t = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    const long long xyz[3] = {node[3 * e], node[3 * e + 1], node[3 * e + 2]};
+    if (node_antisym(h, comp[e], xyz)) continue;
+    h->s_node.push_back(node_flat(h, xyz[0], xyz[1], xyz[2]));
+    h->s_comp.push_back(comp[e]);
+    h->s_val.push_back(value[e]);
+    h->s_set.push_back(set_id);
+    h->dof_used.insert(keys[t++]);
+  }
+  return FFTC_OK;
+}
+
+int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, const int8_t* comp, const double* value,
+                     int32_t set_id) {
+  if (!h || m < 0 || (m > 0 && (!support || !comp || !value))) return FFTC_E_ARG;
+  if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
+  if (k != 4 && k != 8) return fail(h, FFTC_E_ARG, "support size must be 4 or 8");
+  if (h->w_k != 0 && h->w_k != k) return fail(h, FFTC_E_UNSUPPORTED, "all average relations of a problem share one support size");
+  if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
+  std::unordered_set<long long> mine;
+  for (int64_t r = 0; r < m; ++r) {
+    if (comp[r] < 0 || comp[r] > 2) return fail(h, FFTC_E_ARG, "component out of range");
+    if (!isfinite(value[r])) return fail(h, FFTC_E_ARG, "non-finite prescribed value");
+    for (int q = 0; q < k; ++q) {
+      const long long xyz[3] = {support[(r * k + q) * 3], support[(r * k + q) * 3 + 1], support[(r * k + q) * 3 + 2]};
+      for (int J = 0; J < 3; ++J)
+        if (xyz[J] < 0 || xyz[J] >= h->N[J]) return fail(h, FFTC_E_ARG, "support node out of range");
+      if (node_antisym(h, comp[r], xyz)) return fail(h, FFTC_E_BC, "support node held at 0 by a Dirichlet face");
+      const long long key = comp[r] * h->Nn + node_flat(h, xyz[0], xyz[1], xyz[2]);
+      if (h->dof_used.count(key) || mine.count(key)) return fail(h, FFTC_E_OVERLAP, "overlapping constraint supports");
+      mine.insert(key);
+    }
+  }
+  h->w_k = k;
+  for (int64_t r = 0; r < m; ++r) {
+    for (int q = 0; q < k; ++q) {
+      const int64_t* p = support + (r * k + q) * 3;
+      h->w_nodes.push_back(node_flat(h, p[0], p[1], p[2]));
+    }
+    h->w_comp.push_back(comp[r]);
+    h->w_val.push_back(value[r]);
+    h->w_set.push_back(set_id);
+  }
+  for (long long key : mine) h->dof_used.insert(key);
+  return FFTC_OK;
+}
+
+int fftc_set_sphere(fftc_h h, const double center[3], double radius, int32_t face) {
+  if (!h || !center) return FFTC_E_ARG;
+  if (h->bound) return fail(h, FFTC_E_STATE, "set the obstacle before binding the workspace");
+  if (!(radius > 0.0) || face < 0 || face > 5) return fail(h, FFTC_E_ARG, "invalid sphere");
+  if (h->periodic[face / 2]) return fail(h, FFTC_E_ARG, "contact face on a periodic axis");
+  h->has_sphere = 1;
+  for (int c = 0; c < 3; ++c) h->center[c] = center[c];
+  h->radius = radius;
+  h->face = face;
+  int t = 0, bb[2];
+  for (int J = 0; J < 3; ++J)
+    if (J != face / 2) bb[t++] = J;
+  h->b1 = bb[0];
+  h->b2 = bb[1];
+  return FFTC_OK;
+}
+
+int fftc_move_sphere(fftc_h h, const double center[3]) {
+  if (!h || !center || !h->has_sphere) return FFTC_E_ARG;
+  for (int c = 0; c < 3; ++c) h->center[c] = center[c];
+  return FFTC_OK;
+}
+
+int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg) {
+  if (!h || !cfg) return FFTC_E_ARG;
+  if (cfg->depth != 4) return fail(h, FFTC_E_UNSUPPORTED, "Anderson depth must be 4");
+  if (cfg->period < 1 || cfg->max_iter < 0 || !(cfg->tol >= 0.0) || cfg->acv < 0 || cfg->acv > 2)
+    return fail(h, FFTC_E_ARG, "invalid solver settings");
+  h->cfg = *cfg;
+  return FFTC_OK;
+}
+
+int fftc_workspace_bytes(fftc_h h, size_t* bytes) {
+  if (!h || !bytes) return FFTC_E_ARG;
+  *bytes = carve(h, nullptr);
+  return FFTC_OK;
+}
+
+int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
+  if (!h || !ws) return FFTC_E_ARG;
+  if (((uintptr_t)ws) % kAlign) return fail(h, FFTC_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = carve(h, nullptr);
+  if (bytes < need) return fail(h, FFTC_E_WORKSPACE, "workspace too small");
+  // contact face nodes may not carry other constraints
+  if (h->has_sphere) {
+    const int a = h->face / 2;
+    const long long fc = (h->face % 2) ? h->n[a] : 0;
+    for (size_t e = 0; e < h->s_node.size(); ++e) {
+      long long nd = h->s_node[e];
+      const long long xyz[3] = {nd % h->N[0], (nd / h->N[0]) % h->N[1], nd / ((long long)h->N[0] * h->N[1])};
+      if (xyz[a] == fc) return fail(h, FFTC_E_OVERLAP, "strong constraint on a potential contact node");
+    }
+    for (size_t e = 0; e < h->w_nodes.size(); ++e) {
+      long long nd = h->w_nodes[e];
+      const long long xyz[3] = {nd % h->N[0], (nd / h->N[0]) % h->N[1], nd / ((long long)h->N[0] * h->N[1])};
+      if (xyz[a] == fc) return fail(h, FFTC_E_OVERLAP, "average relation on a potential contact node");
+    }
+  }
+  h->ws = (char*)ws;
+  h->ws_bytes = bytes;
+  h->stream = (hipStream_t)stream;
+  carve(h, h->ws);
+  hipStream_t s = h->stream;
+  // geometry
+  Geo& g = h->g;
+  for (int J = 0; J < 3; ++J) {
+    g.n[J] = h->n[J];
+    g.N[J] = h->N[J];
+    g.periodic[J] = h->periodic[J];
+  }
+  g.Nn = h->Nn;
+  g.Nv = h->Nv;
+  g.aface = h->aface;
+  // axis plans: twiddles e^{-2 pi i t/4n}, lines per block
+  for (int J = 0; J < 3; ++J) {
+    AxisPlan& ap = h->ap[J];
+    ap.N = h->N[J];
+    ap.L = std::max(1, h->ept * kBlock / ap.n);
+    const int n = ap.n;
+    std::vector<double> twd(8 * n);
+    std::vector<float> twf(8 * n);
+    for (int t = 0; t < 4 * n; ++t) {
+      const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)t / (4.0L * n);
+      const long double c = cosl(ang), sn = -sinl(ang);
+      twd[2 * t] = (double)c;
+      twd[2 * t + 1] = (double)sn;
+      twf[2 * t] = (float)c;
+      twf[2 * t + 1] = (float)sn;
+    }
+    if (h->precision == FFTC_FP64)
+      HIPCHK(h, hipMemcpyAsync(h->tw[J], twd.data(), 8 * twd.size(), hipMemcpyHostToDevice, s));
+    else
+      HIPCHK(h, hipMemcpyAsync(h->tw[J], twf.data(), 4 * twf.size(), hipMemcpyHostToDevice, s));
+    ap.tw = h->tw[J];
+    // LDS budget: keep one block within 64 KiB
+    const size_t cs = h->precision == FFTC_FP64 ? 16 : 8, rs = cs / 2;
+    while (ap.L > 1 && ap.L * ((n + 1) * cs + (ap.N + 1) * rs) > 65536) ap.L /= 2;
+  }
+  // symbol tables cos(theta) per (comp, axis)
+  std::vector<double> cosT(9 * (size_t)h->maxN, 1.0);
+  for (int c = 0; c < 3; ++c)
+    for (int J = 0; J < 3; ++J)
+      for (int idx = 0; idx < h->N[J]; ++idx) cosT[(c * 3 + J) * h->maxN + idx] = cos(theta_of(h->type[c][J], h->n[J], idx));
+  HIPCHK(h, hipMemcpyAsync(h->cosT, cosT.data(), 8 * cosT.size(), hipMemcpyHostToDevice, s));
+  // node mask
+  std::vector<uint8_t> mask(h->Nn, 0);
+  for (size_t e = 0; e < h->s_node.size(); ++e) mask[h->s_node[e]] |= (uint8_t)(M_STRONG << h->s_comp[e]);
+  for (size_t r = 0; r < h->w_comp.size(); ++r)
+    for (int q = 0; q < h->w_k; ++q) mask[h->w_nodes[r * h->w_k + q]] |= (uint8_t)(M_WEAK << h->w_comp[r]);
+  if (h->has_sphere) {
+    const int a = h->face / 2;
+    const long long fc = (h->face % 2) ? h->n[a] : 0;
+    for (long long nd = 0; nd < h->Nn; ++nd) {
+      const long long xyz[3] = {nd % h->N[0], (nd / h->N[0]) % h->N[1], nd / ((long long)h->N[0] * h->N[1])};
+      if (xyz[a] == fc) mask[nd] |= M_FACE;
+    }
+  }
+  HIPCHK(h, hipMemcpyAsync(h->mask, mask.data(), h->Nn, hipMemcpyHostToDevice, s));
+  const size_t ms = h->s_comp.size(), mw = h->w_comp.size();
+  if (ms) {
+    HIPCHK(h, hipMemcpyAsync(h->d_snode, h->s_node.data(), 8 * ms, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_scomp, h->s_comp.data(), ms, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_sval, h->s_val.data(), 8 * ms, hipMemcpyHostToDevice, s));
+  }
+  if (mw) {
+    HIPCHK(h, hipMemcpyAsync(h->d_wnodes, h->w_nodes.data(), 8 * h->w_nodes.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_wcomp, h->w_comp.data(), mw, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_wval, h->w_val.data(), 8 * mw, hipMemcpyHostToDevice, s));
+  }
+  h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
+  if (h->nblk_res < 1) h->nblk_res = 1;
+  for (int q = 0; q < 10; ++q)
+    HIPCHK(h, hipMemsetAsync(h->fld[q], 0, (h->precision == FFTC_FP64 ? 8 : 4) * 3 * (size_t)h->Nn, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->bound = 1;
+  h->stiff_set = 0;
+  if (h->ref_mode == 1) set_stencil(h);
+  return FFTC_OK;
+}
+
+int fftc_set_stiffness(fftc_h h, const double* lam, const double* mu) {
+  if (!h || !lam || !mu) return FFTC_E_ARG;
+  if (!h->bound) return fail(h, FFTC_E_STATE, "bind the workspace first");
+  hipStream_t s = h->stream;
+  const int nblk = (int)std::min<long long>(1024, (h->Nv + kBlock - 1) / kBlock);
+  launch_check_stiffness(lam, mu, h->Nv, h->chk, nblk, s);
+  std::vector<double> chk(3 * nblk);
+  HIPCHK(h, hipMemcpyAsync(chk.data(), h->chk, 8 * chk.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  double bad = 0, ml = -INFINITY, mm = -INFINITY;
+  for (int b = 0; b < nblk; ++b) {
+    bad = std::max(bad, chk[3 * b]);
+    ml = std::max(ml, chk[3 * b + 1]);
+    mm = std::max(mm, chk[3 * b + 2]);
+  }
+  if (bad >= 2.0) return fail(h, FFTC_E_NAN, "non-finite stiffness");
+  if (bad >= 1.0) return fail(h, FFTC_E_ARG, "stiffness must satisfy mu >= 0 and 3 lam + 2 mu >= 0");
+  if (h->ref_mode == 0) {
+    h->lam0 = h->r0_factor * ml;
+    h->mu0 = h->r0_factor * mm;
+    if (!(h->mu0 > 0.0) || !(h->lam0 + 2 * h->mu0 > 0.0)) return fail(h, FFTC_E_ARG, "degenerate reference medium");
+  }
+  set_stencil(h);
+  if (h->precision == FFTC_FP64) {
+    HIPCHK(h, hipMemcpyAsync(h->lam, lam, 8 * h->Nv, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->mu, mu, 8 * h->Nv, hipMemcpyDeviceToDevice, s));
+  } else {
+    launch_convert<double, float>(lam, (float*)h->lam, h->Nv, s);
+    launch_convert<double, float>(mu, (float*)h->mu, h->Nv, s);
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->stiff_set = 1;
+  return FFTC_OK;
+}
+
+int fftc_solve(fftc_h h, double* u_dev, int32_t zero_start, fftc_report* rep) {
+  if (!h) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set before solving");
+  return h->precision == FFTC_FP64 ? solve_t<double>(h, u_dev, zero_start, rep)
+                                   : solve_t<float>(h, u_dev, zero_start, rep);
+}
+
+int fftc_get_reactions(fftc_h h, double* per_dof, double* per_rel, double* totals, int32_t nsets) {
+  if (!h) return FFTC_E_ARG;
+  if (per_dof) memcpy(per_dof, h->react_strong.data(), 8 * h->react_strong.size());
+  if (per_rel) memcpy(per_rel, h->react_weak.data(), 8 * h->react_weak.size());
+  if (totals) {
+    if (nsets < 0) return FFTC_E_ARG;
+    for (int q = 0; q < 3 * nsets; ++q) totals[q] = 0.0;
+    for (size_t e = 0; e < h->react_strong.size(); ++e)
+      if (h->s_set[e] < nsets) totals[h->s_set[e] * 3 + h->s_comp[e]] += h->react_strong[e];
+    for (size_t r = 0; r < h->react_weak.size(); ++r)
+      if (h->w_set[r] < nsets) totals[h->w_set[r] * 3 + h->w_comp[r]] += h->react_weak[r];
+  }
+  return FFTC_OK;
+}
+
+int fftc_num_constraints(fftc_h h, int64_t* ns, int64_t* nw) {
+  if (!h) return FFTC_E_ARG;
+  if (ns) *ns = (int64_t)h->s_comp.size();
+  if (nw) *nw = (int64_t)h->w_comp.size();
+  return FFTC_OK;
+}
+
+int fftc_num_face_nodes(fftc_h h, int64_t* count) {
+  if (!h || !count) return FFTC_E_ARG;
+  *count = h->has_sphere ? (int64_t)h->nface : 0;
+  return FFTC_OK;
+}
+
+int fftc_get_contact(fftc_h h, uint8_t* mask, double* fnc, double* gap) {
+  if (!h || !h->has_sphere || !h->bound) return FFTC_E_ARG;
+  hipStream_t s = h->stream;
+  if (mask) HIPCHK(h, hipMemcpyAsync(mask, h->C, h->nface, hipMemcpyDeviceToHost, s));
+  if (fnc) HIPCHK(h, hipMemcpyAsync(fnc, h->fnc, 8 * h->nface, hipMemcpyDeviceToHost, s));
+  if (gap) HIPCHK(h, hipMemcpyAsync(gap, h->gap, 8 * h->nface, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return FFTC_OK;
+}
+
+int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* ptil_dev, double* sums) {
+  if (!h || !u_dev) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
+  return h->precision == FFTC_FP64 ? stage_residual_t<double>(h, u_dev, p_dev, ptil_dev, sums)
+                                   : stage_residual_t<float>(h, u_dev, p_dev, ptil_dev, sums);
+}
+
+int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev) {
+  if (!h || !ptil_dev || !u_dev) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
+  return h->precision == FFTC_FP64 ? stage_green_t<double>(h, ptil_dev, u_dev)
+                                   : stage_green_t<float>(h, ptil_dev, u_dev);
+}
+
+const char* fftc_status_str(int status) {
+  switch (status) {
+    case FFTC_OK: return "ok";
+    case FFTC_E_ARG: return "invalid argument";
+    case FFTC_E_BC: return "inconsistent boundary condition";
+    case FFTC_E_OVERLAP: return "overlapping constraints";
+    case FFTC_E_WORKSPACE: return "workspace missing or too small";
+    case FFTC_E_NOCONV: return "not converged";
+    case FFTC_E_NAN: return "non-finite value";
+    case FFTC_E_UNSUPPORTED: return "unsupported";
+    case FFTC_E_STATE: return "call out of order";
+    case FFTC_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* fftc_last_error(fftc_h h) { return h ? h->err.c_str() : "null handle"; }
+
+int fftc_iterate(fftc_h h, int32_t iters) {
+  if (!h || iters < 0) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
+  launch_extend(h->st, iters, 0.0, h->stream);
+  for (int t = 0; t < iters; ++t) {
+    if (h->precision == FFTC_FP64) enqueue_iteration<double>(h);
+    else enqueue_iteration<float>(h);
+  }
+  HIPCHK(h, hipGetLastError());
+  return FFTC_OK;
+}
+
+int fftc_profile_stages(fftc_h h, int32_t iters, double* ms, int32_t nstages) {
+  if (!h || !ms || iters < 1 || nstages < 0) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
+  return h->precision == FFTC_FP64 ? profile_t<double>(h, iters, ms, nstages) : profile_t<float>(h, iters, ms, nstages);
+}
+
+}  // extern "C"

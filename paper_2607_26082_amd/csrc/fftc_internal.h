@@ -1,0 +1,119 @@
+// Internal declarations shared by the kernels and the host runtime of libfftc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftc {
+
+enum DttType { T_DCT1 = 0, T_DCT3 = 1, T_DST1 = 2, T_DST3 = 3, T_DFT = 4 };
+enum PassMode { PASS_FWD = 0, PASS_INV = 1, PASS_FWD_GREEN_INV = 2 };
+enum SrcMode { SRC_BUF = 0, SRC_ANDERSON = 1 };
+
+constexpr int kMaxRadices = 16;
+constexpr int kBlock = 256;          // threads per block of every streaming kernel
+constexpr int kPartStride = 8;       // doubles per block partial of the residual pass
+constexpr int kMaxSets = 64;
+
+// node mask bits
+constexpr uint8_t M_STRONG = 1;      // << comp
+constexpr uint8_t M_WEAK = 8;        // << comp
+constexpr uint8_t M_FACE = 64;       // potential contact node
+
+struct Geo {
+  int n[3];            // voxels per axis
+  int N[3];            // nodes per axis
+  int periodic[3];
+  long long Nn;        // nodes
+  long long Nv;        // voxels
+  int aface;           // bit (c*6 + J*2 + f): component c antisymmetric on face (J, f)
+  // Paux reference stencil per component: diagonal, xy-, xz-, yz-plane face-diagonal coefficients
+  double st[3][4];
+};
+
+// Device-resident iteration state (one per handle, in the workspace).
+struct DevState {
+  int done, status, it, i_local;
+  int store_r, accel, accel_ok, acv;
+  int have_prev, updates, restarts, vpar;
+  int period, max_iter, contact, nC;
+  int vnonempty, pad1, pad2, pad3;
+  double tol, gate, residual, pnorm2;
+  double snorm2, pad4;
+  double ms[6];
+  double gram[16];
+  double alpha[4];
+};
+
+enum StatusCode { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
+
+struct AxisPlan {
+  int n;                   // transform length (voxels on the axis)
+  int N;                   // nodes on a line
+  int nrad;
+  int rad[kMaxRadices];
+  int L;                   // lines per block
+  const void* tw;          // e^{-2 pi i t / 4n}, t = 0..4n-1, as (re, im) pairs of the working type
+};
+
+template <typename T>
+struct Bufs {
+  T* u;        // displacement (also the transform buffer)
+  T* X;        // p~ written by the residual pass
+  T* S[4];
+  T* R[4];
+  const T* lam;
+  const T* mu;
+  const uint8_t* mask;
+};
+
+struct ContactDev {
+  int on;
+  int axis, side;          // contact face
+  int b1, b2;              // in-plane axes (b1 < b2)
+  long long nface;
+  double center[3];
+  double radius;
+  uint8_t* C;              // active set per face node
+  uint8_t* V[2];           // V_gap (bit 0) / V_react (bit 1), current/previous
+  double* fnc;             // normal reaction per face node
+  double* gap;             // gap per face node
+};
+
+struct StrongDev {
+  long long m;
+  const long long* node;
+  const int8_t* comp;
+  const double* val;
+};
+
+struct WeakDev {
+  long long m;
+  int k;
+  const long long* nodes;   // m*k
+  const int8_t* comp;
+  const double* val;
+  double* part;             // per relation partial ||p||^2 after projection
+  double* react;            // per relation reaction
+};
+
+template <typename T>
+struct DttArgs {
+  Geo g;
+  int axis, mode, src;
+  AxisPlan ap;                 // this axis
+  int types[3];                // per component on this axis
+  T* buf;                      // in/out node-shaped field
+  const T* in;                 // forward source when src == SRC_BUF and in != buf
+  Bufs<T> B;                   // Anderson buffers (src == SRC_ANDERSON)
+  int store_s;
+  DevState* st;
+  int force;
+  // Green (z pass)
+  const double* cosT;          // [3 comps][3 axes][maxN]
+  int maxN;
+  int inv_types[3];
+  double thr[3];
+};
+
+}  // namespace fftc

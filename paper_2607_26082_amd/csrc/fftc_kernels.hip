@@ -1,0 +1,1132 @@
+// HIP kernels of libfftc for CDNA4 (gfx950), 64-wide wavefronts.
+//
+// One fixed-point iteration (paper Algorithm 1 / Algorithm 2, eq 3 and eq 9):
+//   k_residual   stress at both TETRA2 integration points of the 8 voxels around
+//                each node, nodal divergence (boundary weight 2^b), proj_P for strong
+//                DOFs and contact nodes, reference-medium term, FP64 partial norms
+//   k_weak       proj_P of the average relations (eq 14)
+//   k_control    equilibrium test (eq 5), contact active-set update, Anderson flags
+//   k_anderson_r / k_alpha   residual store, FP64 Gram matrix, constrained LS
+//   k_dtt        per-axis DTT passes (Tables 2-3) in LDS; the z pass applies the Green
+//                operator between its forward and inverse transforms (eq 3-4)
+//   k_proj_*     proj_U: average relations (eq 11), contact radial projection, strong DOFs
+#include "fftc_internal.h"
+#include "fftc_launch.h"
+
+#include <math.h>
+
+namespace fftc {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cplx {
+  T re, im;
+};
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of NV doubles; result valid in thread 0.  Fixed reduction order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*16 */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q * 16 + wid] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[q * 16 + w];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int mirror_coord(const Geo& g, int x, int J) {
+  if (g.periodic[J]) return x < 0 ? x + g.N[J] : (x >= g.N[J] ? x - g.N[J] : x);
+  return x < 0 ? -x : (x > g.n[J] ? 2 * g.n[J] - x : x);
+}
+
+__device__ __forceinline__ bool is_antisym(const Geo& g, int c, const int xyz[3]) {
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    if (g.periodic[J]) continue;
+    if (xyz[J] == 0 && ((g.aface >> (c * 6 + J * 2 + 0)) & 1)) return true;
+    if (xyz[J] == g.n[J] && ((g.aface >> (c * 6 + J * 2 + 1)) & 1)) return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ int bcount(const Geo& g, const int xyz[3]) {
+  int b = 0;
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    if (!g.periodic[J] && (xyz[J] == 0 || xyz[J] == g.n[J])) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Residual of one node: p = 2^b div_D(C : grad^s_D u) summed over in-cell voxels,
+// and K0 u = -2^b div_D(R0 : grad_D u) from the closed-form Paux stencil applied to
+// the symmetric extension of u.  Optionally the stress norm and mean-stress sums of
+// the tetrahedra owned by this node (T1 of voxel n, T2 of voxel n - e_x).
+// ---------------------------------------------------------------------------
+template <typename T, bool SIG>
+__device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u, const T* __restrict__ lam,
+                                          const T* __restrict__ mu, int i, int j, int k, T p[3], T k0[3],
+                                          double& sn, double ms[6]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  // 13 same-parity neighbours (self + 12 face diagonals), mirrored at the faces
+  T nb[27][3];
+  const int xm = mirror_coord(g, i - 1, 0), xp = mirror_coord(g, i + 1, 0);
+  const int ym = mirror_coord(g, j - 1, 1), yp = mirror_coord(g, j + 1, 1);
+  const int zm = mirror_coord(g, k - 1, 2), zp = mirror_coord(g, k + 1, 2);
+  const int xs[3] = {xm, i, xp}, ys[3] = {ym, j, yp}, zs[3] = {zm, k, zp};
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nrm = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nrm != 0 && nrm != 2) continue;
+        const long long idx = (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1]);
+        const int q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[q][c] = u[c * Nn + idx];
+      }
+
+  T F[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    int vx = i - ax, vy = j - ay, vz = k - az;
+    bool inside = true;
+    if (g.periodic[0]) { if (vx < 0) vx += g.n[0]; } else inside &= (vx >= 0 && vx < g.n[0]);
+    if (g.periodic[1]) { if (vy < 0) vy += g.n[1]; } else inside &= (vy >= 0 && vy < g.n[1]);
+    if (g.periodic[2]) { if (vz < 0) vz += g.n[2]; } else inside &= (vz >= 0 && vz < g.n[2]);
+    if (!inside) continue;
+    const long long vid = (long long)vx + (long long)g.n[0] * ((long long)vy + (long long)g.n[1] * vz);
+    const T l = lam[vid], m = mu[vid];
+    // gradient on the tetrahedron of this voxel that contains the node
+    T G[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) G[r][s] = T(0);
+    const int par = (ax + ay + az) & 1;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+      if (((cx + cy + cz) & 1) != par) continue;
+      const int q = (cx - ax + 1) + 3 * (cy - ay + 1) + 9 * (cz - az + 1);
+      const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        G[r][0] += sx * nb[q][r];
+        G[r][1] += sy * nb[q][r];
+        G[r][2] += sz * nb[q][r];
+      }
+    }
+    const T tr = G[0][0] + G[1][1] + G[2][2];
+    const T s00 = l * tr + T(2) * m * G[0][0];
+    const T s11 = l * tr + T(2) * m * G[1][1];
+    const T s22 = l * tr + T(2) * m * G[2][2];
+    const T s01 = m * (G[0][1] + G[1][0]);
+    const T s02 = m * (G[0][2] + G[2][0]);
+    const T s12 = m * (G[1][2] + G[2][1]);
+    // nodal force: (1/2 IP weight) * B_node^T sigma with B_node = (2a - 1)/2
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    F[0] += bx * s00 + by * s01 + bz * s02;
+    F[1] += bx * s01 + by * s11 + bz * s12;
+    F[2] += bx * s02 + by * s12 + bz * s22;
+    if (SIG && (a == 0 || a == 1)) {
+      const double d00 = s00, d11 = s11, d22 = s22, d01 = s01, d02 = s02, d12 = s12;
+      sn += 0.5 * (d00 * d00 + d11 * d11 + d22 * d22 + 2.0 * (d01 * d01 + d02 * d02 + d12 * d12));
+      ms[0] += 0.5 * d00; ms[1] += 0.5 * d11; ms[2] += 0.5 * d22;
+      ms[3] += 0.5 * d12; ms[4] += 0.5 * d02; ms[5] += 0.5 * d01;
+    }
+  }
+  const int xyz[3] = {i, j, k};
+  const int b = bcount(g, xyz);
+  const T w2b = T(1 << b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int q0 = 13;
+    const T sxy = nb[0 + 0 + 9][c] + nb[2 + 0 + 9][c] + nb[0 + 6 + 9][c] + nb[2 + 6 + 9][c];
+    const T sxz = nb[0 + 3 + 0][c] + nb[2 + 3 + 0][c] + nb[0 + 3 + 18][c] + nb[2 + 3 + 18][c];
+    const T syz = nb[1 + 0 + 0][c] + nb[1 + 6 + 0][c] + nb[1 + 0 + 18][c] + nb[1 + 6 + 18][c];
+    const T kk = T(g.st[c][0]) * nb[q0][c] + T(g.st[c][1]) * sxy + T(g.st[c][2]) * sxz + T(g.st[c][3]) * syz;
+    const bool A = is_antisym(g, c, xyz);
+    p[c] = A ? T(0) : -w2b * F[c];
+    k0[c] = A ? T(0) : kk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual pass
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDev ct, DevState* st,
+                                                     double* __restrict__ part, int force, int write_p) {
+  __shared__ double sh[kPartStride * 16];
+  if (!force && st->done) return;
+  double acc[kPartStride];
+#pragma unroll
+  for (int q = 0; q < kPartStride; ++q) acc[q] = 0.0;
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int cur = ct.on ? st->vpar : 0;
+  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < Nn;
+       node += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(node % Nx);
+    const long long r = node / Nx;
+    const int j = (int)(r % Ny), k = (int)(r / Ny);
+    T p[3], k0[3];
+    double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
+    node_eval<T, true>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+    acc[1] += sn;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
+    const uint8_t m = B.mask[node];
+    if (ct.on && (m & M_FACE)) {
+      const int xyz[3] = {i, j, k};
+      const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
+      const double X0 = i + (double)B.u[node], X1 = j + (double)B.u[Nn + node], X2 = k + (double)B.u[2 * Nn + node];
+      const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
+      const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double gap = rr - ct.radius;
+      const double n0 = -d0 / rr, n1 = -d1 / rr, n2 = -d2 / rr;
+      const double pn = (double)p[0] * n0 + (double)p[1] * n1 + (double)p[2] * n2;
+      const int b = bcount(g, xyz);
+      const double fnc = -pn / (double)(1 << b);
+      const uint8_t inC = ct.C[f];
+      if (inC) {
+        p[0] = (T)((double)p[0] - pn * n0);
+        p[1] = (T)((double)p[1] - pn * n1);
+        p[2] = (T)((double)p[2] - pn * n2);
+      }
+      ct.V[cur][f] = (uint8_t)(((!inC) && gap < 0.0) ? 1 : 0) | (uint8_t)((inC && fnc > 0.0) ? 2 : 0);
+      ct.fnc[f] = fnc;
+      ct.gap[f] = gap;
+      acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (m & (M_STRONG << c)) p[c] = T(0);
+        else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) B.X[c * Nn + node] = write_p ? p[c] : p[c] + k0[c];
+  }
+  block_sum<kPartStride>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < kPartStride; ++q) part[blockIdx.x * kPartStride + q] = acc[q];
+}
+
+// Residual only (no norms) for a list of nodes: used by the weak projection and reactions.
+template <typename T>
+__device__ __forceinline__ void node_p(const Geo& g, const Bufs<T>& B, long long node, T p[3], int& b) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const int i = (int)(node % Nx);
+  const long long r = node / Nx;
+  const int j = (int)(r % Ny), k = (int)(r / Ny);
+  T k0[3];
+  double sn = 0.0, ms[6];
+  node_eval<T, false>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+  const int xyz[3] = {i, j, k};
+  b = bcount(g, xyz);
+}
+
+// proj_P of the average relations (eq 14) on the physical residual 2^-b p.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_weak(Geo g, Bufs<T> B, WeakDev w, DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (r >= w.m) return;
+  const int c = w.comp[r];
+  double phys[8], wb[8];
+  double sum = 0.0;
+  for (int s = 0; s < w.k; ++s) {
+    T p[3];
+    int b;
+    node_p<T>(g, B, w.nodes[r * w.k + s], p, b);
+    wb[s] = (double)(1 << b);
+    phys[s] = (double)p[c] / wb[s];
+    sum += phys[s];
+  }
+  const double mean = sum / w.k;
+  double pn = 0.0;
+  for (int s = 0; s < w.k; ++s) {
+    const long long node = w.nodes[r * w.k + s];
+    const double pnew = (phys[s] - mean) * wb[s];
+    pn += pnew * pnew;
+    B.X[c * g.Nn + node] = (T)((double)B.X[c * g.Nn + node] - mean * wb[s]);
+  }
+  w.part[r] = pn;
+  w.react[r] = -sum;
+}
+
+// ---------------------------------------------------------------------------
+// Control: equilibrium test, contact update, Anderson flags (one block)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* __restrict__ part, int nblk,
+                                                    const double* __restrict__ wpart, long long nweak, ContactDev ct) {
+  __shared__ double sh[kPartStride * 16];
+  __shared__ int flags[4];
+  if (st->done) return;
+  double acc[kPartStride];
+#pragma unroll
+  for (int q = 0; q < kPartStride; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < kPartStride; ++q) acc[q] += part[b * kPartStride + q];
+  for (long long r = threadIdx.x; r < nweak; r += blockDim.x) acc[0] += wpart[r];
+  block_sum<kPartStride>(acc, sh);
+  if (threadIdx.x == 0) {
+    st->pnorm2 = acc[0];
+    st->snorm2 = acc[1];
+    for (int q = 0; q < 6; ++q) st->ms[q] = acc[2 + q];
+    flags[0] = flags[1] = 0;
+  }
+  __syncthreads();
+  // contact: compare V with the previous iteration, test emptiness
+  if (ct.on) {
+    const int cur = st->vpar;
+    int differ = 0, nonempty = 0;
+    for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
+      const uint8_t v = ct.V[cur][f];
+      nonempty |= (v != 0);
+      differ |= (v != ct.V[cur ^ 1][f]);
+    }
+    if (differ) atomicOr(&flags[0], 1);
+    if (nonempty) atomicOr(&flags[1], 1);
+    __syncthreads();
+  }
+  __shared__ int decide, s_done, changed;
+  if (threadIdx.x == 0) {
+    const double pn = st->pnorm2, sn = st->snorm2;
+    double res;
+    if (pn == 0.0) res = 0.0;
+    else if (sn == 0.0) res = INFINITY;
+    else res = sqrt(pn) / sqrt(sn);
+    st->residual = res;
+    decide = 0;
+    changed = 0;
+    s_done = 0;
+    const int nonempty = ct.on ? flags[1] : 0;
+    st->vnonempty = nonempty;
+    if (!isfinite(pn) || !isfinite(sn)) {
+      st->status = ST_NAN;
+      s_done = 1;
+    } else if (res < st->tol && !nonempty) {
+      st->status = ST_CONVERGED;
+      s_done = 1;
+    } else if (st->it >= st->max_iter) {
+      st->status = ST_NOCONV;
+      s_done = 1;
+    } else {
+      if (ct.on && st->have_prev && !flags[0] && nonempty && res < st->gate) decide = 1;
+    }
+    if (s_done) st->done = 1;
+  }
+  __syncthreads();
+  if (s_done) return;
+  if (ct.on) {
+    if (decide) {
+      const int cur = st->vpar;
+      int ch = 0;
+      for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
+        const uint8_t v = ct.V[cur][f];
+        const uint8_t old = ct.C[f];
+        const uint8_t nw = (uint8_t)((old || (v & 1)) && !(v & 2));
+        if (nw != old) {
+          ct.C[f] = nw;
+          ch = 1;
+        }
+      }
+      if (ch) atomicOr(&changed, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (decide) {
+        st->updates += 1;
+        if (changed) {
+          st->i_local = 0;
+          st->restarts += 1;
+        }
+      }
+      st->have_prev = 1;
+      st->vpar ^= 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int i = st->i_local;
+    st->store_r = (st->acv == 2) && (i > 0);
+    st->accel = (st->acv == 2) && (i >= 4) && (i % st->period == 0);
+    st->accel_ok = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Anderson: R_{i-1 mod 4} = p~ - S_{i-1 mod 4}; Gram partials when accelerating
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_anderson_r(Bufs<T> B, long long n3, DevState* st,
+                                                       double* __restrict__ gpart) {
+  __shared__ double sh[10 * 16];
+  if (st->done) return;
+  const int store = st->store_r, accel = st->accel;
+  if (!store && !accel) return;
+  const int i = st->i_local;
+  const int s = (i + 3) & 3;
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  T* Rs = B.R[s];
+  const T* Ss = B.S[s];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
+    T r[4];
+    if (store) {
+      r[s] = B.X[e] - Ss[e];
+      Rs[e] = r[s];
+    }
+    if (accel) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q != s || !store) r[q] = B.R[q][e];
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) acc[t++] += (double)r[a] * (double)r[b];
+    }
+  }
+  if (!accel) return;
+  block_sum<10>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) gpart[blockIdx.x * 10 + q] = acc[q];
+}
+
+// alpha = argmin |sum a_k R_k|, sum a_k = 1, from the regularised FP64 Gram matrix.
+__global__ __launch_bounds__(kBlock) void k_alpha(DevState* st, const double* __restrict__ gpart, int nblk) {
+  __shared__ double sh[10 * 16];
+  if (st->done || !st->accel) return;
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] += gpart[b * 10 + q];
+  block_sum<10>(acc, sh);
+  if (threadIdx.x != 0) return;
+  double G[4][5];
+  int t = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      G[a][b] = acc[t];
+      G[b][a] = acc[t];
+      ++t;
+    }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) st->gram[a * 4 + b] = G[a][b];
+  const double tr = G[0][0] + G[1][1] + G[2][2] + G[3][3];
+  for (int a = 0; a < 4; ++a) {
+    G[a][a] += 1e-14 * tr / 4.0;
+    G[a][4] = 1.0;
+  }
+  // Gaussian elimination with partial pivoting
+  bool ok = true;
+  for (int col = 0; col < 4 && ok; ++col) {
+    int piv = col;
+    double best = fabs(G[col][col]);
+    for (int r = col + 1; r < 4; ++r)
+      if (fabs(G[r][col]) > best) {
+        best = fabs(G[r][col]);
+        piv = r;
+      }
+    if (!(best > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int q = 0; q < 5; ++q) {
+        const double tmp = G[col][q];
+        G[col][q] = G[piv][q];
+        G[piv][q] = tmp;
+      }
+    for (int r = col + 1; r < 4; ++r) {
+      const double f = G[r][col] / G[col][col];
+      for (int q = col; q < 5; ++q) G[r][q] -= f * G[col][q];
+    }
+  }
+  double y[4] = {0, 0, 0, 0};
+  if (ok) {
+    for (int r = 3; r >= 0; --r) {
+      double s = G[r][4];
+      for (int q = r + 1; q < 4; ++q) s -= G[r][q] * y[q];
+      y[r] = s / G[r][r];
+    }
+    const double sy = y[0] + y[1] + y[2] + y[3];
+    ok = isfinite(sy) && sy != 0.0 && isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]) && isfinite(y[3]);
+    if (ok)
+      for (int a = 0; a < 4; ++a) st->alpha[a] = y[a] / sy;
+  }
+  st->accel_ok = ok ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched per-axis discrete trigonometric transforms in LDS
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T> (&a)[R], int sgn) {
+  if constexpr (R == 2) {
+    const cplx<T> t0 = cadd(a[0], a[1]), t1 = csub(a[0], a[1]);
+    a[0] = t0;
+    a[1] = t1;
+  } else if constexpr (R == 3) {
+    const T c1 = T(-0.5), s1 = T(sgn) * T(0.86602540378443864676);
+    const cplx<T> sum = cadd(a[1], a[2]), dif = csub(a[1], a[2]);
+    const cplx<T> m = {a[0].re + c1 * sum.re, a[0].im + c1 * sum.im};
+    const cplx<T> rot = {-s1 * dif.im, s1 * dif.re};   // i * s1 * dif
+    a[0] = cadd(a[0], sum);
+    a[1] = cadd(m, rot);
+    a[2] = csub(m, rot);
+  } else if constexpr (R == 4) {
+    const cplx<T> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    const cplx<T> t2 = cadd(a[1], a[3]), d = csub(a[1], a[3]);
+    const cplx<T> t3 = {-T(sgn) * d.im, T(sgn) * d.re};   // sgn * i * d
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  } else if constexpr (R == 5) {
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+    const T s1 = T(sgn) * T(0.95105651629515357212), s2 = T(sgn) * T(0.58778525229247312917);
+    const cplx<T> b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+    const cplx<T> d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+    const cplx<T> m1 = {a[0].re + c1 * b1.re + c2 * b2.re, a[0].im + c1 * b1.im + c2 * b2.im};
+    const cplx<T> m2 = {a[0].re + c2 * b1.re + c1 * b2.re, a[0].im + c2 * b1.im + c1 * b2.im};
+    // rotations i*(s1 d1 + s2 d2) and i*(s2 d1 - s1 d2)
+    const cplx<T> r1 = {-(s1 * d1.im + s2 * d2.im), s1 * d1.re + s2 * d2.re};
+    const cplx<T> r2 = {-(s2 * d1.im - s1 * d2.im), s2 * d1.re - s1 * d2.re};
+    a[0] = {a[0].re + b1.re + b2.re, a[0].im + b1.im + b2.im};
+    a[1] = cadd(m1, r1);
+    a[4] = csub(m1, r1);
+    a[2] = cadd(m2, r2);
+    a[3] = csub(m2, r2);
+  }
+}
+
+// One Stockham stage of radix R over L lines of length n (single LDS buffer,
+// register staging between a read phase and a write phase).
+template <typename T, int R, int EPT>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, int cstride, int L, int n, int Ns, int sgn,
+                                          const cplx<T>* __restrict__ tw) {
+  constexpr int MAXW = (EPT + R - 1) / R;
+  const int nb = n / R;
+  const int total = L * nb;
+  cplx<T> v[MAXW][R];
+#pragma unroll
+  for (int t = 0; t < MAXW; ++t) {
+    const int w = threadIdx.x + t * kBlock;
+    if (w < total) {
+      const int line = w / nb, jj = w - line * nb;
+      const cplx<T>* src = buf + line * cstride + jj;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[t][q] = src[q * nb];
+    }
+  }
+  __syncthreads();
+  const int step = n / (Ns * R);
+#pragma unroll
+  for (int t = 0; t < MAXW; ++t) {
+    const int w = threadIdx.x + t * kBlock;
+    if (w < total) {
+      const int line = w / nb, jj = w - line * nb;
+      const int kk = jj % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          cplx<T> f = tw[4 * (q * kk * step)];
+          if (sgn > 0) f.im = -f.im;
+          v[t][q] = cmul(v[t][q], f);
+        }
+      }
+      dft_small<T, R>(v[t], sgn);
+      cplx<T>* dst = buf + line * cstride + (jj / Ns) * Ns * R + kk;
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[q * Ns] = v[t][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int EPT>
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, int cstride, int L, const AxisPlan& ap, int sgn) {
+  const cplx<T>* tw = (const cplx<T>*)ap.tw;
+  int Ns = 1;
+  for (int s = 0; s < ap.nrad; ++s) {
+    const int r = ap.rad[s];
+    if (r == 4) fft_stage<T, 4, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    else if (r == 2) fft_stage<T, 2, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    else if (r == 3) fft_stage<T, 3, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    else fft_stage<T, 5, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    Ns *= r;
+  }
+}
+
+// FFT direction of each (type, forward/inverse): -1 = e^{-i}, +1 = e^{+i}
+__device__ __forceinline__ int fft_sign(int type, int inv) {
+  if (!inv) return (type == T_DCT3 || type == T_DST3) ? +1 : -1;
+  return (type == T_DFT) ? +1 : -1;
+}
+
+// Pre-processing: complex input z_k (k < n) of the length-n FFT from the real line x.
+template <typename T>
+__device__ __forceinline__ cplx<T> dtt_pre(int type, int inv, const T* x, int n, int k, const cplx<T>* tw) {
+  if (type == T_DCT1) {
+    const int j0 = 2 * k, j1 = 2 * k + 1;
+    const T a = x[j0 <= n ? j0 : 2 * n - j0];
+    const T b = x[j1 <= n ? j1 : 2 * n - j1];
+    return {a, b};
+  }
+  if (type == T_DST1) {
+    const int j0 = 2 * k, j1 = 2 * k + 1;
+    const T a = (j0 == 0 || j0 == n) ? T(0) : (j0 < n ? x[j0] : -x[2 * n - j0]);
+    const T b = (j1 == n) ? T(0) : (j1 < n ? x[j1] : -x[2 * n - j1]);
+    return {a, b};
+  }
+  if (type == T_DFT) {
+    if (!inv) return {x[k], T(0)};
+    if (k == 0) return {x[0], T(0)};
+    if (2 * k == n) return {x[k], T(0)};
+    if (2 * k < n) return {x[k], x[n - k]};
+    return {x[n - k], -x[k]};
+  }
+  if (!inv) {
+    // DCT3 / DST3 forward: W_k = e^{+i pi k / 2n} (a - i b)
+    T a, b;
+    if (type == T_DCT3) {
+      a = x[k];
+      b = (k == 0) ? T(0) : x[n - k];
+    } else {
+      a = x[n - k];
+      b = (k == 0) ? T(0) : x[k];
+    }
+    const cplx<T> w = cconj(tw[k]);
+    return cmul(w, cplx<T>{a, -b});
+  }
+  // inverse of DCT3 (DCT2) / of DST3 (DST2 via alternating signs): reordered real input
+  const int h = (n + 1) / 2;
+  if (k < h) return {x[2 * k], T(0)};
+  const T v = x[2 * n - 1 - 2 * k];
+  return {type == T_DST3 ? -v : v, T(0)};
+}
+
+// Post-processing: real output at storage index m (0..N-1) from the FFT result Z.
+template <typename T>
+__device__ __forceinline__ T dtt_post(int type, int inv, const cplx<T>* Z, int n, int m, const cplx<T>* tw) {
+  if (type == T_DCT1 || type == T_DST1) {
+    if (type == T_DST1 && (m == 0 || m == n)) return T(0);
+    const cplx<T> Zm = Z[m == n ? 0 : m];
+    const cplx<T> Zc = cconj(Z[m == 0 ? 0 : n - m]);
+    const cplx<T> E = {(Zm.re + Zc.re) * T(0.5), (Zm.im + Zc.im) * T(0.5)};
+    const cplx<T> D = {(Zm.re - Zc.re) * T(0.5), (Zm.im - Zc.im) * T(0.5)};
+    const cplx<T> O = {D.im, -D.re};   // D / i
+    const cplx<T> Y = cadd(E, cmul(tw[2 * m], O));
+    const T s = inv ? T(1) / T(2 * n) : T(1);
+    return (type == T_DCT1 ? Y.re : -Y.im) * s;
+  }
+  if (type == T_DFT) {
+    if (inv) return Z[m].re / T(n);
+    return (2 * m <= n) ? Z[m].re : Z[n - m].im;
+  }
+  if (!inv) {
+    if (m >= n) return T(0);
+    const int h = (m & 1) ? (n - 1 - (m - 1) / 2) : (m / 2);
+    const T v = Z[h].re;
+    return (type == T_DST3 && (m & 1)) ? -v : v;
+  }
+  // inverse: DCT2 (nodes 0..n-1) or DST2 (nodes 1..n), scaled by 1/2n
+  if (type == T_DCT3) {
+    if (m >= n) return T(0);
+    return cmul(tw[m], Z[m]).re / T(n);
+  }
+  if (m == 0) return T(0);
+  const int kk = n - m;
+  return cmul(tw[kk], Z[kk]).re / T(n);
+}
+
+
+template <typename T, int EPT>
+__global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (!a.force && a.st->done) return;
+  const int c = blockIdx.y;
+  const int n = a.ap.n, N = a.ap.N, L = a.ap.L;
+  const int Nx = a.g.N[0], Ny = a.g.N[1];
+  const long long Nn = a.g.Nn;
+  const int axis = a.axis;
+  const long long nlines = axis == 0 ? (long long)Ny * a.g.N[2] : axis == 1 ? (long long)Nx * a.g.N[2] : (long long)Nx * Ny;
+  const long long stride = axis == 0 ? 1 : axis == 1 ? Nx : (long long)Nx * Ny;
+  const long long l0 = (long long)blockIdx.x * L;
+  const int cstride = n + 1, rstride = N + 1;
+  cplx<T>* cb = (cplx<T>*)smem;
+  T* rb = (T*)(smem + sizeof(cplx<T>) * (size_t)L * cstride);
+  const cplx<T>* tw = (const cplx<T>*)a.ap.tw;
+  const int type = a.types[c];
+  auto off = [&](long long l) -> long long {
+    if (axis == 0) return l * Nx;
+    if (axis == 1) return (l / Nx) * ((long long)Nx * Ny) + (l % Nx);
+    return l;
+  };
+  const long long cbase = (long long)c * Nn;
+  // phase 1: gather the real lines into LDS (each node once)
+  const int inv_first = (a.mode == PASS_INV);
+  {
+    const int total = L * N;
+    int slot = 0, acc_ok = 0;
+    double al[4] = {0, 0, 0, 0};
+    if (a.src == SRC_ANDERSON) {
+      slot = a.st->i_local & 3;
+      acc_ok = a.st->accel_ok;
+      if (acc_ok)
+        for (int q = 0; q < 4; ++q) al[q] = a.st->alpha[q];
+    }
+    for (int w = threadIdx.x; w < total; w += kBlock) {
+      int l, m;
+      if (axis == 0) { l = w / N; m = w - l * N; } else { m = w / L; l = w - m * L; }
+      const long long lg = l0 + l;
+      T v = T(0);
+      if (lg < nlines) {
+        const long long addr = cbase + off(lg) + (long long)m * stride;
+        if (a.src == SRC_ANDERSON) {
+          if (acc_ok) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += al[q] * ((double)a.B.S[q][addr] + (double)a.B.R[q][addr]);
+            v = (T)s;
+          } else {
+            v = a.B.X[addr];
+          }
+          if (a.store_s) a.B.S[slot][addr] = v;
+        } else {
+          v = a.in[addr];
+        }
+      }
+      rb[l * rstride + m] = v;
+    }
+  }
+  __syncthreads();
+  // phase 2 + 3: pre-process and FFT
+  {
+    const int sg = fft_sign(type, inv_first);
+    for (int w = threadIdx.x; w < L * n; w += kBlock) {
+      const int l = w / n, k = w - l * n;
+      cb[l * cstride + k] = dtt_pre<T>(type, inv_first, rb + l * rstride, n, k, tw);
+    }
+    __syncthreads();
+    fft_lines<T, EPT>(cb, cstride, L, a.ap, sg);
+  }
+  if (a.mode == PASS_FWD_GREEN_INV) {
+    // forward post-processing, Green operator M^-1, back into LDS
+    const double* cx = a.cosT + (c * 3 + 0) * a.maxN;
+    const double* cy = a.cosT + (c * 3 + 1) * a.maxN;
+    const double* cz = a.cosT + (c * 3 + 2) * a.maxN;
+    const double d = a.g.st[c][0], exy = a.g.st[c][1], exz = a.g.st[c][2], eyz = a.g.st[c][3];
+    for (int w = threadIdx.x; w < L * N; w += kBlock) {
+      const int l = w / N, m = w - l * N;
+      const long long lg = l0 + l;
+      T v = dtt_post<T>(type, 0, cb + l * cstride, n, m, tw);
+      if (lg < nlines) {
+        const int mx = (int)(lg % Nx), my = (int)(lg / Nx);
+        const double Cx = cx[mx], Cy = cy[my], Cz = cz[m];
+        // symbol of the Paux stencil: d + sum over the 4 face diagonals of each plane
+        const double M = d + 4.0 * (exy * Cx * Cy + exz * Cx * Cz + eyz * Cy * Cz);
+        v = (M > a.thr[c]) ? (T)((double)v / M) : T(0);
+      } else {
+        v = T(0);
+      }
+      rb[l * rstride + m] = v;
+    }
+    __syncthreads();
+    const int itype = type;
+    const int sg = fft_sign(itype, 1);
+    for (int w = threadIdx.x; w < L * n; w += kBlock) {
+      const int l = w / n, k = w - l * n;
+      cb[l * cstride + k] = dtt_pre<T>(itype, 1, rb + l * rstride, n, k, tw);
+    }
+    __syncthreads();
+    fft_lines<T, EPT>(cb, cstride, L, a.ap, sg);
+  }
+  // phase 4: post-process and write
+  const int inv_out = (a.mode != PASS_FWD);
+  {
+    const int total = L * N;
+    for (int w = threadIdx.x; w < total; w += kBlock) {
+      int l, m;
+      if (axis == 0) { l = w / N; m = w - l * N; } else { m = w / L; l = w - m * L; }
+      const long long lg = l0 + l;
+      if (lg >= nlines) continue;
+      const T v = dtt_post<T>(type, inv_out, cb + l * cstride, n, m, tw);
+      a.buf[cbase + off(lg) + (long long)m * stride] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// proj_U kernels and bookkeeping
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_weak(Geo g, T* u, WeakDev w, DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (r >= w.m) return;
+  const int c = w.comp[r];
+  double s = 0.0;
+  for (int q = 0; q < w.k; ++q) s += (double)u[c * g.Nn + w.nodes[r * w.k + q]];
+  const double corr = w.val[r] - s / w.k;
+  for (int q = 0; q < w.k; ++q) {
+    const long long idx = c * g.Nn + w.nodes[r * w.k + q];
+    u[idx] = (T)((double)u[idx] + corr);
+  }
+}
+
+// radial projection of the active contact nodes onto the sphere (proj_U of eq 28)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_contact(Geo g, T* u, ContactDev ct, DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (f >= ct.nface || !ct.C[f]) return;
+  int xyz[3];
+  xyz[ct.axis] = ct.side ? g.n[ct.axis] : 0;
+  xyz[ct.b1] = (int)(f % g.N[ct.b1]);
+  xyz[ct.b2] = (int)(f / g.N[ct.b1]);
+  const long long node = xyz[0] + (long long)g.N[0] * (xyz[1] + (long long)g.N[1] * xyz[2]);
+  double d[3], r2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    d[c] = xyz[c] + (double)u[c * g.Nn + node] - ct.center[c];
+    r2 += d[c] * d[c];
+  }
+  const double r = sqrt(r2);
+  for (int c = 0; c < 3; ++c) u[c * g.Nn + node] = (T)(ct.center[c] + ct.radius * d[c] / r - xyz[c]);
+}
+
+// initial active set C = {g < 0} from the current u (start of an increment)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_contact_init(Geo g, const T* u, ContactDev ct) {
+  const long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (f >= ct.nface) return;
+  int xyz[3];
+  xyz[ct.axis] = ct.side ? g.n[ct.axis] : 0;
+  xyz[ct.b1] = (int)(f % g.N[ct.b1]);
+  xyz[ct.b2] = (int)(f / g.N[ct.b1]);
+  const long long node = xyz[0] + (long long)g.N[0] * (xyz[1] + (long long)g.N[1] * xyz[2]);
+  double r2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double d = xyz[c] + (double)u[c * g.Nn + node] - ct.center[c];
+    r2 += d * d;
+  }
+  ct.C[f] = (sqrt(r2) - ct.radius < 0.0) ? 1 : 0;
+  ct.V[0][f] = 0;
+  ct.V[1][f] = 0;
+}
+
+// strong proj_U and the end-of-iteration counters
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_finish(Geo g, T* u, StrongDev s, DevState* st, int advance) {
+  if (st->done) return;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < s.m; e += (long long)gridDim.x * blockDim.x)
+    u[s.comp[e] * g.Nn + s.node[e]] = (T)s.val[e];
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    st->it += 1;
+    st->i_local += 1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_strong_scatter(Geo g, T* u, StrongDev s) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < s.m; e += (long long)gridDim.x * blockDim.x)
+    u[s.comp[e] * g.Nn + s.node[e]] = (T)s.val[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reactions(Geo g, Bufs<T> B, StrongDev s, double* out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= s.m) return;
+  T p[3];
+  int b;
+  node_p<T>(g, B, s.node[e], p, b);
+  out[e] = -(double)p[s.comp[e]] / (double)(1 << b);
+}
+
+// elementwise conversion / utility kernels
+template <typename A, typename Bt>
+__global__ __launch_bounds__(kBlock) void k_convert(const A* __restrict__ in, Bt* __restrict__ out, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = (Bt)in[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_amask(Geo g, T* u) {
+  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < g.Nn;
+       node += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(node % g.N[0]);
+    const long long r = node / g.N[0];
+    const int xyz[3] = {i, (int)(r % g.N[1]), (int)(r / g.N[1])};
+    for (int c = 0; c < 3; ++c)
+      if (is_antisym(g, c, xyz)) u[c * g.Nn + node] = T(0);
+  }
+}
+
+// stiffness check: finite values, mu >= 0, 3 lam + 2 mu >= 0; max lam, max mu
+__global__ __launch_bounds__(kBlock) void k_check_stiffness(const double* lam, const double* mu, long long nv,
+                                                            double* out /* per block: bad, maxl, maxm */) {
+  __shared__ double sh[3 * 64];
+  double bad = 0.0, ml = -INFINITY, mm = -INFINITY;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nv; e += (long long)gridDim.x * blockDim.x) {
+    const double l = lam[e], m = mu[e];
+    if (!isfinite(l) || !isfinite(m)) bad = fmax(bad, 2.0);
+    else if (m < 0.0 || 3.0 * l + 2.0 * m < 0.0) bad = fmax(bad, 1.0);
+    ml = fmax(ml, l);
+    mm = fmax(mm, m);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    bad = fmax(bad, __shfl_xor(bad, o, 64));
+    ml = fmax(ml, __shfl_xor(ml, o, 64));
+    mm = fmax(mm, __shfl_xor(mm, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wid] = bad;
+    sh[64 + wid] = ml;
+    sh[128 + wid] = mm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      sh[0] = fmax(sh[0], sh[w]);
+      sh[64] = fmax(sh[64], sh[64 + w]);
+      sh[128] = fmax(sh[128], sh[128 + w]);
+    }
+    out[blockIdx.x * 3 + 0] = sh[0];
+    out[blockIdx.x * 3 + 1] = sh[64];
+    out[blockIdx.x * 3 + 2] = sh[128];
+  }
+}
+
+// Anderson on the displacement (ACV_U): flags at the start of the iteration, then the
+// accelerated combination and the solution store after the residual store and LS.
+__global__ void k_flags_u(DevState* st) {
+  if (st->done) return;
+  const int i = st->i_local;
+  st->store_r = (i > 0);
+  st->accel = (i >= 4) && (i % st->period == 0);
+  st->accel_ok = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_combine_u(Bufs<T> B, long long n3, DevState* st) {
+  if (st->done) return;
+  const int slot = st->i_local & 3, ok = st->accel_ok;
+  double al[4];
+  for (int q = 0; q < 4; ++q) al[q] = ok ? st->alpha[q] : 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
+    T v = B.u[e];
+    if (ok) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += al[q] * ((double)B.S[q][e] + (double)B.R[q][e]);
+      v = (T)s;
+      B.u[e] = v;
+    }
+    B.S[slot][e] = v;
+  }
+}
+
+// Contact force along the face normal: -side_sign * sum over C of f_nc n_c[axis] (FP64).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_contact_force(Geo g, const T* u, ContactDev ct, double* out) {
+  __shared__ double sh[2 * 16];
+  double acc[2] = {0.0, 0.0};
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < ct.nface; f += (long long)gridDim.x * blockDim.x) {
+    if (!ct.C[f]) continue;
+    int xyz[3];
+    xyz[ct.axis] = ct.side ? g.n[ct.axis] : 0;
+    xyz[ct.b1] = (int)(f % g.N[ct.b1]);
+    xyz[ct.b2] = (int)(f / g.N[ct.b1]);
+    const long long node = xyz[0] + (long long)g.N[0] * (xyz[1] + (long long)g.N[1] * xyz[2]);
+    double d[3], r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      d[c] = xyz[c] + (double)u[c * g.Nn + node] - ct.center[c];
+      r2 += d[c] * d[c];
+    }
+    const double nca = -d[ct.axis] / sqrt(r2);
+    acc[0] += ct.fnc[f] * nca;
+    acc[1] += 1.0;
+  }
+  block_sum<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = acc[0];
+    out[2 * blockIdx.x + 1] = acc[1];
+  }
+}
+
+// Re-arm the iteration state for `iters` more iterations (fixed-count runs).
+__global__ void k_extend(DevState* st, int iters, double tol) {
+  st->done = 0;
+  st->status = ST_RUNNING;
+  st->max_iter = st->it + iters;
+  st->tol = tol;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline int grid_for(long long n, int cap) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (int)(b < cap ? b : cap);
+}
+
+template <typename T>
+void launch_residual(const Geo& g, const Bufs<T>& B, const ContactDev& ct, DevState* st, double* part, int nblk,
+                     int force, int write_p, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual<T>, dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+}
+
+template <typename T>
+void launch_weak(const Geo& g, const Bufs<T>& B, const WeakDev& w, DevState* st, int force, hipStream_t s) {
+  if (w.m == 0) return;
+  hipLaunchKernelGGL(k_weak<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, B, w, st, force);
+}
+
+void launch_control(DevState* st, const double* part, int nblk, const double* wpart, long long nweak,
+                    const ContactDev& ct, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, nweak, ct);
+}
+
+template <typename T>
+void launch_anderson(const Bufs<T>& B, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_anderson_r<T>, dim3(nblk), dim3(kBlock), 0, s, B, n3, st, gpart);
+  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kBlock), 0, s, st, gpart, nblk);
+}
+
+template <typename T>
+size_t dtt_smem(const AxisPlan& ap) {
+  return sizeof(cplx<T>) * (size_t)ap.L * (ap.n + 1) + sizeof(T) * (size_t)ap.L * (ap.N + 1);
+}
+
+template <typename T>
+void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s) {
+  const int Nx = a.g.N[0], Ny = a.g.N[1], Nz = a.g.N[2];
+  const long long nlines = a.axis == 0 ? (long long)Ny * Nz : a.axis == 1 ? (long long)Nx * Nz : (long long)Nx * Ny;
+  const long long nb = (nlines + a.ap.L - 1) / a.ap.L;
+  const size_t sm = dtt_smem<T>(a.ap);
+  if (ept <= 8)
+    hipLaunchKernelGGL((k_dtt<T, 8>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+  else
+    hipLaunchKernelGGL((k_dtt<T, 16>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+}
+
+template <typename T>
+void launch_proj(const Geo& g, T* u, const WeakDev& w, const ContactDev& ct, const StrongDev& sd, DevState* st,
+                 int advance, int force, hipStream_t s) {
+  if (w.m > 0) hipLaunchKernelGGL(k_proj_weak<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, u, w, st, force);
+  if (ct.on)
+    hipLaunchKernelGGL(k_proj_contact<T>, dim3(grid_for(ct.nface, 1 << 30)), dim3(kBlock), 0, s, g, u, ct, st, force);
+  if (force) {
+    if (sd.m > 0) hipLaunchKernelGGL(k_strong_scatter<T>, dim3(grid_for(sd.m, 1024)), dim3(kBlock), 0, s, g, u, sd);
+  } else {
+    hipLaunchKernelGGL(k_finish<T>, dim3(grid_for(sd.m, 1024)), dim3(kBlock), 0, s, g, u, sd, st, advance);
+  }
+}
+
+template <typename T>
+void launch_flags_combine(const Bufs<T>& B, long long n3, DevState* st, int which, hipStream_t s) {
+  if (which == 0) hipLaunchKernelGGL(k_flags_u, dim3(1), dim3(1), 0, s, st);
+  else hipLaunchKernelGGL(k_combine_u<T>, dim3(grid_for(n3, 2048)), dim3(kBlock), 0, s, B, n3, st);
+}
+
+template <typename T>
+void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double* out, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_contact_force<T>, dim3(nblk), dim3(kBlock), 0, s, g, u, ct, out);
+}
+
+template <typename T>
+void launch_contact_init(const Geo& g, const T* u, const ContactDev& ct, hipStream_t s) {
+  hipLaunchKernelGGL(k_contact_init<T>, dim3(grid_for(ct.nface, 1 << 30)), dim3(kBlock), 0, s, g, u, ct);
+}
+
+template <typename T>
+void launch_reactions(const Geo& g, const Bufs<T>& B, const StrongDev& sd, double* out, hipStream_t s) {
+  if (sd.m == 0) return;
+  hipLaunchKernelGGL(k_reactions<T>, dim3(grid_for(sd.m, 1 << 30)), dim3(kBlock), 0, s, g, B, sd, out);
+}
+
+template <typename A, typename Bt>
+void launch_convert(const A* in, Bt* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<A, Bt>), dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, in, out, n);
+}
+
+template <typename T>
+void launch_zero_amask(const Geo& g, T* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_amask<T>, dim3(grid_for(g.Nn, 8192)), dim3(kBlock), 0, s, g, u);
+}
+
+void launch_extend(DevState* st, int iters, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_extend, dim3(1), dim3(1), 0, s, st, iters, tol);
+}
+
+void launch_check_stiffness(const double* lam, const double* mu, long long nv, double* out, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_stiffness, dim3(nblk), dim3(kBlock), 0, s, lam, mu, nv, out);
+}
+
+#define FFTC_INST(T)                                                                                              \
+  template void launch_residual<T>(const Geo&, const Bufs<T>&, const ContactDev&, DevState*, double*, int, int,   \
+                                   int, hipStream_t);                                                                  \
+  template void launch_weak<T>(const Geo&, const Bufs<T>&, const WeakDev&, DevState*, int, hipStream_t);         \
+  template void launch_anderson<T>(const Bufs<T>&, long long, DevState*, double*, int, hipStream_t);             \
+  template void launch_dtt<T>(const DttArgs<T>&, int, hipStream_t);                                                \
+  template size_t dtt_smem<T>(const AxisPlan&);                                                                    \
+  template void launch_proj<T>(const Geo&, T*, const WeakDev&, const ContactDev&, const StrongDev&, DevState*,   \
+                               int, int, hipStream_t);                                                            \
+  template void launch_contact_init<T>(const Geo&, const T*, const ContactDev&, hipStream_t);                     \
+  template void launch_contact_force<T>(const Geo&, const T*, const ContactDev&, double*, int, hipStream_t);     \
+  template void launch_reactions<T>(const Geo&, const Bufs<T>&, const StrongDev&, double*, hipStream_t);         \
+  template void launch_zero_amask<T>(const Geo&, T*, hipStream_t);                                                 \
+  template void launch_flags_combine<T>(const Bufs<T>&, long long, DevState*, int, hipStream_t);
+
+FFTC_INST(double)
+FFTC_INST(float)
+template void launch_convert<double, double>(const double*, double*, long long, hipStream_t);
+template void launch_convert<double, float>(const double*, float*, long long, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, long long, hipStream_t);
+
+}  // namespace fftc

@@ -1,0 +1,38 @@
+// Host-callable launchers of the libfftc kernels (instantiated for float and double).
+#pragma once
+#include "fftc_internal.h"
+
+namespace fftc {
+
+template <typename T>
+void launch_residual(const Geo& g, const Bufs<T>& B, const ContactDev& ct, DevState* st, double* part, int nblk,
+                     int force, int write_p, hipStream_t s);
+template <typename T>
+void launch_weak(const Geo& g, const Bufs<T>& B, const WeakDev& w, DevState* st, int force, hipStream_t s);
+void launch_control(DevState* st, const double* part, int nblk, const double* wpart, long long nweak,
+                    const ContactDev& ct, hipStream_t s);
+template <typename T>
+void launch_anderson(const Bufs<T>& B, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
+template <typename T>
+void launch_flags_combine(const Bufs<T>& B, long long n3, DevState* st, int which, hipStream_t s);
+template <typename T>
+size_t dtt_smem(const AxisPlan& ap);
+template <typename T>
+void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s);
+template <typename T>
+void launch_proj(const Geo& g, T* u, const WeakDev& w, const ContactDev& ct, const StrongDev& sd, DevState* st,
+                 int advance, int force, hipStream_t s);
+template <typename T>
+void launch_contact_init(const Geo& g, const T* u, const ContactDev& ct, hipStream_t s);
+template <typename T>
+void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double* out, int nblk, hipStream_t s);
+template <typename T>
+void launch_reactions(const Geo& g, const Bufs<T>& B, const StrongDev& sd, double* out, hipStream_t s);
+template <typename A, typename B>
+void launch_convert(const A* in, B* out, long long n, hipStream_t s);
+template <typename T>
+void launch_zero_amask(const Geo& g, T* u, hipStream_t s);
+void launch_extend(DevState* st, int iters, double tol, hipStream_t s);
+void launch_check_stiffness(const double* lam, const double* mu, long long nv, double* out, int nblk, hipStream_t s);
+
+}  // namespace fftc

@@ -1,0 +1,151 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.solver import Solver as OSolver
+from oracle.contact import ContactSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2607_26082_amd as F
+    F.load()
+    return F
+
+
+def _case(seed, n, periodic_axis=None, weak=True):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    lam = rng.uniform(0.3, 3, (nz, ny, nx)); mu = rng.uniform(0.2, 2, (nz, ny, nx))
+    lam[0, 0, :2] = 0.0; mu[0, 0, :2] = 0.0
+    bc = rng.integers(0, 2, (3, 3, 2)).astype(np.int8)
+    if periodic_axis is not None:
+        bc[:, periodic_axis, :] = 2
+    strong = [W.Strong(np.array([[1, 1, 1], [2, 1, 1], [1, 2, 2]]), np.array([0, 1, 2], np.int8),
+                       np.array([0.01, -0.02, 0.03]))]
+    avg = []
+    if weak:
+        sup = np.stack(np.meshgrid([3, 4], [2, 3], [2, 3], indexing="ij"), -1).reshape(1, 8, 3)
+        avg = [W.Average(sup, np.array([1], np.int8), np.array([0.015]), set_id=1)]
+    return lam, mu, bc, strong, avg
+
+
+SHAPES = [((6, 5, 9), None), ((10, 12, 15), 1), ((16, 16, 16), None), ((24, 20, 18), 0), ((9, 8, 10), 2)]
+
+
+@pytest.mark.parametrize("idx", range(len(SHAPES)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_residual(idx, prec):
+    F = _lib()
+    n, per = SHAPES[idx]
+    print(f"[stage_residual] n={n} periodic={per} prec={prec}", flush=True)
+    lam, mu, bc, strong, avg = _case(10 + idx, n, per)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.3)
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=1.3, precision=prec)
+    rng = np.random.default_rng(idx)
+    u = rng.standard_normal(o.zeros().shape) * 1e-2
+    u[o.plan.amask] = 0.0
+    parts = o.iterate_parts(u)
+    p, pt, sums = g.stage_residual(u)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    scale = np.abs(parts["ptil"]).max()
+    assert np.abs(pt - parts["ptil"]).max() <= tol * scale
+    assert np.abs(p - parts["p"]).max() <= tol * np.abs(parts["p"]).max()
+    assert abs(sums[0] - parts["pnorm2"]) <= tol * parts["pnorm2"] * 10
+    assert abs(sums[1] - parts["sig2"]) <= tol * parts["sig2"] * 10
+
+
+@pytest.mark.parametrize("idx", range(len(SHAPES)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_green(idx, prec):
+    F = _lib()
+    n, per = SHAPES[idx]
+    print(f"[stage_green] n={n} periodic={per} prec={prec}", flush=True)
+    lam, mu, bc, strong, avg = _case(20 + idx, n, per, weak=False)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=0.7)
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=0.7, precision=prec)
+    rng = np.random.default_rng(100 + idx)
+    p = rng.standard_normal(o.zeros().shape)
+    p[o.plan.amask] = 0.0
+    ref = o.green.apply(p)
+    out = g.stage_green(p)
+    tol = 1e-12 if prec == "fp64" else 3e-5
+    assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_c1_fp64_trajectory():
+    F = _lib()
+    prob = W.c1_inclusion_patch()
+    print("[c1 fp64]", flush=True)
+    o = OSolver.from_problem(prob).solve(tol=prob.tol)
+    g = F.Solver.from_problem(prob, precision="fp64")
+    rc, rep = g.solve()
+    assert rc == 0 and rep.status == 0
+    assert rep.iterations == o["iterations"]
+    u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
+    _, _, tot = g.reactions()
+    assert np.abs(tot - o["totals"]).max() <= 1e-9 * np.abs(o["totals"]).max()
+
+
+def test_c1_fp32_solution():
+    F = _lib()
+    prob = W.c1_inclusion_patch()
+    print("[c1 fp32]", flush=True)
+    o = OSolver.from_problem(prob).solve(tol=1e-12)
+    g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6)
+    rc, rep = g.solve()
+    assert rc == 0 and rep.residual < 1e-6
+    u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-5 * np.linalg.norm(o["u"])
+
+
+@pytest.mark.parametrize("acv,period", [("P", 3), ("U", 2), ("NONE", 2)])
+def test_acceleration_variants_fp64(acv, period):
+    F = _lib()
+    n = (8, 8, 8)
+    lam, mu, bc, strong, avg = _case(7, n, None)
+    bc[:, 2, 0] = 1
+    print(f"[acv] {acv} {period}", flush=True)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=2.0).solve(tol=1e-9, acv=acv, period=period, max_iter=3000)
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=2.0, precision="fp64", tol=1e-9, acv=acv,
+                 period=period, max_iter=3000)
+    rc, rep = g.solve()
+    assert rc == 0
+    assert rep.iterations == o["iterations"]
+    u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_contact_increments(prec):
+    F = _lib()
+    n = (32, 32, 16); R = 12.0
+    print(f"[contact] {prec}", flush=True)
+    prob = W.c3_indentation(n=n, R=R)
+    cs = ContactSolver(n, prob.lam, prob.mu, prob.bc, face=5, radius=R, r0_factor=5.0)
+    sph = W.Sphere(np.array([16.0, 16.0, 16 + R]), R, 5)
+    g = F.Solver(n, prob.lam, prob.mu, prob.bc, sphere=sph, r0_factor=5.0, precision=prec,
+                 tol=1e-6 if prec == "fp32" else 1e-8)
+    u_o = None
+    for k in range(1, 4):
+        d = 0.004 * k * R
+        c = np.array([16.0, 16.0, 16 + R - d])
+        o = cs.solve_increment(u_o, c, tol=1e-8 if prec == "fp64" else 1e-11)
+        u_o = o["u"]
+        g.move_sphere(c)
+        rc, rep = g.solve(zero_start=(k == 1))
+        assert rc == 0
+        mask, fnc, gap = g.contact()
+        Cg = mask.reshape(-1).astype(bool)
+        assert np.array_equal(Cg, o["C"])
+        u = g.u.cpu().numpy()
+        tol = 1e-10 if prec == "fp64" else 1e-5
+        assert np.linalg.norm(u - o["u"]) <= tol * np.linalg.norm(o["u"])
+        if prec == "fp64":
+            assert rep.iterations == o["iterations"]
+        assert abs(rep.force_contact - o["force_contact"]) <= 1e-6 * o["force_contact"] + (0 if prec == "fp64" else 1e-4 * o["force_contact"])
