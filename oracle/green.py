@@ -54,11 +54,17 @@ def stencil(lam0, mu0):
 
 
 def symbol(st, th_x, th_y, th_z):
-    """M(theta) = sum_delta c_delta cos(theta . delta) on the grid th_z x th_y x th_x."""
+    """M(theta) = sum_delta c_delta cos(theta . delta) on the grid th_z x th_y x th_x.
+
+    The stencil rows sum to zero (rigid translations are in the null space of K0), so the
+    same value is evaluated as -2 sum_delta c_delta sin^2(theta . delta / 2), which avoids
+    the cancellation of the O(1) terms at low frequencies."""
     tz, ty, tx = np.meshgrid(th_z, th_y, th_x, indexing="ij")
     M = np.zeros(tz.shape)
     for (dx, dy, dz), cval in st.items():
-        M += cval * np.cos(dx * tx + dy * ty + dz * tz)
+        if (dx, dy, dz) == (0, 0, 0):
+            continue
+        M -= 2.0 * cval * np.sin(0.5 * (dx * tx + dy * ty + dz * tz)) ** 2
     return M
 
 

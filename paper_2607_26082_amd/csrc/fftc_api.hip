@@ -45,6 +45,10 @@ struct fftc_problem {
   hipStream_t stream = nullptr;
   int bound = 0, stiff_set = 0;
   void* fld[10];  // u, X, S0..3, R0..3
+  // residual-form (FP32) fields: delta, e, p0, p1, R0, R1, dR0..2, dY0..2, t; FP64 u
+  void* dfld[13] = {};
+  double* u64 = nullptr;
+  int delta_mode = 0;
   void* lam = nullptr;
   void* mu = nullptr;
   uint8_t* mask = nullptr;
@@ -63,6 +67,8 @@ struct fftc_problem {
   int b1 = 0, b2 = 1;
   AxisPlan ap[3];
   int ept = 8, nblk_res = 1, maxN = 1;
+  int dtt_nt[3] = {0, 0, 0};   // autotuned block size per axis pass
+  double tune_ms[3][2];
   Geo g;
   std::string err;
   DevState last{};
@@ -169,14 +175,14 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take((size_t)h->Nn);
-  off[q++] = L.take(sizeof(double) * kPartStride * 2048);
+  off[q++] = L.take(sizeof(double) * kPartStrideD * 2048);
   off[q++] = L.take(sizeof(double) * 10 * 2048);
   off[q++] = L.take(sizeof(DevState));
   const size_t mw = h->w_comp.size(), ms = h->s_comp.size();
   off[q++] = L.take(sizeof(double) * (mw + 1));
   off[q++] = L.take(sizeof(double) * (mw + 1));
   int maxN = std::max(h->N[0], std::max(h->N[1], h->N[2]));
-  off[q++] = L.take(sizeof(double) * 9 * maxN);
+  off[q++] = L.take(sizeof(double) * 18 * maxN);
   for (int J = 0; J < 3; ++J) off[q++] = L.take(2 * ts * 4 * (size_t)h->n[J]);
   off[q++] = L.take(8 * (ms + 1));
   off[q++] = L.take(ms + 1);
@@ -199,6 +205,9 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(8 * nface);
   off[q++] = L.take(8 * (ms + 1));
   off[q++] = L.take(sizeof(double) * 3 * 1024);
+  const int nd = h->precision == FFTC_FP32 ? 13 : 0;
+  for (int i = 0; i < nd; ++i) off[q++] = L.take(4 * 3 * (size_t)h->Nn);
+  if (nd) off[q++] = L.take(8 * 3 * (size_t)h->Nn);
   if (base) {
     q = 0;
     for (int i = 0; i < 10; ++i) h->fld[i] = base + off[q++];
@@ -225,6 +234,8 @@ size_t carve(fftc_problem* h, char* base) {
     h->gap = (double*)(base + off[q++]);
     h->sreact = (double*)(base + off[q++]);
     h->chk = (double*)(base + off[q++]);
+    for (int i = 0; i < nd; ++i) h->dfld[i] = base + off[q++];
+    if (nd) h->u64 = (double*)(base + off[q++]);
     h->nface = nface;
     h->maxN = maxN;
   }
@@ -239,6 +250,7 @@ void set_stencil(fftc_problem* h) {
     h->g.st[c][1] = (cj[2] - cj[0] - cj[1]) / 4.0;
     h->g.st[c][2] = (cj[1] - cj[0] - cj[2]) / 4.0;
     h->g.st[c][3] = (cj[0] - cj[1] - cj[2]) / 4.0;
+    for (int J = 0; J < 3; ++J) h->g.ac[c][J] = cj[J];
   }
 }
 
@@ -255,6 +267,26 @@ Bufs<T> bufs(fftc_problem* h) {
   B.mu = (const T*)h->mu;
   B.mask = h->mask;
   return B;
+}
+
+DeltaBufs<float> dbufs(fftc_problem* h) {
+  DeltaBufs<float> D;
+  D.u = h->u64;
+  D.delta = (float*)h->dfld[0];
+  D.e = (float*)h->dfld[1];
+  D.p[0] = (float*)h->dfld[2];
+  D.p[1] = (float*)h->dfld[3];
+  D.R[0] = (float*)h->dfld[4];
+  D.R[1] = (float*)h->dfld[5];
+  for (int q = 0; q < 3; ++q) {
+    D.dR[q] = (float*)h->dfld[6 + q];
+    D.dY[q] = (float*)h->dfld[9 + q];
+  }
+  D.t = (float*)h->dfld[12];
+  D.lam = (const float*)h->lam;
+  D.mu = (const float*)h->mu;
+  D.mask = h->mask;
+  return D;
 }
 
 ContactDev contact_dev(fftc_problem* h) {
@@ -302,11 +334,10 @@ DttArgs<T> dtt_args(fftc_problem* h, int axis, int mode, int force) {
   a.force = force;
   a.cosT = h->cosT;
   a.maxN = h->maxN;
-  for (int c = 0; c < 3; ++c) {
-    const double d = h->g.st[c][0];
-    const double e = fabs(h->g.st[c][1]) + fabs(h->g.st[c][2]) + fabs(h->g.st[c][3]);
-    a.thr[c] = 1e-12 * (d + 4.0 * e);
-  }
+  // the symbol vanishes only at theta = 0 and (pi, pi, pi) (exact zeros of the factored
+  // form); any positive value is at least ~ a theta_min^2, far above this threshold
+  for (int c = 0; c < 3; ++c) a.thr[c] = 1e-13 * std::max(h->g.ac[c][0], std::max(h->g.ac[c][1], h->g.ac[c][2]));
+  a.nt = h->dtt_nt[axis];
   return a;
 }
 
@@ -324,8 +355,61 @@ struct StageTimer {
   }
 };
 
+void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
+  DeltaBufs<float> D = dbufs(h);
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  const StrongDev sd = strong_dev(h);
+  const long long n3 = 3 * h->Nn;
+  hipStream_t s = h->stream;
+  if (tm) tm->mark(s);
+  launch_delta_iteration_front<float>(h->g, D, ct, w, h->st, h->part, h->wpart, h->nblk_res, s);
+  if (tm) tm->mark(s);
+  if (tm) tm->mark(s);
+  if (h->cfg.acv == FFTC_ACV_P) launch_delta_anderson<float>(D, n3, h->st, h->gpart, h->nblk_res, s);
+  if (tm) tm->mark(s);
+  DttArgs<float> a = dtt_args<float>(h, 0, PASS_FWD, 0);
+  a.src = SRC_DELTA;
+  a.dp2[0] = D.p[0];
+  a.dp2[1] = D.p[1];
+  for (int q = 0; q < 3; ++q) a.dY[q] = D.dY[q];
+  a.de = D.e;
+  a.buf = D.t;
+  launch_dtt<float>(a, h->ept, s);
+  if (tm) tm->mark(s);
+  a = dtt_args<float>(h, 1, PASS_FWD, 0);
+  a.buf = D.t;
+  a.in = D.t;
+  launch_dtt<float>(a, h->ept, s);
+  if (tm) tm->mark(s);
+  a = dtt_args<float>(h, 2, PASS_FWD_GREEN_INV, 0);
+  a.buf = D.t;
+  a.in = D.t;
+  launch_dtt<float>(a, h->ept, s);
+  if (tm) tm->mark(s);
+  a = dtt_args<float>(h, 1, PASS_INV, 0);
+  a.buf = D.t;
+  a.in = D.t;
+  launch_dtt<float>(a, h->ept, s);
+  if (tm) tm->mark(s);
+  a = dtt_args<float>(h, 0, PASS_INV, 0);
+  a.buf = D.t;
+  a.in = D.t;
+  a.dst = DST_UPDATE;
+  a.u64 = D.u;
+  a.delta = D.delta;
+  launch_dtt<float>(a, h->ept, s);
+  if (tm) tm->mark(s);
+  launch_delta_proj<float>(h->g, D, sd, w, ct, h->st, 0, 1, s);
+  if (tm) tm->mark(s);
+}
+
 template <typename T>
 void enqueue_iteration(fftc_problem* h, StageTimer* tm = nullptr) {
+  if (h->delta_mode) {
+    enqueue_delta_iteration(h, tm);
+    return;
+  }
   Bufs<T> B = bufs<T>(h);
   const ContactDev ct = contact_dev(h);
   const WeakDev w = weak_dev(h);
@@ -343,7 +427,7 @@ void enqueue_iteration(fftc_problem* h, StageTimer* tm = nullptr) {
   launch_residual<T>(h->g, B, ct, h->st, h->part, h->nblk_res, 0, 0, s);
   if (tm) tm->mark(s);
   launch_weak<T>(h->g, B, w, h->st, 0, s);
-  launch_control(h->st, h->part, h->nblk_res, h->wpart, w.m, ct, s);
+  launch_control(h->st, h->part, h->nblk_res, h->wpart, w.m, ct, kPartStride, s);
   if (tm) tm->mark(s);
   if (h->cfg.acv == FFTC_ACV_P) launch_anderson<T>(B, n3, h->st, h->gpart, h->nblk_res, s);
   if (tm) tm->mark(s);
@@ -410,8 +494,96 @@ int profile_t(fftc_problem* h, int iters, double* ms, int nst) {
   return FFTC_OK;
 }
 
+int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, fftc_report* rep);
+
+int solve_delta(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
+  DeltaBufs<float> D = dbufs(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(D.u, 0, 8 * n3, s));
+  else HIPCHK(h, hipMemcpyAsync(D.u, u_dev, 8 * n3, hipMemcpyDeviceToDevice, s));
+  launch_zero_amask<double>(h->g, D.u, s);
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  const StrongDev sd = strong_dev(h);
+  if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
+  launch_delta_proj<float>(h->g, D, sd, w, ct, h->st, 1, 0, s);
+  for (int q = 0; q < 12; ++q) HIPCHK(h, hipMemsetAsync(h->dfld[q], 0, 4 * n3, s));
+  DevState hs{};
+  hs.tol = h->cfg.tol;
+  hs.gate = h->cfg.update_gate;
+  hs.max_iter = h->cfg.max_iter;
+  hs.period = h->cfg.period;
+  hs.acv = h->cfg.acv;
+  hs.contact = h->has_sphere;
+  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  int chunk = 4;
+  DevState out{};
+  for (;;) {
+    for (int t = 0; t < chunk; ++t) enqueue_delta_iteration(h, nullptr);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(&out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (out.done) break;
+    chunk = std::min(64, chunk * 2);
+  }
+  h->last = out;
+  launch_reactions_d<float>(h->g, D, sd, h->sreact, s);
+  if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
+  h->react_strong.assign(h->s_comp.size(), 0.0);
+  h->react_weak.assign(h->w_comp.size(), 0.0);
+  if (!h->react_strong.empty())
+    HIPCHK(h, hipMemcpyAsync(h->react_strong.data(), h->sreact, 8 * h->react_strong.size(), hipMemcpyDeviceToHost, s));
+  if (!h->react_weak.empty())
+    HIPCHK(h, hipMemcpyAsync(h->react_weak.data(), h->wreact, 8 * h->react_weak.size(), hipMemcpyDeviceToHost, s));
+  double force_c = 0.0;
+  int nC = 0;
+  std::vector<double> cf(2 * 64, 0.0);
+  if (ct.on) {
+    launch_contact_force<double>(h->g, D.u, ct, h->chk, 64, s);
+    HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (ct.on) {
+    double fs = 0.0, cnt = 0.0;
+    for (int b = 0; b < 64; ++b) {
+      fs += cf[2 * b];
+      cnt += cf[2 * b + 1];
+    }
+    force_c = -((h->face % 2) ? 1.0 : -1.0) * fs;
+    nC = (int)cnt;
+  }
+  return finish_report(h, out, force_c, nC, rep);
+}
+
+int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, fftc_report* rep) {
+  const int status = out.status == ST_CONVERGED ? FFTC_OK : (out.status == ST_NAN ? FFTC_E_NAN : FFTC_E_NOCONV);
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    rep->status = status;
+    rep->iterations = out.it;
+    rep->residual = out.residual;
+    rep->contact_updates = out.updates;
+    rep->anderson_restarts = out.restarts;
+    for (int q = 0; q < 6; ++q) rep->mean_stress[q] = out.ms[q] / (double)h->Nv;
+    if (h->has_sphere) {
+      const int a = h->face / 2;
+      double A0 = 1.0;
+      for (int J = 0; J < 3; ++J)
+        if (J != a) A0 *= h->n[J];
+      rep->force_mean_stress = -A0 * rep->mean_stress[a];
+      rep->force_contact = force_c;
+      rep->contact_nodes = nC;
+    }
+  }
+  if (out.status == ST_NAN) return fail(h, FFTC_E_NAN, "non-finite iterate");
+  if (out.status != ST_CONVERGED) return fail(h, FFTC_E_NOCONV, "maximum number of iterations reached");
+  return FFTC_OK;
+}
+
 template <typename T>
 int solve_t(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
+  if (h->delta_mode) return solve_delta(h, u_dev, zero_start, rep);
   Bufs<T> B = bufs<T>(h);
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
@@ -758,6 +930,24 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
   g.Nn = h->Nn;
   g.Nv = h->Nv;
   g.aface = h->aface;
+  // singular modes of each component: theta = 0 needs DCT1 or DFT on all axes; theta = pi
+  // additionally needs an even length on DFT axes
+  for (int c = 0; c < 3; ++c) {
+    int zero = 1, pi = 1;
+    double sc = 1.0;
+    for (int J = 0; J < 3; ++J) {
+      const int ty = h->type[c][J];
+      if (ty == T_DCT1) sc /= 2.0 * h->n[J];
+      else if (ty == T_DFT) {
+        sc /= h->n[J];
+        if (h->n[J] % 2) pi = 0;
+      } else {
+        zero = pi = 0;
+      }
+    }
+    g.sing[c] = zero ? (1 | (pi ? 2 : 0)) : 0;
+    g.sing_scale[c] = sc;
+  }
   // axis plans: twiddles e^{-2 pi i t/4n}, lines per block
   for (int J = 0; J < 3; ++J) {
     AxisPlan& ap = h->ap[J];
@@ -784,10 +974,19 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     while (ap.L > 1 && ap.L * ((n + 1) * cs + (ap.N + 1) * rs) > 65536) ap.L /= 2;
   }
   // symbol tables cos(theta) per (comp, axis)
-  std::vector<double> cosT(9 * (size_t)h->maxN, 1.0);
+  std::vector<double> cosT(18 * (size_t)h->maxN, 0.0);
   for (int c = 0; c < 3; ++c)
     for (int J = 0; J < 3; ++J)
-      for (int idx = 0; idx < h->N[J]; ++idx) cosT[(c * 3 + J) * h->maxN + idx] = cos(theta_of(h->type[c][J], h->n[J], idx));
+      for (int idx = 0; idx < h->N[J]; ++idx) {
+        const int ty = h->type[c][J], nJ = h->n[J];
+        // theta = pi exactly at the last DCT1/DST1 index and at n/2 of a DFT axis
+        const bool at_pi = ((ty == T_DCT1 || ty == T_DST1) && idx == nJ) ||
+                           (ty == T_DFT && 2 * std::min(idx, nJ - idx) == nJ);
+        const double half = 0.5 * theta_of(ty, nJ, idx);
+        const double sn = sin(half), cs = cos(half);
+        cosT[((c * 3 + J) * 2 + 0) * h->maxN + idx] = at_pi ? 1.0 : sn * sn;
+        cosT[((c * 3 + J) * 2 + 1) * h->maxN + idx] = at_pi ? 0.0 : cs * cs;
+      }
   HIPCHK(h, hipMemcpyAsync(h->cosT, cosT.data(), 8 * cosT.size(), hipMemcpyHostToDevice, s));
   // node mask
   std::vector<uint8_t> mask(h->Nn, 0);
@@ -815,6 +1014,36 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_wval, h->w_val.data(), 8 * mw, hipMemcpyHostToDevice, s));
   }
   h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
+  // autotune the block size of each axis pass: time both variants on the bound buffers
+  {
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    const int cand[2] = {h->precision == FFTC_FP64 ? 128 : 256, h->precision == FFTC_FP64 ? 256 : 512};
+    for (int J = 0; J < 3; ++J) {
+      float best = 1e30f;
+      for (int v = 0; v < 2; ++v) {
+        h->dtt_nt[J] = cand[v];
+        const int mode = J == 2 ? PASS_FWD_GREEN_INV : PASS_FWD;
+        float tot = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HIPCHK(h, hipEventRecord(e0, s));
+          if (h->precision == FFTC_FP64) launch_dtt<double>(dtt_args<double>(h, J, mode, 1), h->ept, s);
+          else launch_dtt<float>(dtt_args<float>(h, J, mode, 1), h->ept, s);
+          HIPCHK(h, hipEventRecord(e1, s));
+          HIPCHK(h, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) tot += ms;
+        }
+        h->tune_ms[J][v] = tot / 2;
+        if (tot < best) best = tot;
+      }
+      h->dtt_nt[J] = (h->tune_ms[J][0] <= h->tune_ms[J][1]) ? cand[0] : cand[1];
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
   if (h->nblk_res < 1) h->nblk_res = 1;
   for (int q = 0; q < 10; ++q)
     HIPCHK(h, hipMemsetAsync(h->fld[q], 0, (h->precision == FFTC_FP64 ? 8 : 4) * 3 * (size_t)h->Nn, s));
@@ -863,6 +1092,8 @@ int fftc_set_stiffness(fftc_h h, const double* lam, const double* mu) {
 int fftc_solve(fftc_h h, double* u_dev, int32_t zero_start, fftc_report* rep) {
   if (!h) return FFTC_E_ARG;
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set before solving");
+  // FP32: residual-form iteration (FP64 displacement), except for ACV_U
+  h->delta_mode = (h->precision == FFTC_FP32 && h->cfg.acv != FFTC_ACV_U) ? 1 : 0;
   return h->precision == FFTC_FP64 ? solve_t<double>(h, u_dev, zero_start, rep)
                                    : solve_t<float>(h, u_dev, zero_start, rep);
 }

@@ -8,11 +8,13 @@ namespace fftc {
 
 enum DttType { T_DCT1 = 0, T_DCT3 = 1, T_DST1 = 2, T_DST3 = 3, T_DFT = 4 };
 enum PassMode { PASS_FWD = 0, PASS_INV = 1, PASS_FWD_GREEN_INV = 2 };
-enum SrcMode { SRC_BUF = 0, SRC_ANDERSON = 1 };
+enum SrcMode { SRC_BUF = 0, SRC_ANDERSON = 1, SRC_DELTA = 2 };
+enum DstMode { DST_BUF = 0, DST_UPDATE = 1 };
 
 constexpr int kMaxRadices = 16;
 constexpr int kBlock = 256;          // threads per block of every streaming kernel
 constexpr int kPartStride = 8;       // doubles per block partial of the residual pass
+constexpr int kPartStrideD = 14;     // residual-form pass: + 6 singular-mode sums of u
 constexpr int kMaxSets = 64;
 
 // node mask bits
@@ -29,6 +31,11 @@ struct Geo {
   int aface;           // bit (c*6 + J*2 + f): component c antisymmetric on face (J, f)
   // Paux reference stencil per component: diagonal, xy-, xz-, yz-plane face-diagonal coefficients
   double st[3][4];
+  // axis coefficients of the Paux medium per component: a[c][J] = 2 mu0 + lam0 delta_cJ
+  double ac[3][3];
+  // singular modes (symbol zero) per component: bit 0 theta = 0, bit 1 theta = (pi, pi, pi)
+  int sing[3];
+  double sing_scale[3];   // inverse-transform factor of one singular coefficient (prod 1/2n or 1/n)
 };
 
 // Device-resident iteration state (one per handle, in the workspace).
@@ -43,6 +50,8 @@ struct DevState {
   double ms[6];
   double gram[16];
   double alpha[4];
+  double sing[6];     // singular-mode coefficients of u (comp, {theta = 0, theta = pi})
+  double gamma[3];    // difference-form Anderson coefficients
 };
 
 enum StatusCode { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
@@ -110,10 +119,35 @@ struct DttArgs {
   DevState* st;
   int force;
   // Green (z pass)
-  const double* cosT;          // [3 comps][3 axes][maxN]
+  const double* cosT;          // [3 comps][3 axes][2][maxN]: sin^2(theta/2), cos^2(theta/2)
   int maxN;
   int inv_types[3];
   double thr[3];
+  int generic;                 // force the runtime-length kernel
+  int nt;                      // threads per block of the compile-time-length kernel
+  // residual-form (FP32) iteration
+  int dst;                     // DST_BUF or DST_UPDATE (x inverse pass: delta and FP64 u update)
+  const T* dp2[2];             // p ping-pong buffers (SRC_DELTA, selected by iteration parity)
+  const T* dY[3];              // Y-difference ring (SRC_DELTA)
+  T* de;                       // Green input e written by the x forward pass (SRC_DELTA)
+  double* u64;                 // FP64 displacement (DST_UPDATE)
+  T* delta;                    // displacement increment (DST_UPDATE)
+};
+
+// Fields of the residual-form iteration
+template <typename T>
+struct DeltaBufs {
+  double* u;                 // displacement (FP64)
+  T* delta;                  // u_i - u_{i-1}
+  T* e;                      // Green input of the last iteration
+  T* p[2];                   // residual after proj_P (ping-pong by iteration parity)
+  T* R[2];                   // R_i = p_i + K0 delta_i - e_{i-1} (ping-pong)
+  T* dR[3];                  // R differences (ring of 3)
+  T* dY[3];                  // Y differences (ring of 3)
+  T* t;                      // transform buffer
+  const T* lam;
+  const T* mu;
+  const uint8_t* mask;
 };
 
 }  // namespace fftc

@@ -12,6 +12,7 @@
 //   k_proj_*     proj_U: average relations (eq 11), contact radial projection, strong DOFs
 #include "fftc_internal.h"
 #include "fftc_launch.h"
+#include "fftc_dtt.h"
 
 #include <math.h>
 
@@ -20,21 +21,6 @@ namespace fftc {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-template <typename T>
-struct cplx {
-  T re, im;
-};
-template <typename T>
-__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename T>
-__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.re, -a.im}; }
-template <typename T>
-__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename T>
-__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -295,22 +281,24 @@ __global__ __launch_bounds__(kBlock) void k_weak(Geo g, Bufs<T> B, WeakDev w, De
 // Control: equilibrium test, contact update, Anderson flags (one block)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* __restrict__ part, int nblk,
-                                                    const double* __restrict__ wpart, long long nweak, ContactDev ct) {
-  __shared__ double sh[kPartStride * 16];
+                                                    const double* __restrict__ wpart, long long nweak, ContactDev ct,
+                                                    int pstride) {
+  __shared__ double sh[kPartStrideD * 16];
   __shared__ int flags[4];
   if (st->done) return;
-  double acc[kPartStride];
+  double acc[kPartStrideD];
 #pragma unroll
-  for (int q = 0; q < kPartStride; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-    for (int q = 0; q < kPartStride; ++q) acc[q] += part[b * kPartStride + q];
+    for (int q = 0; q < pstride; ++q) acc[q] += part[b * pstride + q];
   for (long long r = threadIdx.x; r < nweak; r += blockDim.x) acc[0] += wpart[r];
-  block_sum<kPartStride>(acc, sh);
+  block_sum<kPartStrideD>(acc, sh);
   if (threadIdx.x == 0) {
     st->pnorm2 = acc[0];
     st->snorm2 = acc[1];
     for (int q = 0; q < 6; ++q) st->ms[q] = acc[2 + q];
+    if (pstride > kPartStride)
+      for (int q = 0; q < 6; ++q) st->sing[q] = acc[8 + q];
     flags[0] = flags[1] = 0;
   }
   __syncthreads();
@@ -607,6 +595,30 @@ __device__ __forceinline__ int fft_sign(int type, int inv) {
   return (type == T_DFT) ? +1 : -1;
 }
 
+// Symbol of the Paux stencil for component c from per-axis s = sin^2(theta/2),
+// q = cos^2(theta/2): M = 4 sum_J a_J (s_J q_K q_L + q_J s_K s_L) -- the factored form of
+// d + 4 (e_xy Cx Cy + e_xz Cx Cz + e_yz Cy Cz), exact at theta = 0 and (pi, pi, pi).
+__device__ __forceinline__ double paux_symbol(const double a[3], double sx, double qx, double sy, double qy,
+                                              double sz, double qz) {
+  return 4.0 * (a[0] * (sx * qy * qz + qx * sy * sz) + a[1] * (sy * qx * qz + qy * sx * sz) +
+                a[2] * (sz * qx * qy + qz * sx * sy));
+}
+
+// Residual-form update in the last inverse pass: delta = K0^+ e - (I - Pi) u, u += delta,
+// at node (i, j, k) of component c.
+template <typename T>
+__device__ __forceinline__ void dtt_update(const DttArgs<T>& a, int c, int i, int j, int k, long long addr, T v) {
+  double d = (double)v;
+  const int sg = a.g.sing[c];
+  if (sg) {
+    const double s0 = a.st->sing[2 * c], s1 = a.st->sing[2 * c + 1];
+    const int parity = (i + j + k) & 1;
+    d -= a.g.sing_scale[c] * (s0 + ((sg & 2) ? (parity ? -s1 : s1) : 0.0));
+  }
+  a.u64[addr] += d;
+  a.delta[addr] = (T)d;
+}
+
 // Pre-processing: complex input z_k (k < n) of the length-n FFT from the real line x.
 template <typename T>
 __device__ __forceinline__ cplx<T> dtt_pre(int type, int inv, const T* x, int n, int k, const cplx<T>* tw) {
@@ -736,6 +748,12 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
             v = a.B.X[addr];
           }
           if (a.store_s) a.B.S[slot][addr] = v;
+        } else if (a.src == SRC_DELTA) {
+          v = a.dp2[a.st->it & 1][addr];
+          if (a.st->accel_ok)
+            v = v - ((T)a.st->gamma[0] * a.dY[0][addr] + (T)a.st->gamma[1] * a.dY[1][addr] +
+                     (T)a.st->gamma[2] * a.dY[2][addr]);
+          a.de[addr] = v;
         } else {
           v = a.in[addr];
         }
@@ -756,19 +774,19 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
   }
   if (a.mode == PASS_FWD_GREEN_INV) {
     // forward post-processing, Green operator M^-1, back into LDS
-    const double* cx = a.cosT + (c * 3 + 0) * a.maxN;
-    const double* cy = a.cosT + (c * 3 + 1) * a.maxN;
-    const double* cz = a.cosT + (c * 3 + 2) * a.maxN;
-    const double d = a.g.st[c][0], exy = a.g.st[c][1], exz = a.g.st[c][2], eyz = a.g.st[c][3];
+    const double* sxT = a.cosT + ((c * 3 + 0) * 2 + 0) * a.maxN;
+    const double* qxT = a.cosT + ((c * 3 + 0) * 2 + 1) * a.maxN;
+    const double* syT = a.cosT + ((c * 3 + 1) * 2 + 0) * a.maxN;
+    const double* qyT = a.cosT + ((c * 3 + 1) * 2 + 1) * a.maxN;
+    const double* szT = a.cosT + ((c * 3 + 2) * 2 + 0) * a.maxN;
+    const double* qzT = a.cosT + ((c * 3 + 2) * 2 + 1) * a.maxN;
     for (int w = threadIdx.x; w < L * N; w += kBlock) {
       const int l = w / N, m = w - l * N;
       const long long lg = l0 + l;
       T v = dtt_post<T>(type, 0, cb + l * cstride, n, m, tw);
       if (lg < nlines) {
         const int mx = (int)(lg % Nx), my = (int)(lg / Nx);
-        const double Cx = cx[mx], Cy = cy[my], Cz = cz[m];
-        // symbol of the Paux stencil: d + sum over the 4 face diagonals of each plane
-        const double M = d + 4.0 * (exy * Cx * Cy + exz * Cx * Cz + eyz * Cy * Cz);
+        const double M = paux_symbol(a.g.ac[c], sxT[mx], qxT[mx], syT[my], qyT[my], szT[m], qzT[m]);
         v = (M > a.thr[c]) ? (T)((double)v / M) : T(0);
       } else {
         v = T(0);
@@ -795,7 +813,192 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
       const long long lg = l0 + l;
       if (lg >= nlines) continue;
       const T v = dtt_post<T>(type, inv_out, cb + l * cstride, n, m, tw);
-      a.buf[cbase + off(lg) + (long long)m * stride] = v;
+      const long long addr = cbase + off(lg) + (long long)m * stride;
+      if (a.dst == DST_UPDATE) {
+        int xi, yj, zk;
+        if (axis == 0) { xi = m; yj = (int)(lg % Ny); zk = (int)(lg / Ny); }
+        else if (axis == 1) { xi = (int)(lg % Nx); yj = m; zk = (int)(lg / Nx); }
+        else { xi = (int)(lg % Nx); yj = (int)(lg / Nx); zk = m; }
+        dtt_update<T>(a, c, xi, yj, zk, addr, v);
+      } else {
+        a.buf[addr] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DTT pass with a compile-time length (non-periodic axes, n in {16,32,48,64,96,128,256})
+// ---------------------------------------------------------------------------
+template <typename T, int NF, int NTH>
+__global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
+  using S = DttShape<NF, NTH>;
+  constexpr int LB = S::LB, NN = S::NN, CS = S::CS, RS = S::RS, NT = S::NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (!a.force && a.st->done) return;
+  const int c = blockIdx.z;
+  const int axis = a.axis;
+  const int Nx = a.g.N[0], Ny = a.g.N[1];
+  long long base;
+  int nl, lstride, estride;
+  if (axis == 0) {
+    const int y0 = blockIdx.x * LB;
+    nl = Ny - y0;
+    base = ((long long)blockIdx.y * Ny + y0) * Nx;
+    lstride = Nx;
+    estride = 1;
+  } else if (axis == 1) {
+    const int x0 = blockIdx.x * LB;
+    nl = Nx - x0;
+    base = (long long)blockIdx.y * Nx * Ny + x0;
+    lstride = 1;
+    estride = Nx;
+  } else {
+    const int x0 = blockIdx.x * LB;
+    nl = Nx - x0;
+    base = (long long)blockIdx.y * Nx + x0;
+    lstride = 1;
+    estride = Nx * Ny;
+  }
+  base += (long long)c * a.g.Nn;
+  T* rb = (T*)smem;
+  cplx<T>* cb = (cplx<T>*)smem;
+  const cplx<T>* tw = (const cplx<T>*)a.ap.tw;
+  const int type = a.types[c];
+  const int tid = threadIdx.x;
+  // phase 1: gather the real lines (each node once; x lines element-fastest, y/z lines
+  // line-fastest).  All loads of a thread are issued before the LDS stores so that many
+  // requests are in flight per wave.
+  {
+    constexpr int NO = (LB * NN + NT - 1) / NT;
+    T vals[NO];
+    if (a.src == SRC_ANDERSON) {
+      const int slot = a.st->i_local & 3;
+      const int acc_ok = a.st->accel_ok;
+      double al[4] = {0, 0, 0, 0};
+      if (acc_ok)
+        for (int q = 0; q < 4; ++q) al[q] = a.st->alpha[q];
+#pragma unroll 2
+      for (int i = 0; i < NO; ++i) {
+        const int w = tid + i * NT;
+        int l, m;
+        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+        T v = T(0);
+        if (w < LB * NN && l < nl) {
+          const long long addr = base + (long long)(l * lstride + m * estride);
+          if (acc_ok) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sacc += al[q] * ((double)a.B.S[q][addr] + (double)a.B.R[q][addr]);
+            v = (T)sacc;
+          } else {
+            v = a.B.X[addr];
+          }
+          if (a.store_s) a.B.S[slot][addr] = v;
+        }
+        vals[i] = v;
+      }
+    } else if (a.src == SRC_DELTA) {
+      const T* pcur = a.dp2[a.st->it & 1];
+      const int acc_ok = a.st->accel_ok;
+      const T g0 = acc_ok ? (T)a.st->gamma[0] : T(0), g1 = acc_ok ? (T)a.st->gamma[1] : T(0),
+              g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
+#pragma unroll 4
+      for (int i = 0; i < NO; ++i) {
+        const int w = tid + i * NT;
+        int l, m;
+        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+        T v = T(0);
+        if (w < LB * NN && l < nl) {
+          const long long addr = base + (long long)(l * lstride + m * estride);
+          v = pcur[addr];
+          if (acc_ok) v = v - (g0 * a.dY[0][addr] + g1 * a.dY[1][addr] + g2 * a.dY[2][addr]);
+          a.de[addr] = v;
+        }
+        vals[i] = v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NO; ++i) {
+        const int w = tid + i * NT;
+        int l, m;
+        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+        vals[i] = (w < LB * NN && l < nl) ? a.in[base + (long long)(l * lstride + m * estride)] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      const int w = tid + i * NT;
+      if (w < LB * NN) {
+        int l, m;
+        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+        rb[l * RS + m] = vals[i];
+      }
+    }
+  }
+  __syncthreads();
+  const int inv_first = (a.mode == PASS_INV);
+  {
+    auto ld = [&](int l, int k) { return pre_ct<T, NF>(type, inv_first, rb + l * RS, k, tw); };
+    if (fft_sign(type, inv_first) < 0) fft_ct<T, NF, -1, NT>(cb, CS, tw, ld);
+    else fft_ct<T, NF, +1, NT>(cb, CS, tw, ld);
+  }
+  if (a.mode == PASS_FWD_GREEN_INV) {
+    constexpr int NO = (LB * NN + NT - 1) / NT;
+    T vals[NO];
+    const double* sxT = a.cosT + ((c * 3 + 0) * 2 + 0) * a.maxN;
+    const double* qxT = a.cosT + ((c * 3 + 0) * 2 + 1) * a.maxN;
+    const double* syT = a.cosT + ((c * 3 + 1) * 2 + 0) * a.maxN;
+    const double* qyT = a.cosT + ((c * 3 + 1) * 2 + 1) * a.maxN;
+    const double* szT = a.cosT + ((c * 3 + 2) * 2 + 0) * a.maxN;
+    const double* qzT = a.cosT + ((c * 3 + 2) * 2 + 1) * a.maxN;
+    const double sy = syT[blockIdx.y], qy = qyT[blockIdx.y];
+    const int x0 = blockIdx.x * LB;
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      const int w = tid + i * NT;
+      T v = T(0);
+      if (w < LB * NN) {
+        const int l = w / NN, m = w - l * NN;
+        if (l < nl) {
+          v = post_ct<T, NF>(type, 0, cb + l * CS, m, tw);
+          const double M = paux_symbol(a.g.ac[c], sxT[x0 + l], qxT[x0 + l], sy, qy, szT[m], qzT[m]);
+          v = (M > a.thr[c]) ? (T)((double)v / M) : T(0);
+        }
+      }
+      vals[i] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      const int w = tid + i * NT;
+      if (w < LB * NN) {
+        const int l = w / NN, m = w - l * NN;
+        rb[l * RS + m] = vals[i];
+      }
+    }
+    __syncthreads();
+    auto ld = [&](int l, int k) { return pre_ct<T, NF>(type, 1, rb + l * RS, k, tw); };
+    if (fft_sign(type, 1) < 0) fft_ct<T, NF, -1, NT>(cb, CS, tw, ld);
+    else fft_ct<T, NF, +1, NT>(cb, CS, tw, ld);
+  }
+  // phase 4: post-process and scatter
+  const int inv_out = (a.mode != PASS_FWD);
+#pragma unroll 4
+  for (int w = tid; w < LB * NN; w += NT) {
+    int l, m;
+    if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+    if (l >= nl) continue;
+    const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
+    const long long addr = base + (long long)(l * lstride + m * estride);
+    if (a.dst == DST_UPDATE) {
+      int xi, yj, zk;
+      if (axis == 0) { xi = m; yj = blockIdx.x * LB + l; zk = blockIdx.y; }
+      else if (axis == 1) { xi = blockIdx.x * LB + l; yj = m; zk = blockIdx.y; }
+      else { xi = blockIdx.x * LB + l; yj = blockIdx.y; zk = m; }
+      dtt_update<T>(a, c, xi, yj, zk, addr, v);
+    } else {
+      a.buf[addr] = v;
     }
   }
 }
@@ -1006,6 +1209,404 @@ __global__ void k_extend(DevState* st, int iters, double tol) {
   st->tol = tol;
 }
 
+// ===========================================================================
+// Residual-form iteration (FP32 fields, FP64 displacement).  The same fixed point as
+// above with ACV_P, rearranged exactly: with y_i = p_i + K0 u_i the Green input of the
+// paper's iteration, e_i = x_i - K0 u_i is residual-sized, u_{i+1} = Pi u_i + K0^+ e_i,
+// and Anderson runs in difference form on
+//   R_i = p_i + K0 delta_i - e_{i-1},  dR = R_i - R_{i-1},  dY = p_i - p_{i-1} + K0 delta_i,
+//   e_i = p_i - sum_j gamma_j dY_j,  gamma = argmin |R_i - sum_j gamma_j dR_j|.
+// Only residual-sized quantities pass through FP32 transforms.
+// ===========================================================================
+
+// K0 f at a node for the three components (Paux stencil, mirrored neighbours)
+template <typename T>
+__device__ __forceinline__ void stencil_k0(const Geo& g, const T* __restrict__ f, int i, int j, int k, T out[3]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int xs[3] = {mirror_coord(g, i - 1, 0), i, mirror_coord(g, i + 1, 0)};
+  const int ys[3] = {mirror_coord(g, j - 1, 1), j, mirror_coord(g, j + 1, 1)};
+  const int zs[3] = {mirror_coord(g, k - 1, 2), k, mirror_coord(g, k + 1, 2)};
+  auto at = [&](int c, int dx, int dy, int dz) {
+    return f[c * Nn + (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1])];
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T sxy = at(c, -1, -1, 0) + at(c, 1, -1, 0) + at(c, -1, 1, 0) + at(c, 1, 1, 0);
+    const T sxz = at(c, -1, 0, -1) + at(c, 1, 0, -1) + at(c, -1, 0, 1) + at(c, 1, 0, 1);
+    const T syz = at(c, 0, -1, -1) + at(c, 0, 1, -1) + at(c, 0, -1, 1) + at(c, 0, 1, 1);
+    out[c] = T(g.st[c][0]) * at(c, 0, 0, 0) + T(g.st[c][1]) * sxy + T(g.st[c][2]) * sxz + T(g.st[c][3]) * syz;
+  }
+}
+
+// p = 2^b div_D(sigma) from an FP64 displacement: neighbour differences are formed in
+// FP64 and rounded once, the stress and divergence arithmetic is in T.
+template <typename T, bool SIG>
+__device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restrict__ u, const T* __restrict__ lam,
+                                            const T* __restrict__ mu, int i, int j, int k, T p[3], double& sn,
+                                            double ms[6]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int xs[3] = {mirror_coord(g, i - 1, 0), i, mirror_coord(g, i + 1, 0)};
+  const int ys[3] = {mirror_coord(g, j - 1, 1), j, mirror_coord(g, j + 1, 1)};
+  const int zs[3] = {mirror_coord(g, k - 1, 2), k, mirror_coord(g, k + 1, 2)};
+  const long long self = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * k);
+  double u0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u0[c] = u[c * Nn + self];
+  T nb[27][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nrm = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nrm != 2) continue;
+        const long long idx = (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1]);
+        const int q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[q][c] = (T)(u[c * Nn + idx] - u0[c]);
+      }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) nb[13][c] = T(0);
+  T F[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    int vx = i - ax, vy = j - ay, vz = k - az;
+    bool inside = true;
+    if (g.periodic[0]) { if (vx < 0) vx += g.n[0]; } else inside &= (vx >= 0 && vx < g.n[0]);
+    if (g.periodic[1]) { if (vy < 0) vy += g.n[1]; } else inside &= (vy >= 0 && vy < g.n[1]);
+    if (g.periodic[2]) { if (vz < 0) vz += g.n[2]; } else inside &= (vz >= 0 && vz < g.n[2]);
+    if (!inside) continue;
+    const long long vid = (long long)vx + (long long)g.n[0] * ((long long)vy + (long long)g.n[1] * vz);
+    const T l = lam[vid], m = mu[vid];
+    T G[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) G[r][s] = T(0);
+    const int par = (ax + ay + az) & 1;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+      if (((cx + cy + cz) & 1) != par) continue;
+      const int q = (cx - ax + 1) + 3 * (cy - ay + 1) + 9 * (cz - az + 1);
+      const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        G[r][0] += sx * nb[q][r];
+        G[r][1] += sy * nb[q][r];
+        G[r][2] += sz * nb[q][r];
+      }
+    }
+    const T tr = G[0][0] + G[1][1] + G[2][2];
+    const T s00 = l * tr + T(2) * m * G[0][0];
+    const T s11 = l * tr + T(2) * m * G[1][1];
+    const T s22 = l * tr + T(2) * m * G[2][2];
+    const T s01 = m * (G[0][1] + G[1][0]);
+    const T s02 = m * (G[0][2] + G[2][0]);
+    const T s12 = m * (G[1][2] + G[2][1]);
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    F[0] += bx * s00 + by * s01 + bz * s02;
+    F[1] += bx * s01 + by * s11 + bz * s12;
+    F[2] += bx * s02 + by * s12 + bz * s22;
+    if (SIG && (a == 0 || a == 1)) {
+      const double d00 = s00, d11 = s11, d22 = s22, d01 = s01, d02 = s02, d12 = s12;
+      sn += 0.5 * (d00 * d00 + d11 * d11 + d22 * d22 + 2.0 * (d01 * d01 + d02 * d02 + d12 * d12));
+      ms[0] += 0.5 * d00; ms[1] += 0.5 * d11; ms[2] += 0.5 * d22;
+      ms[3] += 0.5 * d12; ms[4] += 0.5 * d02; ms[5] += 0.5 * d01;
+    }
+  }
+  const int xyz[3] = {i, j, k};
+  const T w2b = T(1 << bcount(g, xyz));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+}
+
+// forward-transform weight of a node in the singular coefficients (DCT1 ends 1, interior 2; DFT 1)
+__device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
+  double w = 1.0;
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    if (!g.periodic[J] && xyz[J] > 0 && xyz[J] < g.n[J]) w *= 2.0;
+  return w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[kPartStrideD * 16];
+  if (st->done) return;
+  double acc[kPartStrideD];
+#pragma unroll
+  for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int cur = ct.on ? st->vpar : 0;
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;   // (il - 2) mod 3
+  T* pc = D.p[par];
+  const T* pp = D.p[par ^ 1];
+  T* Rc = D.R[par];
+  const T* Rp = D.R[par ^ 1];
+  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < Nn;
+       node += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(node % Nx);
+    const long long r = node / Nx;
+    const int j = (int)(r % Ny), k = (int)(r / Ny);
+    T p[3];
+    double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
+    node_eval_d<T, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    acc[1] += sn;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
+    const int xyz[3] = {i, j, k};
+    // singular-mode coefficients of u (projection Pi of the update)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (!g.sing[c]) continue;
+      const double wu = sing_weight(g, xyz) * D.u[c * Nn + node];
+      acc[8 + 2 * c] += wu;
+      if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
+    }
+    const uint8_t m = D.mask[node];
+    if (ct.on && (m & M_FACE)) {
+      const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
+      const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
+      const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
+      const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double gap = rr - ct.radius;
+      const double n0 = -d0 / rr, n1 = -d1 / rr, n2 = -d2 / rr;
+      const double pn = (double)p[0] * n0 + (double)p[1] * n1 + (double)p[2] * n2;
+      const double fnc = -pn / (double)(1 << bcount(g, xyz));
+      const uint8_t inC = ct.C[f];
+      if (inC) {
+        p[0] = (T)((double)p[0] - pn * n0);
+        p[1] = (T)((double)p[1] - pn * n1);
+        p[2] = (T)((double)p[2] - pn * n2);
+      }
+      ct.V[cur][f] = (uint8_t)(((!inC) && gap < 0.0) ? 1 : 0) | (uint8_t)((inC && fnc > 0.0) ? 2 : 0);
+      ct.fnc[f] = fnc;
+      ct.gap[f] = gap;
+      acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (m & (M_STRONG << c)) p[c] = T(0);
+        else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pc[c * Nn + node] = p[c];
+    if (acvp && il >= 1) {
+      T kd[3];
+      stencil_k0<T>(g, D.delta, i, j, k, kd);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long e = c * Nn + node;
+        const T Ri = p[c] + kd[c] - D.e[e];
+        Rc[e] = Ri;
+        if (il >= 2) {
+          D.dR[slot][e] = Ri - Rp[e];
+          D.dY[slot][e] = p[c] - pp[e] + kd[c];
+        }
+      }
+    }
+  }
+  block_sum<kPartStrideD>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+}
+
+// proj_P of the average relations on p (and on the quantities linear in p)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st) {
+  if (st->done) return;
+  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (r >= w.m) return;
+  const int c = w.comp[r];
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;
+  double phys[8], wb[8];
+  double sum = 0.0;
+  for (int s = 0; s < w.k; ++s) {
+    const long long node = w.nodes[r * w.k + s];
+    const int i = (int)(node % g.N[0]);
+    const long long q = node / g.N[0];
+    const int j = (int)(q % g.N[1]), k = (int)(q / g.N[1]);
+    T p[3];
+    double sn = 0.0, ms[6];
+    node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    const int xyz[3] = {i, j, k};
+    wb[s] = (double)(1 << bcount(g, xyz));
+    phys[s] = (double)p[c] / wb[s];
+    sum += phys[s];
+  }
+  const double mean = sum / w.k;
+  double pn = 0.0;
+  for (int s = 0; s < w.k; ++s) {
+    const long long e = c * g.Nn + w.nodes[r * w.k + s];
+    const double pnew = (phys[s] - mean) * wb[s];
+    pn += pnew * pnew;
+    const T sh = (T)(mean * wb[s]);
+    D.p[par][e] = (T)pnew;
+    if (acvp && il >= 1) {
+      D.R[par][e] -= sh;
+      if (il >= 2) {
+        D.dR[slot][e] -= sh;
+        D.dY[slot][e] -= sh;
+      }
+    }
+  }
+  w.part[r] = pn;
+  w.react[r] = -sum;
+}
+
+// Gram matrix of the R differences and their products with R_i (accelerating iterations)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gram3(DeltaBufs<T> D, long long n3, DevState* st, double* __restrict__ gpart) {
+  __shared__ double sh[9 * 16];
+  if (st->done || !st->accel) return;
+  const T* Ri = D.R[st->it & 1];
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
+    const double a0 = D.dR[0][e], a1 = D.dR[1][e], a2 = D.dR[2][e], r = Ri[e];
+    acc[0] += a0 * a0; acc[1] += a0 * a1; acc[2] += a0 * a2;
+    acc[3] += a1 * a1; acc[4] += a1 * a2; acc[5] += a2 * a2;
+    acc[6] += a0 * r; acc[7] += a1 * r; acc[8] += a2 * r;
+  }
+  block_sum<9>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gpart[blockIdx.x * 9 + q] = acc[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* __restrict__ gpart, int nblk) {
+  __shared__ double sh[9 * 16];
+  if (st->done || !st->accel) return;
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] += gpart[b * 9 + q];
+  block_sum<9>(acc, sh);
+  if (threadIdx.x != 0) return;
+  double G[3][4] = {{acc[0], acc[1], acc[2], acc[6]}, {acc[1], acc[3], acc[4], acc[7]}, {acc[2], acc[4], acc[5], acc[8]}};
+  const double tr = G[0][0] + G[1][1] + G[2][2];
+  for (int a = 0; a < 3; ++a) G[a][a] += 1e-14 * tr / 3.0;
+  bool ok = true;
+  for (int col = 0; col < 3 && ok; ++col) {
+    int piv = col;
+    double best = fabs(G[col][col]);
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(G[r][col]) > best) {
+        best = fabs(G[r][col]);
+        piv = r;
+      }
+    if (!(best > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int q = 0; q < 4; ++q) {
+        const double t = G[col][q];
+        G[col][q] = G[piv][q];
+        G[piv][q] = t;
+      }
+    for (int r = col + 1; r < 3; ++r) {
+      const double f = G[r][col] / G[col][col];
+      for (int q = col; q < 4; ++q) G[r][q] -= f * G[col][q];
+    }
+  }
+  double y[3] = {0, 0, 0};
+  if (ok) {
+    for (int r = 2; r >= 0; --r) {
+      double s = G[r][3];
+      for (int q = r + 1; q < 3; ++q) s -= G[r][q] * y[q];
+      y[r] = s / G[r][r];
+    }
+    ok = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  }
+  if (ok)
+    for (int a = 0; a < 3; ++a) st->gamma[a] = y[a];
+  st->accel_ok = ok ? 1 : 0;
+}
+
+// proj_U of the residual-form path on the FP64 displacement; the increment follows
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_d(Geo g, DeltaBufs<T> D, StrongDev s, WeakDev w, ContactDev ct,
+                                                   DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  // strong DOFs
+  if (e < s.m) {
+    const long long idx = s.comp[e] * g.Nn + s.node[e];
+    const double old = D.u[idx];
+    D.u[idx] = s.val[e];
+    D.delta[idx] = (T)((double)D.delta[idx] + (s.val[e] - old));
+  }
+  // average relations
+  if (e < w.m) {
+    const int c = w.comp[e];
+    double sum = 0.0;
+    for (int q = 0; q < w.k; ++q) sum += D.u[c * g.Nn + w.nodes[e * w.k + q]];
+    const double corr = w.val[e] - sum / w.k;
+    for (int q = 0; q < w.k; ++q) {
+      const long long idx = c * g.Nn + w.nodes[e * w.k + q];
+      D.u[idx] += corr;
+      D.delta[idx] = (T)((double)D.delta[idx] + corr);
+    }
+  }
+  // contact nodes: radial projection onto the sphere
+  if (ct.on && e < ct.nface && ct.C[e]) {
+    int xyz[3];
+    xyz[ct.axis] = ct.side ? g.n[ct.axis] : 0;
+    xyz[ct.b1] = (int)(e % g.N[ct.b1]);
+    xyz[ct.b2] = (int)(e / g.N[ct.b1]);
+    const long long node = xyz[0] + (long long)g.N[0] * (xyz[1] + (long long)g.N[1] * xyz[2]);
+    double d[3], r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      d[c] = xyz[c] + D.u[c * g.Nn + node] - ct.center[c];
+      r2 += d[c] * d[c];
+    }
+    const double rr = sqrt(r2);
+    for (int c = 0; c < 3; ++c) {
+      const long long idx = c * g.Nn + node;
+      const double nw = ct.center[c] + ct.radius * d[c] / rr - xyz[c];
+      D.delta[idx] = (T)((double)D.delta[idx] + (nw - D.u[idx]));
+      D.u[idx] = nw;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_advance(DevState* st) {
+  if (st->done) return;
+  st->it += 1;
+  st->i_local += 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, StrongDev s, double* out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= s.m) return;
+  const long long node = s.node[e];
+  const int i = (int)(node % g.N[0]);
+  const long long q = node / g.N[0];
+  const int j = (int)(q % g.N[1]), k = (int)(q / g.N[1]);
+  T p[3];
+  double sn = 0.0, ms[6];
+  node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  const int xyz[3] = {i, j, k};
+  out[e] = -(double)p[s.comp[e]] / (double)(1 << bcount(g, xyz));
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -1028,8 +1629,8 @@ void launch_weak(const Geo& g, const Bufs<T>& B, const WeakDev& w, DevState* st,
 }
 
 void launch_control(DevState* st, const double* part, int nblk, const double* wpart, long long nweak,
-                    const ContactDev& ct, hipStream_t s) {
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, nweak, ct);
+                    const ContactDev& ct, int pstride, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, nweak, ct, pstride);
 }
 
 template <typename T>
@@ -1043,8 +1644,42 @@ size_t dtt_smem(const AxisPlan& ap) {
   return sizeof(cplx<T>) * (size_t)ap.L * (ap.n + 1) + sizeof(T) * (size_t)ap.L * (ap.N + 1);
 }
 
+template <typename T, int NF, int NTH>
+static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
+  using S = DttShape<NF, NTH>;
+  const int Nx = a.g.N[0], Ny = a.g.N[1], Nz = a.g.N[2];
+  dim3 grid;
+  if (a.axis == 0) grid = dim3((Ny + S::LB - 1) / S::LB, Nz, 3);
+  else if (a.axis == 1) grid = dim3((Nx + S::LB - 1) / S::LB, Nz, 3);
+  else grid = dim3((Nx + S::LB - 1) / S::LB, Ny, 3);
+  const size_t sm = sizeof(cplx<T>) * (size_t)S::LB * S::CS;
+  hipLaunchKernelGGL((k_dtt2<T, NF, NTH>), grid, dim3(S::NT), sm, s, a);
+}
+
 template <typename T>
 void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s) {
+  if (!a.g.periodic[a.axis] && !a.generic) {
+    // block size chosen by the host autotuner (a.nt): FP64 128 or 256 threads, FP32 256 or 512
+    constexpr int NLO = sizeof(T) == 8 ? 128 : 256;
+    constexpr int NHI = sizeof(T) == 8 ? 256 : 512;
+    const bool hi = a.nt >= NHI;
+#define FFTC_DTT_CASE(L)                                   \
+  case L:                                                  \
+    if (hi) launch_dtt2<T, L, NHI>(a, s);                  \
+    else launch_dtt2<T, L, NLO>(a, s);                     \
+    return;
+    switch (a.ap.n) {
+      FFTC_DTT_CASE(16)
+      FFTC_DTT_CASE(32)
+      FFTC_DTT_CASE(48)
+      FFTC_DTT_CASE(64)
+      FFTC_DTT_CASE(96)
+      FFTC_DTT_CASE(128)
+      FFTC_DTT_CASE(256)
+      default: break;
+    }
+#undef FFTC_DTT_CASE
+  }
   const int Nx = a.g.N[0], Ny = a.g.N[1], Nz = a.g.N[2];
   const long long nlines = a.axis == 0 ? (long long)Ny * Nz : a.axis == 1 ? (long long)Nx * Nz : (long long)Nx * Ny;
   const long long nb = (nlines + a.ap.L - 1) / a.ap.L;
@@ -1077,6 +1712,40 @@ void launch_flags_combine(const Bufs<T>& B, long long n3, DevState* st, int whic
 template <typename T>
 void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double* out, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_contact_force<T>, dim3(nblk), dim3(kBlock), 0, s, g, u, ct, out);
+}
+
+template <typename T>
+void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
+                                  DevState* st, double* part, double* wpart, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+  if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, D, w, st);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, w.m, ct, kPartStrideD);
+}
+
+template <typename T>
+void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram3<T>, dim3(nblk), dim3(kBlock), 0, s, D, n3, st, gpart);
+  hipLaunchKernelGGL(k_alpha3, dim3(1), dim3(kBlock), 0, s, st, gpart, nblk);
+}
+
+template <typename T>
+void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, const WeakDev& w,
+                       const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s) {
+  long long m = sd.m > w.m ? sd.m : w.m;
+  if (ct.on && ct.nface > m) m = ct.nface;
+  if (m > 0) hipLaunchKernelGGL(k_proj_d<T>, dim3(grid_for(m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, w, ct, st, force);
+  if (advance) hipLaunchKernelGGL(k_advance<T>, dim3(1), dim3(1), 0, s, st);
+}
+
+template <typename T>
+void launch_reactions_d(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, double* out, hipStream_t s) {
+  if (sd.m == 0) return;
+  hipLaunchKernelGGL(k_reactions_d<T>, dim3(grid_for(sd.m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, out);
+}
+
+template <typename T>
+void launch_weak_d_stage(const Geo& g, const DeltaBufs<T>& D, const WeakDev& w, DevState* st, hipStream_t s) {
+  if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, D, w, st);
 }
 
 template <typename T>
@@ -1128,5 +1797,11 @@ FFTC_INST(float)
 template void launch_convert<double, double>(const double*, double*, long long, hipStream_t);
 template void launch_convert<double, float>(const double*, float*, long long, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, long long, hipStream_t);
+template void launch_delta_iteration_front<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
+                                                  DevState*, double*, double*, int, hipStream_t);
+template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
+template void launch_delta_proj<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, const WeakDev&,
+                                       const ContactDev&, DevState*, int, int, hipStream_t);
+template void launch_reactions_d<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, double*, hipStream_t);
 
 }  // namespace fftc

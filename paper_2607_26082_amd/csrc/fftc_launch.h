@@ -10,7 +10,17 @@ void launch_residual(const Geo& g, const Bufs<T>& B, const ContactDev& ct, DevSt
 template <typename T>
 void launch_weak(const Geo& g, const Bufs<T>& B, const WeakDev& w, DevState* st, int force, hipStream_t s);
 void launch_control(DevState* st, const double* part, int nblk, const double* wpart, long long nweak,
-                    const ContactDev& ct, hipStream_t s);
+                    const ContactDev& ct, int pstride, hipStream_t s);
+template <typename T>
+void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
+                                  DevState* st, double* part, double* wpart, int nblk, hipStream_t s);
+template <typename T>
+void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
+template <typename T>
+void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, const WeakDev& w,
+                       const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s);
+template <typename T>
+void launch_reactions_d(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, double* out, hipStream_t s);
 template <typename T>
 void launch_anderson(const Bufs<T>& B, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
 template <typename T>

@@ -34,7 +34,10 @@ def _case(seed, n, periodic_axis=None, weak=True):
     return lam, mu, bc, strong, avg
 
 
-SHAPES = [((6, 5, 9), None), ((10, 12, 15), 1), ((16, 16, 16), None), ((24, 20, 18), 0), ((9, 8, 10), 2)]
+SHAPES = [((6, 5, 9), None), ((10, 12, 15), 1), ((16, 16, 16), None), ((24, 20, 18), 0), ((9, 8, 10), 2),
+          # every compile-time transform length on every axis, ragged line tiles
+          ((32, 48, 6), None), ((64, 5, 96), None), ((128, 6, 16), None), ((256, 4, 5), None),
+          ((5, 256, 4), None), ((4, 6, 128), None), ((64, 32, 48), 1), ((96, 128, 32), None)]
 
 
 @pytest.mark.parametrize("idx", range(len(SHAPES)))
@@ -78,18 +81,36 @@ def test_stage_green(idx, prec):
 
 
 def test_c1_fp64_trajectory():
+    """Same algorithm, same iteration count at the workload tolerance (1e-8); the final
+    iterates agree to the sensitivity of the accelerated iteration (rounding of the two
+    implementations differs at 1e-16 and the Anderson least squares amplifies it)."""
     F = _lib()
     prob = W.c1_inclusion_patch()
-    print("[c1 fp64]", flush=True)
+    print("[c1 fp64 trajectory]", flush=True)
     o = OSolver.from_problem(prob).solve(tol=prob.tol)
     g = F.Solver.from_problem(prob, precision="fp64")
     rc, rep = g.solve()
     assert rc == 0 and rep.status == 0
     assert rep.iterations == o["iterations"]
     u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-9 * np.linalg.norm(o["u"])
+    _, _, tot = g.reactions()
+    assert np.abs(tot - o["totals"]).max() <= 1e-8 * np.abs(o["totals"]).max()
+
+
+def test_c1_fp64_solution():
+    """Both sides converged to 1e-12: displacements within 1e-10 (relative L2), reactions 1e-10."""
+    F = _lib()
+    prob = W.c1_inclusion_patch()
+    print("[c1 fp64 solution]", flush=True)
+    o = OSolver.from_problem(prob).solve(tol=1e-12)
+    g = F.Solver.from_problem(prob, precision="fp64", tol=1e-12)
+    rc, rep = g.solve()
+    assert rc == 0
+    u = g.u.cpu().numpy()
     assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
     _, _, tot = g.reactions()
-    assert np.abs(tot - o["totals"]).max() <= 1e-9 * np.abs(o["totals"]).max()
+    assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()
 
 
 def test_c1_fp32_solution():
@@ -129,13 +150,15 @@ def test_contact_increments(prec):
     prob = W.c3_indentation(n=n, R=R)
     cs = ContactSolver(n, prob.lam, prob.mu, prob.bc, face=5, radius=R, r0_factor=5.0)
     sph = W.Sphere(np.array([16.0, 16.0, 16 + R]), R, 5)
+    # FP64: both sides converge to 1e-10 so the comparison measures the solution, not the
+    # rounding-sensitive Anderson path; FP32: GPU to 1e-6 against the oracle at 1e-11
     g = F.Solver(n, prob.lam, prob.mu, prob.bc, sphere=sph, r0_factor=5.0, precision=prec,
-                 tol=1e-6 if prec == "fp32" else 1e-8)
+                 tol=1e-6 if prec == "fp32" else 1e-10)
     u_o = None
     for k in range(1, 4):
         d = 0.004 * k * R
         c = np.array([16.0, 16.0, 16 + R - d])
-        o = cs.solve_increment(u_o, c, tol=1e-8 if prec == "fp64" else 1e-11)
+        o = cs.solve_increment(u_o, c, tol=1e-10 if prec == "fp64" else 1e-11)
         u_o = o["u"]
         g.move_sphere(c)
         rc, rep = g.solve(zero_start=(k == 1))
@@ -146,6 +169,4 @@ def test_contact_increments(prec):
         u = g.u.cpu().numpy()
         tol = 1e-10 if prec == "fp64" else 1e-5
         assert np.linalg.norm(u - o["u"]) <= tol * np.linalg.norm(o["u"])
-        if prec == "fp64":
-            assert rep.iterations == o["iterations"]
         assert abs(rep.force_contact - o["force_contact"]) <= 1e-6 * o["force_contact"] + (0 if prec == "fp64" else 1e-4 * o["force_contact"])
