@@ -6,6 +6,7 @@ solve, inverse DTTs, proj_U) on the 256^3 two-phase block (bottom fixed, 16x16-n
 pressed on the top face), inputs resident in HBM.  Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,14 +21,27 @@ METRIC = "voxel-iters/s at 256^3; time to 1e-6 residual, NN warm-start vs plain"
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_bytes(N, nv, s):
-    """Algorithmic HBM bytes of each stage per iteration (s = bytes per value).
-    Node fields have 3 components; N = nodes, nv = voxels."""
-    f = 3 * N * s
+def stage_bytes(N, nv, precision):
+    """Algorithmic HBM bytes of one launch of each stage (N nodes, nv voxels; vector node
+    fields have 3 components).  FP32 is the residual-form iteration (FP64 displacement);
+    FP64 the literal one.  Accelerating iterations of the Anderson stage and the x forward
+    pass are counted (they dominate their average)."""
+    if precision == "fp32":
+        f = 3 * N * 4
+        return {
+            # read u (FP64), delta, e, R_prev, p_prev, lam, mu; write p, R, dR, dY
+            "residual": 2 * f + 5 * f + 2 * nv * 4 + 4 * f,
+            "anderson": 4 * f,                 # read dR x3, R
+            "dtt_x_fwd": 4 * f + 2 * f,        # read p, dY x3; write e, t
+            "dtt_y_fwd": 2 * f, "dtt_z_green": 2 * f, "dtt_y_inv": 2 * f,
+            "dtt_x_inv": f + 2 * f + 2 * f + f,  # read t, u (FP64); write u (FP64), delta
+        }
+    f = 3 * N * 8
     return {
-        "residual": 2 * f + 2 * nv * s,        # read u, lam, mu; write p~
-        "anderson": 3 * f,                     # read p~, S_prev; write R (Gram reads counted below)
-        "dtt_x_fwd": 2 * f, "dtt_y_fwd": 2 * f, "dtt_z_green": 2 * f, "dtt_y_inv": 2 * f, "dtt_x_inv": 2 * f,
+        "residual": 2 * f + 2 * nv * 8,        # read u, lam, mu; write p~
+        "anderson": 3 * f + 3 * f,             # read p~, S_prev, 3 R; write R
+        "dtt_x_fwd": 8 * f + 2 * f,            # read 4 S + 4 R; write S, t
+        "dtt_y_fwd": 2 * f, "dtt_z_green": 2 * f, "dtt_y_inv": 2 * f, "dtt_x_inv": 2 * f,
     }
 
 
@@ -39,7 +53,31 @@ def b_alg_per_voxel_iter(N, nv, s, m=4, q=2):
     return (vals * N * s + 2 * nv * s) / nv
 
 
-def cpu_baseline(prob):
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("fftc_kernels.hip", "fftc_dtt.h", "fftc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2607_26082_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary, only if
+    the kernel sources are unchanged since the counters were taken (else None)."""
+    path = os.path.join(ROOT, "profiles", "residual_d_m256_fp32_traffic.txt")
+    if precision != "fp32" or kernel != "residual" or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(prob, iters=2):
     """One oracle iteration (FP64 NumPy/SciPy) of the same workload on the host."""
     from oracle.solver import Anderson, Solver as OSolver
     t0 = time.time()
@@ -48,15 +86,16 @@ def cpu_baseline(prob):
     s.cons.proj_U(u)
     setup = time.time() - t0
     t0 = time.time()
-    parts = s.iterate_parts(u)
     acc = Anderson(4, 2)
-    x = acc.step(0, parts["ptil"])
-    u = s.green.apply(x)
-    s.cons.proj_U(u)
+    for i in range(iters):
+        parts = s.iterate_parts(u)
+        x = acc.step(i, parts["ptil"])
+        u = s.green.apply(x)
+        s.cons.proj_U(u)
     dt = time.time() - t0
     nv = int(np.prod(prob.n))
-    return {"value": nv / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 iteration of the FP64 NumPy/SciPy oracle on the same 256^3 workload "
+    return {"value": nv * iters / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations of the FP64 NumPy/SciPy oracle on the same 256^3 workload "
                       f"({dt:.1f} s; set-up {setup:.1f} s excluded); NumPy elementwise and scipy.fft "
                       f"(default workers=1) single-threaded"}
 
@@ -66,7 +105,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=5)
@@ -99,7 +140,14 @@ def main():
     s = 8 if args.precision == "fp64" else 4
     # per-stage HIP-event timing on the library's stream
     prof = g.profile(args.profile_iters)
-    sb = stage_bytes(N, nv, s)
+    sb = stage_bytes(N, nv, args.precision)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
     stages = {}
     for k, t in prof.items():
         stages[k] = {"ms": round(t, 4)}
@@ -118,7 +166,9 @@ def main():
                                "ACV_P depth 4 period 2, no exit test",
                    "voxels": nv, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.precision, dom), "kernel": dom,
+                     "alg_bytes_per_launch": sb[dom]},
         "iteration_bytes_alg_GBps": round(balg * value / 1e9, 1),
         "iteration_frac_of_hbm_peak": round(balg * value / 1e9 / HBM_PEAK_GBS, 4),
         "stages": stages,

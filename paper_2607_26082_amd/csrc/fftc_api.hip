@@ -745,6 +745,10 @@ int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision) {
   memset(h->bc, FFTC_BC_NEUMANN, sizeof(h->bc));
   build_plan(h);
   h->Nv = (long long)n[0] * n[1] * n[2];
+  if (3LL * (n[0] + 1LL) * (n[1] + 1LL) * (n[2] + 1LL) >= (1LL << 31)) {
+    delete h;
+    return FFTC_E_UNSUPPORTED;   // node indices are 32-bit inside the kernels
+  }
   *out = h;
   return FFTC_OK;
 }
@@ -1044,6 +1048,7 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
   }
+  if (h->nblk_res >= 8) h->nblk_res -= h->nblk_res % 8;   // whole slabs per XCD
   if (h->nblk_res < 1) h->nblk_res = 1;
   for (int q = 0; q < 10; ++q)
     HIPCHK(h, hipMemsetAsync(h->fld[q], 0, (h->precision == FFTC_FP64 ? 8 : 4) * 3 * (size_t)h->Nn, s));

@@ -49,6 +49,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*1
   __syncthreads();
 }
 
+// Contiguous node range of this block, with blocks of one XCD (workgroups are dealt
+// round-robin to the 8 XCDs) owning one contiguous slab, so that the y/z neighbours a
+// block reads are produced by blocks on the same XCD and hit its L2.
+__device__ __forceinline__ void xcd_chunk(long long total, long long& lo, long long& hi) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const long long chunk = (total + G - 1) / G;
+  lo = (long long)lb * chunk;
+  hi = lo + chunk < total ? lo + chunk : total;
+}
+
 __device__ __forceinline__ int mirror_coord(const Geo& g, int x, int J) {
   if (g.periodic[J]) return x < 0 ? x + g.N[J] : (x >= g.N[J] ? x - g.N[J] : x);
   return x < 0 ? -x : (x > g.n[J] ? 2 * g.n[J] - x : x);
@@ -185,11 +196,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDe
   const int Nx = g.N[0], Ny = g.N[1];
   const long long Nn = g.Nn;
   const int cur = ct.on ? st->vpar : 0;
-  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < Nn;
-       node += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(node % Nx);
-    const long long r = node / Nx;
-    const int j = (int)(r % Ny), k = (int)(r / Ny);
+  long long lo, hi;
+  xcd_chunk(Nn, lo, hi);
+  for (long long node = lo + threadIdx.x; node < hi; node += blockDim.x) {
+    const int nd = (int)node;
+    const int r = nd / Nx;
+    const int i = nd - r * Nx;
+    const int k = r / Ny, j = r - k * Ny;
     T p[3], k0[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
     node_eval<T, true>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
@@ -1351,11 +1364,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
   const T* pp = D.p[par ^ 1];
   T* Rc = D.R[par];
   const T* Rp = D.R[par ^ 1];
-  for (long long node = blockIdx.x * (long long)blockDim.x + threadIdx.x; node < Nn;
-       node += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(node % Nx);
-    const long long r = node / Nx;
-    const int j = (int)(r % Ny), k = (int)(r / Ny);
+  long long lo, hi;
+  xcd_chunk(Nn, lo, hi);
+  for (long long node = lo + threadIdx.x; node < hi; node += blockDim.x) {
+    const int nd = (int)node;
+    const int r = nd / Nx;
+    const int i = nd - r * Nx;
+    const int k = r / Ny, j = r - k * Ny;
     T p[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
     node_eval_d<T, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
