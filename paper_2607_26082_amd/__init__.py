@@ -68,6 +68,10 @@ _SIGS = {
     "fftc_stage_green": (C.c_int, [_P, _P, _P]),
     "fftc_iterate": (C.c_int, [_P, C.c_int32]),
     "fftc_profile_stages": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_double), C.c_int32]),
+    "fftc_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P), _P]),
+    "fftc_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.c_int32, C.POINTER(fftc_report)]),
+    "fftc_batch_destroy": (None, [_P]),
+    "fftc_batch_last_error": (C.c_char_p, [_P]),
     "fftc_status_str": (C.c_char_p, [C.c_int]),
     "fftc_last_error": (C.c_char_p, [_P]),
 }
@@ -240,6 +244,51 @@ def fftc_profile_stages(h, iters):
     ms = np.zeros(len(STAGES))
     _check(h, load().fftc_profile_stages(h, int(iters), _ptr(ms, C.c_double), len(STAGES)), "fftc_profile_stages")
     return dict(zip(STAGES, ms))
+
+
+def fftc_batch_create(handles, stream):
+    lib = load()
+    bh = C.c_void_p()
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    rc = lib.fftc_batch_create(C.byref(bh), len(handles), arr, C.c_void_p(stream))
+    if rc != FFTC_OK:
+        raise FftcError(rc, "fftc_batch_create: " + lib.fftc_status_str(rc).decode())
+    return bh
+
+
+def fftc_batch_solve(bh, u_devs, zero_start=True):
+    lib = load()
+    n = len(u_devs)
+    ptrs = (C.c_void_p * n)(*[int(t.data_ptr()) for t in u_devs])
+    reps = (fftc_report * n)()
+    rc = lib.fftc_batch_solve(bh, ptrs, 1 if zero_start else 0, reps)
+    if rc not in (FFTC_OK, FFTC_E_NOCONV, FFTC_E_NAN):
+        raise FftcError(rc, "fftc_batch_solve: " + lib.fftc_batch_last_error(bh).decode())
+    return rc, list(reps)
+
+
+def fftc_batch_destroy(bh):
+    load().fftc_batch_destroy(bh)
+
+
+class Batch:
+    """Batched solve of several Solver objects (same device)."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        self.stream = self.solvers[0].stream
+        self.bh = fftc_batch_create([s.h for s in self.solvers], self.stream.cuda_stream)
+
+    def solve(self, zero_start=True):
+        return fftc_batch_solve(self.bh, [s.u for s in self.solvers], zero_start)
+
+    def __del__(self):
+        try:
+            if getattr(self, "bh", None) is not None:
+                fftc_batch_destroy(self.bh)
+                self.bh = None
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

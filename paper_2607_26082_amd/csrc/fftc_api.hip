@@ -72,8 +72,22 @@ struct fftc_problem {
   Geo g;
   std::string err;
   DevState last{};
+  DevState init_host{};
   std::vector<double> react_strong, react_weak;
   int profiling = 0;
+};
+
+struct fftc_batch {
+  std::vector<fftc_problem*> cells;
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipStream_t cap = nullptr;      // capture / replay stream (the caller's may be the NULL stream)
+  hipEvent_t ready = nullptr;
+  DevState* pinned = nullptr;     // host-pinned copies of the cells' device states
+  int iters_per_graph = 4;
+  std::string err;
 };
 
 namespace {
@@ -494,21 +508,9 @@ int profile_t(fftc_problem* h, int iters, double* ms, int nst) {
   return FFTC_OK;
 }
 
-int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, fftc_report* rep);
+// ---- solve = init + device-driven iterations + finish (shared by solo and batched solves)
 
-int solve_delta(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
-  DeltaBufs<float> D = dbufs(h);
-  hipStream_t s = h->stream;
-  const long long n3 = 3 * h->Nn;
-  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(D.u, 0, 8 * n3, s));
-  else HIPCHK(h, hipMemcpyAsync(D.u, u_dev, 8 * n3, hipMemcpyDeviceToDevice, s));
-  launch_zero_amask<double>(h->g, D.u, s);
-  const ContactDev ct = contact_dev(h);
-  const WeakDev w = weak_dev(h);
-  const StrongDev sd = strong_dev(h);
-  if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
-  launch_delta_proj<float>(h->g, D, sd, w, ct, h->st, 1, 0, s);
-  for (int q = 0; q < 12; ++q) HIPCHK(h, hipMemsetAsync(h->dfld[q], 0, 4 * n3, s));
+int init_state(fftc_problem* h) {
   DevState hs{};
   hs.tol = h->cfg.tol;
   hs.gate = h->cfg.update_gate;
@@ -516,44 +518,51 @@ int solve_delta(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep
   hs.period = h->cfg.period;
   hs.acv = h->cfg.acv;
   hs.contact = h->has_sphere;
-  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
-  int chunk = 4;
-  DevState out{};
-  for (;;) {
-    for (int t = 0; t < chunk; ++t) enqueue_delta_iteration(h, nullptr);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(&out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    if (out.done) break;
-    chunk = std::min(64, chunk * 2);
-  }
-  h->last = out;
-  launch_reactions_d<float>(h->g, D, sd, h->sreact, s);
-  if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
-  h->react_strong.assign(h->s_comp.size(), 0.0);
-  h->react_weak.assign(h->w_comp.size(), 0.0);
-  if (!h->react_strong.empty())
-    HIPCHK(h, hipMemcpyAsync(h->react_strong.data(), h->sreact, 8 * h->react_strong.size(), hipMemcpyDeviceToHost, s));
-  if (!h->react_weak.empty())
-    HIPCHK(h, hipMemcpyAsync(h->react_weak.data(), h->wreact, 8 * h->react_weak.size(), hipMemcpyDeviceToHost, s));
-  double force_c = 0.0;
-  int nC = 0;
-  std::vector<double> cf(2 * 64, 0.0);
-  if (ct.on) {
-    launch_contact_force<double>(h->g, D.u, ct, h->chk, 64, s);
-    HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
-  }
-  HIPCHK(h, hipStreamSynchronize(s));
-  if (ct.on) {
-    double fs = 0.0, cnt = 0.0;
-    for (int b = 0; b < 64; ++b) {
-      fs += cf[2 * b];
-      cnt += cf[2 * b + 1];
-    }
-    force_c = -((h->face % 2) ? 1.0 : -1.0) * fs;
-    nC = (int)cnt;
-  }
-  return finish_report(h, out, force_c, nC, rep);
+  h->init_host = hs;
+  HIPCHK(h, hipMemcpyAsync(h->st, &h->init_host, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  return FFTC_OK;
+}
+
+template <typename T>
+int init_literal(fftc_problem* h, const double* u_dev, int zero_start) {
+  Bufs<T> B = bufs<T>(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(B.u, 0, sizeof(T) * n3, s));
+  else launch_convert<double, T>(u_dev, B.u, n3, s);
+  launch_zero_amask<T>(h->g, B.u, s);
+  const ContactDev ct = contact_dev(h);
+  // initial proj_U (and the initial active set from the gaps)
+  if (ct.on) launch_contact_init<T>(h->g, B.u, ct, s);
+  launch_proj<T>(h->g, B.u, weak_dev(h), ct, strong_dev(h), h->st, 0, 1, s);
+  return init_state(h);
+}
+
+int init_delta(fftc_problem* h, const double* u_dev, int zero_start) {
+  DeltaBufs<float> D = dbufs(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(D.u, 0, 8 * n3, s));
+  else HIPCHK(h, hipMemcpyAsync(D.u, u_dev, 8 * n3, hipMemcpyDeviceToDevice, s));
+  launch_zero_amask<double>(h->g, D.u, s);
+  const ContactDev ct = contact_dev(h);
+  if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
+  launch_delta_proj<float>(h->g, D, strong_dev(h), weak_dev(h), ct, h->st, 1, 0, s);
+  for (int q = 0; q < 12; ++q) HIPCHK(h, hipMemsetAsync(h->dfld[q], 0, 4 * n3, s));
+  return init_state(h);
+}
+
+int solve_init(fftc_problem* h, const double* u_dev, int zero_start) {
+  // FP32: residual-form iteration (FP64 displacement), except for ACV_U
+  h->delta_mode = (h->precision == FFTC_FP32 && h->cfg.acv != FFTC_ACV_U) ? 1 : 0;
+  if (h->delta_mode) return init_delta(h, u_dev, zero_start);
+  return h->precision == FFTC_FP64 ? init_literal<double>(h, u_dev, zero_start)
+                                   : init_literal<float>(h, u_dev, zero_start);
+}
+
+void enqueue_iter(fftc_problem* h) {
+  if (h->precision == FFTC_FP64) enqueue_iteration<double>(h);
+  else enqueue_iteration<float>(h);
 }
 
 int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, fftc_report* rep) {
@@ -581,57 +590,40 @@ int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, 
   return FFTC_OK;
 }
 
-template <typename T>
-int solve_t(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
-  if (h->delta_mode) return solve_delta(h, u_dev, zero_start, rep);
-  Bufs<T> B = bufs<T>(h);
+// After the iterations: reactions of the returned iterate, output displacement, report.
+int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
-  if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(B.u, 0, sizeof(T) * n3, s));
-  else launch_convert<double, T>(u_dev, B.u, n3, s);
-  launch_zero_amask<T>(h->g, B.u, s);
   const ContactDev ct = contact_dev(h);
-  const WeakDev w = weak_dev(h);
   const StrongDev sd = strong_dev(h);
-  // initial proj_U (and the initial active set from the gaps)
-  if (ct.on) launch_contact_init<T>(h->g, B.u, ct, s);
-  launch_proj<T>(h->g, B.u, w, ct, sd, h->st, 0, 1, s);
-  DevState hs{};
-  hs.tol = h->cfg.tol;
-  hs.gate = h->cfg.update_gate;
-  hs.max_iter = h->cfg.max_iter;
-  hs.period = h->cfg.period;
-  hs.acv = h->cfg.acv;
-  hs.contact = h->has_sphere;
-  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
-  int chunk = 4;
-  DevState out{};
-  for (;;) {
-    for (int t = 0; t < chunk; ++t) enqueue_iteration<T>(h);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(&out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    if (out.done) break;
-    chunk = std::min(64, chunk * 2);
+  HIPCHK(h, hipMemcpyAsync(&h->last, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  if (h->delta_mode) {
+    DeltaBufs<float> D = dbufs(h);
+    launch_reactions_d<float>(h->g, D, sd, h->sreact, s);
+    if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
+    if (ct.on) launch_contact_force<double>(h->g, D.u, ct, h->chk, 64, s);
+  } else if (h->precision == FFTC_FP64) {
+    Bufs<double> B = bufs<double>(h);
+    launch_reactions<double>(h->g, B, sd, h->sreact, s);
+    if (u_dev) launch_convert<double, double>(B.u, u_dev, n3, s);
+    if (ct.on) launch_contact_force<double>(h->g, B.u, ct, h->chk, 64, s);
+  } else {
+    Bufs<float> B = bufs<float>(h);
+    launch_reactions<float>(h->g, B, sd, h->sreact, s);
+    if (u_dev) launch_convert<float, double>(B.u, u_dev, n3, s);
+    if (ct.on) launch_contact_force<float>(h->g, B.u, ct, h->chk, 64, s);
   }
-  h->last = out;
-  // reactions of the returned iterate
-  launch_reactions<T>(h->g, B, sd, h->sreact, s);
-  if (u_dev) launch_convert<T, double>(B.u, u_dev, n3, s);
   h->react_strong.assign(h->s_comp.size(), 0.0);
   h->react_weak.assign(h->w_comp.size(), 0.0);
   if (!h->react_strong.empty())
     HIPCHK(h, hipMemcpyAsync(h->react_strong.data(), h->sreact, 8 * h->react_strong.size(), hipMemcpyDeviceToHost, s));
   if (!h->react_weak.empty())
     HIPCHK(h, hipMemcpyAsync(h->react_weak.data(), h->wreact, 8 * h->react_weak.size(), hipMemcpyDeviceToHost, s));
+  std::vector<double> cf(2 * 64, 0.0);
+  if (ct.on) HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
   double force_c = 0.0;
   int nC = 0;
-  std::vector<double> cf(2 * 64, 0.0);
-  if (ct.on) {
-    launch_contact_force<T>(h->g, B.u, ct, h->chk, 64, s);
-    HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
-  }
-  HIPCHK(h, hipStreamSynchronize(s));
   if (ct.on) {
     double fs = 0.0, cnt = 0.0;
     for (int b = 0; b < 64; ++b) {
@@ -641,29 +633,24 @@ int solve_t(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
     force_c = -((h->face % 2) ? 1.0 : -1.0) * fs;
     nC = (int)cnt;
   }
-  int status = out.status == ST_CONVERGED ? FFTC_OK : (out.status == ST_NAN ? FFTC_E_NAN : FFTC_E_NOCONV);
-  if (rep) {
-    memset(rep, 0, sizeof(*rep));
-    rep->status = status;
-    rep->iterations = out.it;
-    rep->residual = out.residual;
-    rep->contact_updates = out.updates;
-    rep->anderson_restarts = out.restarts;
-    const double nv = (double)h->Nv;
-    for (int q = 0; q < 6; ++q) rep->mean_stress[q] = out.ms[q] / nv;
-    if (ct.on) {
-      const int a = h->face / 2;
-      double A0 = 1.0;
-      for (int J = 0; J < 3; ++J)
-        if (J != a) A0 *= h->n[J];
-      rep->force_mean_stress = -A0 * rep->mean_stress[a];
-      rep->force_contact = force_c;
-      rep->contact_nodes = nC;
-    }
+  return finish_report(h, h->last, force_c, nC, rep);
+}
+
+int solve_all(fftc_problem* h, double* u_dev, int zero_start, fftc_report* rep) {
+  int rc = solve_init(h, u_dev, zero_start);
+  if (rc != FFTC_OK) return rc;
+  hipStream_t s = h->stream;
+  int chunk = 4;
+  DevState out{};
+  for (;;) {
+    for (int t = 0; t < chunk; ++t) enqueue_iter(h);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(&out, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (out.done) break;
+    chunk = std::min(64, chunk * 2);
   }
-  if (out.status == ST_NAN) return fail(h, FFTC_E_NAN, "non-finite iterate");
-  if (out.status != ST_CONVERGED) return fail(h, FFTC_E_NOCONV, "maximum number of iterations reached");
-  return FFTC_OK;
+  return solve_finish(h, u_dev, rep);
 }
 
 template <typename T>
@@ -1097,11 +1084,133 @@ int fftc_set_stiffness(fftc_h h, const double* lam, const double* mu) {
 int fftc_solve(fftc_h h, double* u_dev, int32_t zero_start, fftc_report* rep) {
   if (!h) return FFTC_E_ARG;
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set before solving");
-  // FP32: residual-form iteration (FP64 displacement), except for ACV_U
-  h->delta_mode = (h->precision == FFTC_FP32 && h->cfg.acv != FFTC_ACV_U) ? 1 : 0;
-  return h->precision == FFTC_FP64 ? solve_t<double>(h, u_dev, zero_start, rep)
-                                   : solve_t<float>(h, u_dev, zero_start, rep);
+  return solve_all(h, u_dev, zero_start, rep);
 }
+
+int fftc_batch_create(fftc_batch_h* out, int32_t count, const fftc_h* cells, void* stream) {
+  if (!out || count < 1 || !cells) return FFTC_E_ARG;
+  *out = nullptr;
+  for (int c = 0; c < count; ++c)
+    if (!cells[c] || !cells[c]->bound || !cells[c]->stiff_set) return FFTC_E_STATE;
+  fftc_batch* b = new (std::nothrow) fftc_batch();
+  if (!b) return FFTC_E_ARG;
+  b->cells.assign(cells, cells + count);
+  b->origin = (hipStream_t)stream;
+  const int K = std::min(count, 16);
+  b->streams.resize(K);
+  b->join.resize(K);
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+  for (int k = 0; k < K && ok; ++k) {
+    ok = hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipHostMalloc((void**)&b->pinned, sizeof(DevState) * count, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    fftc_batch_destroy(b);
+    return FFTC_E_HIP;
+  }
+  *out = b;
+  return FFTC_OK;
+}
+
+void fftc_batch_destroy(fftc_batch_h b) {
+  if (!b) return;
+  for (auto s : b->streams)
+    if (s) hipStreamDestroy(s);
+  for (auto e : b->join)
+    if (e) hipEventDestroy(e);
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->ready) hipEventDestroy(b->ready);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->pinned) hipHostFree(b->pinned);
+  delete b;
+}
+
+int fftc_batch_solve(fftc_batch_h b, double* const* u_dev, int32_t zero_start, fftc_report* reps) {
+  if (!b) return FFTC_E_ARG;
+  const int n = (int)b->cells.size();
+  const int K = (int)b->streams.size();
+  hipStream_t s0 = b->origin;
+  std::vector<hipStream_t> saved(n);
+  for (int c = 0; c < n; ++c) {
+    saved[c] = b->cells[c]->stream;
+    b->cells[c]->stream = s0;
+  }
+  auto restore = [&]() {
+    for (int c = 0; c < n; ++c) b->cells[c]->stream = saved[c];
+  };
+#define BCHK(call)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      restore();                                                                                \
+      b->err = std::string("HIP: ") + hipGetErrorString(e_);                                    \
+      return FFTC_E_HIP;                                                                        \
+    }                                                                                           \
+  } while (0)
+  // initial projections and device states, on the origin stream
+  for (int c = 0; c < n; ++c) {
+    const int rc = solve_init(b->cells[c], u_dev ? u_dev[c] : nullptr, zero_start || !u_dev);
+    if (rc != FFTC_OK) {
+      restore();
+      b->err = "cell " + std::to_string(c) + ": " + b->cells[c]->err;
+      return rc;
+    }
+  }
+  // capture iters_per_graph iterations of every cell; cells run as parallel branches
+  BCHK(hipEventRecord(b->ready, s0));
+  BCHK(hipStreamWaitEvent(b->cap, b->ready, 0));
+  const hipStream_t user = s0;
+  s0 = b->cap;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BCHK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+  BCHK(hipEventRecord(b->fork, s0));
+  for (int k = 0; k < K; ++k) BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0));
+  for (int c = 0; c < n; ++c) {
+    fftc_problem* h = b->cells[c];
+    h->stream = b->streams[c % K];
+    for (int it = 0; it < b->iters_per_graph; ++it) enqueue_iter(h);
+    h->stream = s0;
+  }
+  for (int k = 0; k < K; ++k) {
+    BCHK(hipEventRecord(b->join[k], b->streams[k]));
+    BCHK(hipStreamWaitEvent(s0, b->join[k], 0));
+  }
+  BCHK(hipStreamEndCapture(s0, &graph));
+  BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  // replay until every cell has set its done flag (each stops at its own max_iter at the latest)
+  int chunk = 1;
+  for (;;) {
+    for (int t = 0; t < chunk; ++t) BCHK(hipGraphLaunch(exec, s0));
+    for (int c = 0; c < n; ++c)
+      BCHK(hipMemcpyAsync(&b->pinned[c], b->cells[c]->st, sizeof(DevState), hipMemcpyDeviceToHost, s0));
+    BCHK(hipStreamSynchronize(s0));
+    bool all = true;
+    for (int c = 0; c < n; ++c) all = all && b->pinned[c].done;
+    if (all) break;
+    chunk = std::min(16, chunk * 2);
+  }
+  hipGraphExecDestroy(exec);
+  hipGraphDestroy(graph);
+  s0 = user;   // the replay stream is idle (synchronised above)
+  int worst = FFTC_OK;
+  for (int c = 0; c < n; ++c) {
+    const int rc = solve_finish(b->cells[c], u_dev ? u_dev[c] : nullptr, reps ? &reps[c] : nullptr);
+    if (rc == FFTC_E_HIP) {
+      restore();
+      return rc;
+    }
+    if (rc != FFTC_OK && worst == FFTC_OK) worst = rc;
+  }
+#undef BCHK
+  restore();
+  return worst;
+}
+
+const char* fftc_batch_last_error(fftc_batch_h b) { return b ? b->err.c_str() : "null batch"; }
 
 int fftc_get_reactions(fftc_h h, double* per_dof, double* per_rel, double* totals, int32_t nsets) {
   if (!h) return FFTC_E_ARG;

@@ -1,0 +1,71 @@
+"""Batched form: many uneven cells in one captured graph; equal to solo solves and to the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.solver import Solver as OSolver
+
+pytestmark = pytest.mark.gpu
+
+_REF = {}
+
+
+SIZES = [(16, 16, 16), (20, 12, 16), (32, 16, 24), (16, 10, 48)]
+
+
+def _cell(seed, n):
+    """Uneven cell: heterogeneous stiffness, random face BCs (>= 1 Dirichlet face per
+    component), one strong patch on a Neumann face."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    lam = rng.uniform(0.5, 5.0, (nz, ny, nx)); mu = rng.uniform(0.3, 3.0, (nz, ny, nx))
+    while True:
+        bc = (rng.random((3, 3, 2)) < 0.5).astype(np.int8)
+        if all(bc[c].any() for c in range(3)) and (bc[:, 2, 1] == 0).any():
+            break
+    c = int(np.flatnonzero(bc[:, 2, 1] == 0)[0])
+    xs, ys = np.meshgrid(np.arange(3, nx - 3), np.arange(3, ny - 3), indexing="ij")
+    nodes = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, nz)], -1)
+    strong = [W.Strong(nodes, np.full(len(nodes), c, np.int8), np.full(len(nodes), 1e-3 * nz))]
+    return W.Problem(f"cell{seed}", n, lam, mu, bc, strong=strong, r0_factor=1.0, tol=1e-6)
+
+
+def _cells():
+    return [_cell(9000 + c, n) for c, n in enumerate(SIZES)]
+
+
+def _oracle(c, prob):
+    if c not in _REF:
+        _REF[c] = OSolver.from_problem(prob).solve(tol=1e-9, max_iter=5000)["u"]
+    return _REF[c]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_solo_and_oracle(prec):
+    import paper_2607_26082_amd as F
+    import torch
+    cells = _cells()
+    print(f"[batch] {prec} sizes {[c.n for c in cells]}", flush=True)
+    solvers = [F.Solver.from_problem(p, precision=prec, tol=1e-6 if prec == "fp32" else 1e-10, max_iter=3000)
+               for p in cells]
+    solo_u, solo_it = [], []
+    for s in solvers:
+        rc, rep = s.solve()
+        assert rc == 0
+        solo_u.append(s.u.clone())
+        solo_it.append(rep.iterations)
+        s.u.zero_()
+    batch = F.Batch(solvers)
+    rc, reps = batch.solve()
+    torch.cuda.synchronize()
+    assert rc == 0
+    for c, (s, r) in enumerate(zip(solvers, reps)):
+        assert r.status == 0 and r.iterations == solo_it[c]
+        assert torch.equal(s.u, solo_u[c]), f"cell {c} differs from its solo solve"
+    for c, (p, s) in enumerate(zip(cells, solvers)):
+        ref = _oracle(c, p)
+        u = s.u.cpu().numpy()
+        # the FP64 batch is checked bitwise against its solo solves above; here both
+        # sides are converged solutions (oracle at 1e-9)
+        tol = 1e-5 if prec == "fp32" else 1e-7
+        assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref), f"cell {c}"

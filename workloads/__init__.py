@@ -96,7 +96,9 @@ def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries
     nx, ny, nz = n
     L = float(min(n))
     mask = np.zeros((nz, ny, nx), dtype=bool)
-    centers, radii = [], []
+    cap = 1024
+    centers, radii = np.zeros((cap, 3)), np.zeros(cap)
+    k = 0
     total = nx * ny * nz
     count = 0
     for _ in range(max_tries):
@@ -104,15 +106,15 @@ def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries
             break
         r = rng.uniform(rmin_frac * L, rmax_frac * L)
         c = rng.uniform([0.0, 0.0, 0.0], [nx, ny, nz])
-        ok = True
-        for cc, rr in zip(centers, radii):
-            if np.sum((cc - c) ** 2) < (rr + r) ** 2:
-                ok = False
-                break
-        if not ok:
+        if k and np.any(np.sum((centers[:k] - c) ** 2, axis=1) < (radii[:k] + r) ** 2):
             continue
-        centers.append(c)
-        radii.append(r)
+        if k == cap:
+            cap *= 2
+            centers = np.concatenate([centers, np.zeros((cap - k, 3))])
+            radii = np.concatenate([radii, np.zeros(cap - k)])
+        centers[k] = c
+        radii[k] = r
+        k += 1
         lo = np.maximum(np.floor(c - r).astype(int), 0)
         hi = np.minimum(np.ceil(c + r).astype(int) + 1, [nx, ny, nz])
         xs = np.arange(lo[0], hi[0]) + 0.5
