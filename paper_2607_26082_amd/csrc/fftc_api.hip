@@ -1159,42 +1159,86 @@ int fftc_batch_solve(fftc_batch_h b, double* const* u_dev, int32_t zero_start, f
       return rc;
     }
   }
-  // capture iters_per_graph iterations of every cell; cells run as parallel branches
+  // Capture iters_per_graph iterations of the unfinished cells as parallel branches.  The
+  // graph is captured again whenever the set of unfinished cells shrinks, so finished cells
+  // cost no launches.  Cells go to branches largest first, each to the least loaded branch.
   BCHK(hipEventRecord(b->ready, s0));
   BCHK(hipStreamWaitEvent(b->cap, b->ready, 0));
   const hipStream_t user = s0;
   s0 = b->cap;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  BCHK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
-  BCHK(hipEventRecord(b->fork, s0));
-  for (int k = 0; k < K; ++k) BCHK(hipStreamWaitEvent(b->streams[k], b->fork, 0));
-  for (int c = 0; c < n; ++c) {
-    fftc_problem* h = b->cells[c];
-    h->stream = b->streams[c % K];
-    for (int it = 0; it < b->iters_per_graph; ++it) enqueue_iter(h);
-    h->stream = s0;
-  }
-  for (int k = 0; k < K; ++k) {
-    BCHK(hipEventRecord(b->join[k], b->streams[k]));
-    BCHK(hipStreamWaitEvent(s0, b->join[k], 0));
-  }
-  BCHK(hipStreamEndCapture(s0, &graph));
-  BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  auto release = [&]() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  std::vector<int> order(n);
+  for (int c = 0; c < n; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return b->cells[a]->g.Nv > b->cells[c]->g.Nv; });
+  std::vector<char> active(n, 1);
+  auto capture = [&]() -> hipError_t {
+    release();
+    const int nb = std::min(K, (int)std::count(active.begin(), active.end(), 1));
+    std::vector<double> load(nb, 0.0);
+    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipEventRecord(b->fork, s0);
+    for (int k = 0; k < nb; ++k) hipStreamWaitEvent(b->streams[k], b->fork, 0);
+    for (int c : order) {
+      if (!active[c]) continue;
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += (double)b->cells[c]->g.Nv;
+      fftc_problem* h = b->cells[c];
+      h->stream = b->streams[k];
+      for (int it = 0; it < b->iters_per_graph; ++it) enqueue_iter(h);
+      h->stream = s0;
+    }
+    for (int k = 0; k < nb; ++k) {
+      hipEventRecord(b->join[k], b->streams[k]);
+      hipStreamWaitEvent(s0, b->join[k], 0);
+    }
+    e = hipStreamEndCapture(s0, &graph);
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  };
+#undef BCHK
+#define BCHK(call)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      release();                                                                                \
+      restore();                                                                                \
+      b->err = std::string("HIP: ") + hipGetErrorString(e_);                                    \
+      return FFTC_E_HIP;                                                                        \
+    }                                                                                           \
+  } while (0)
+  BCHK(capture());
   // replay until every cell has set its done flag (each stops at its own max_iter at the latest)
   int chunk = 1;
   for (;;) {
     for (int t = 0; t < chunk; ++t) BCHK(hipGraphLaunch(exec, s0));
     for (int c = 0; c < n; ++c)
-      BCHK(hipMemcpyAsync(&b->pinned[c], b->cells[c]->st, sizeof(DevState), hipMemcpyDeviceToHost, s0));
+      if (active[c])
+        BCHK(hipMemcpyAsync(&b->pinned[c], b->cells[c]->st, sizeof(DevState), hipMemcpyDeviceToHost, s0));
     BCHK(hipStreamSynchronize(s0));
-    bool all = true;
-    for (int c = 0; c < n; ++c) all = all && b->pinned[c].done;
-    if (all) break;
-    chunk = std::min(16, chunk * 2);
+    bool changed = false;
+    for (int c = 0; c < n; ++c)
+      if (active[c] && b->pinned[c].done) {
+        active[c] = 0;
+        changed = true;
+      }
+    if (std::count(active.begin(), active.end(), 1) == 0) break;
+    if (changed) {
+      BCHK(capture());
+      chunk = 1;
+    } else {
+      chunk = std::min(16, chunk * 2);
+    }
   }
-  hipGraphExecDestroy(exec);
-  hipGraphDestroy(graph);
+  release();
   s0 = user;   // the replay stream is idle (synchronised above)
   int worst = FFTC_OK;
   for (int c = 0; c < n; ++c) {

@@ -20,6 +20,7 @@ from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
+from scipy.spatial import cKDTree
 
 BC_N, BC_D, BC_P = 0, 1, 2
 BASE_SEED = 260726082
@@ -90,42 +91,62 @@ def bc_table(default=BC_N):
 # Random two-phase microstructures (non-overlapping spheres)
 # ---------------------------------------------------------------------------
 
-def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries=100000):
+def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries=100000, block=512):
     """Place non-overlapping spheres uniformly in the cell until the voxelised
-    inclusion fraction reaches phi_target.  Returns (mask [nz,ny,nx] bool, phi)."""
+    inclusion fraction reaches phi_target.  Returns (mask [nz,ny,nx] bool, phi).
+
+    Candidates (radius, centre) are drawn in blocks and accepted in draw order: a
+    candidate is kept if it overlaps no sphere kept before it."""
     nx, ny, nz = n
     L = float(min(n))
     mask = np.zeros((nz, ny, nx), dtype=bool)
-    cap = 1024
-    centers, radii = np.zeros((cap, 3)), np.zeros(cap)
-    k = 0
+    centers = np.zeros((0, 3))
+    radii = np.zeros(0)
     total = nx * ny * nz
     count = 0
-    for _ in range(max_tries):
-        if count >= phi_target * total:
-            break
-        r = rng.uniform(rmin_frac * L, rmax_frac * L)
-        c = rng.uniform([0.0, 0.0, 0.0], [nx, ny, nz])
-        if k and np.any(np.sum((centers[:k] - c) ** 2, axis=1) < (radii[:k] + r) ** 2):
-            continue
-        if k == cap:
-            cap *= 2
-            centers = np.concatenate([centers, np.zeros((cap - k, 3))])
-            radii = np.concatenate([radii, np.zeros(cap - k)])
-        centers[k] = c
-        radii[k] = r
-        k += 1
-        lo = np.maximum(np.floor(c - r).astype(int), 0)
-        hi = np.minimum(np.ceil(c + r).astype(int) + 1, [nx, ny, nz])
-        xs = np.arange(lo[0], hi[0]) + 0.5
-        ys = np.arange(lo[1], hi[1]) + 0.5
-        zs = np.arange(lo[2], hi[2]) + 0.5
-        d2 = ((zs[:, None, None] - c[2]) ** 2 + (ys[None, :, None] - c[1]) ** 2
-              + (xs[None, None, :] - c[0]) ** 2)
-        sub = mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-        newly = (d2 < r * r) & ~sub
-        count += int(newly.sum())
-        sub |= d2 < r * r
+    tries = 0
+    while tries < max_tries and count < phi_target * total:
+        m = min(block, max_tries - tries)
+        tries += m
+        u = rng.random((m, 4))
+        r = rmin_frac * L + (rmax_frac - rmin_frac) * L * u[:, 0]
+        c = u[:, 1:] * np.array([nx, ny, nz], dtype=np.float64)
+        ok = np.ones(m, bool)
+        if len(radii):
+            # Neighbours within r + max(radii) hold every sphere the candidate can touch.
+            pairs = cKDTree(c).sparse_distance_matrix(cKDTree(centers), r.max() + radii.max(),
+                                                       output_type="ndarray")
+            hit = pairs["v"] < r[pairs["i"]] + radii[pairs["j"]]
+            ok[pairs["i"][hit]] = False
+        cand = np.flatnonzero(ok)
+        cc, rc = c[cand], r[cand]
+        clash = (((cc[:, None, :] - cc[None, :, :]) ** 2).sum(-1)
+                 < (rc[:, None] + rc[None, :]) ** 2)
+        taken = np.zeros(len(cand), bool)
+        new_c, new_r = [], []
+        for k in range(len(cand)):
+            if count >= phi_target * total:
+                break
+            if np.any(clash[k, :k] & taken[:k]):
+                continue
+            taken[k] = True
+            cq, rq = cc[k], rc[k]
+            new_c.append(cq)
+            new_r.append(rq)
+            lo = np.maximum(np.floor(cq - rq).astype(int), 0)
+            hi = np.minimum(np.ceil(cq + rq).astype(int) + 1, [nx, ny, nz])
+            xs = np.arange(lo[0], hi[0]) + 0.5
+            ys = np.arange(lo[1], hi[1]) + 0.5
+            zs = np.arange(lo[2], hi[2]) + 0.5
+            d2s = ((zs[:, None, None] - cq[2]) ** 2 + (ys[None, :, None] - cq[1]) ** 2
+                   + (xs[None, None, :] - cq[0]) ** 2)
+            sub = mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+            inside = d2s < rq * rq
+            count += int((inside & ~sub).sum())
+            sub |= inside
+        if new_r:
+            centers = np.concatenate([centers, np.array(new_c)])
+            radii = np.concatenate([radii, np.array(new_r)])
     return mask, count / total
 
 
