@@ -91,7 +91,8 @@ def bc_table(default=BC_N):
 # Random two-phase microstructures (non-overlapping spheres)
 # ---------------------------------------------------------------------------
 
-def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries=100000, block=512):
+def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries=100000, block=512,
+                   return_geometry=False):
     """Place non-overlapping spheres uniformly in the cell until the voxelised
     inclusion fraction reaches phi_target.  Returns (mask [nz,ny,nx] bool, phi).
 
@@ -147,7 +148,25 @@ def random_spheres(rng, n, phi_target, rmin_frac=0.02, rmax_frac=0.10, max_tries
         if new_r:
             centers = np.concatenate([centers, np.array(new_c)])
             radii = np.concatenate([radii, np.array(new_r)])
+    if return_geometry:
+        return mask, count / total, centers, radii
     return mask, count / total
+
+
+def voxelize_spheres(centers, radii, n):
+    """Voxels whose centre lies inside one of the spheres (same rule as random_spheres)."""
+    nx, ny, nz = n
+    mask = np.zeros((nz, ny, nx), dtype=bool)
+    for cq, rq in zip(centers, radii):
+        lo = np.maximum(np.floor(cq - rq).astype(int), 0)
+        hi = np.minimum(np.ceil(cq + rq).astype(int) + 1, [nx, ny, nz])
+        xs = np.arange(lo[0], hi[0]) + 0.5
+        ys = np.arange(lo[1], hi[1]) + 0.5
+        zs = np.arange(lo[2], hi[2]) + 0.5
+        d2s = ((zs[:, None, None] - cq[2]) ** 2 + (ys[None, :, None] - cq[1]) ** 2
+               + (xs[None, None, :] - cq[0]) ** 2)
+        mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] |= d2s < rq * rq
+    return mask
 
 
 def two_phase_lame(mask, contrast, nu=0.3):
@@ -266,6 +285,92 @@ def random_cell(seed, n=None, edges=(32, 48, 64, 96, 128), with_patches=True):
 
 def c4_batch(count=64, base_seed=BASE_SEED):
     return [random_cell(base_seed + c) for c in range(count)]
+
+
+def nn_case(seed, kind=None, scale=1, n0=(64, 64, 64)):
+    """Case for the learned warm start: a two-phase cell as in the batched workload,
+    drawn at n0 and voxelised at scale * n0 (geometry scaled with it).
+
+    kind "patch": random DTT face BCs and 1-4 local Dirichlet patches;
+    kind "indent": bottom face fixed, other faces traction-free, rigid sphere of
+    radius 0.75 nz pressed into the top face to depth d, d/R ~ U[0.002, 0.03].
+    Without kind, even seeds give patch cases and odd seeds indentation cases."""
+    rng = np.random.default_rng(seed)
+    if kind is None:
+        kind = "patch" if seed % 2 == 0 else "indent"
+    k = int(scale)
+    n = tuple(int(v) * k for v in n0)
+    L0 = min(n0)
+    phi = rng.uniform(0.1, 0.4)
+    mask0, phi_got, cen, rad = random_spheres(rng, n0, phi, return_geometry=True)
+    contrast = float(np.exp(rng.uniform(np.log(2.0), np.log(100.0))))
+    mask = mask0 if k == 1 else voxelize_spheres(cen * k, rad * k, n)
+    lam, mu = two_phase_lame(mask, contrast)
+    meta = {"phi": phi_got, "contrast": contrast, "kind": kind, "scale": k}
+    if kind == "indent":
+        bc = bc_table(BC_N)
+        bc[:, 2, 0] = BC_D
+        R0 = 0.75 * n0[2]
+        d0 = rng.uniform(0.002, 0.03) * R0
+        sph = Sphere(np.array([n[0] / 2.0, n[1] / 2.0, n[2] + k * (R0 - d0)]), k * R0, face=5)
+        meta["d_over_R"] = d0 / R0
+        return Problem("C5-indent", n, lam, mu, bc, sphere=sph, r0_factor=5.0, tol=1e-6,
+                       max_iter=4000, meta=meta)
+    while True:
+        bc = (rng.random((3, 3, 2)) < 0.5).astype(np.int8)
+        if all(bc[c].any() for c in range(3)):
+            break
+    strong, used = [], []
+    for p in range(int(rng.integers(1, 5))):
+        for _ in range(100):
+            s = int(rng.integers(4, 17))
+            axis = int(rng.integers(0, 3))
+            side = int(rng.integers(0, 2))
+            comps = [c for c in range(3) if bc[c, axis, side] == BC_N]
+            if not comps:
+                continue
+            ta, tb = [a for a in range(3) if a != axis]
+            if s + 1 > min(n0[ta], n0[tb]) - 1:
+                continue
+            oa = int(rng.integers(1, n0[ta] - s))
+            ob = int(rng.integers(1, n0[tb] - s))
+            if any(u[0] == axis and u[1] == side and not (oa + s < u[2] or u[2] + u[4] < oa
+                                                          or ob + s < u[3] or u[3] + u[4] < ob)
+                   for u in used):
+                continue
+            used.append((axis, side, oa, ob, s))
+            # s nodes span s-1 voxels at n0; the scaled patch spans k (s-1) voxels
+            m = k * (s - 1) + 1
+            aa, bb = np.meshgrid(np.arange(k * oa, k * oa + m), np.arange(k * ob, k * ob + m), indexing="ij")
+            idx = np.zeros((m * m, 3), np.int64)
+            idx[:, ta] = aa.ravel()
+            idx[:, tb] = bb.ravel()
+            idx[:, axis] = 0 if side == 0 else n[axis]
+            for c in comps:
+                val = k * rng.uniform(-1.0, 1.0) * 1e-3 * L0 / np.sqrt(3.0)
+                strong.append(Strong(idx.copy(), np.full(len(idx), c, np.int8),
+                                     np.full(len(idx), val), set_id=len(strong)))
+            break
+    return Problem("C5-patch", n, lam, mu, bc, strong=strong, r0_factor=1.0, tol=1e-6,
+                   max_iter=4000, meta=meta)
+
+
+NN_TRAIN_SEED = BASE_SEED + 1_000_000
+NN_EVAL_SEED = BASE_SEED + 2_000_000
+
+
+def nn_init(seed, shapes):
+    """Initial network parameters, flat float64: arrays of rank >= 2 drawn from
+    N(0, 1/fan_in) with fan_in the last extent; rank-1 arrays (biases) zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in shapes:
+        s = tuple(s)
+        if len(s) >= 2:
+            out.append(rng.standard_normal(int(np.prod(s))) / np.sqrt(s[-1]))
+        else:
+            out.append(np.zeros(int(np.prod(s))))
+    return np.concatenate(out)
 
 
 def m256_metric(n=(256, 256, 256), seed=BASE_SEED + 5_000_000, phi=0.25, contrast=10.0):
