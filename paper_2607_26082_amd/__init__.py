@@ -72,6 +72,23 @@ _SIGS = {
     "fftc_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.c_int32, C.POINTER(fftc_report)]),
     "fftc_batch_destroy": (None, [_P]),
     "fftc_batch_last_error": (C.c_char_p, [_P]),
+    "fftc_nn_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32]),
+    "fftc_nn_destroy": (None, [_P]),
+    "fftc_nn_num_params": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "fftc_nn_state_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "fftc_nn_bind_state": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "fftc_nn_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_size_t)]),
+    "fftc_nn_bind": (C.c_int, [_P, C.POINTER(C.c_int32), C.c_int32, _P, C.c_size_t, _P]),
+    "fftc_nn_set_params": (C.c_int, [_P, _P]),
+    "fftc_nn_get_params": (C.c_int, [_P, _P]),
+    "fftc_nn_get_grad": (C.c_int, [_P, _P]),
+    "fftc_nn_features": (C.c_int, [_P, _P]),
+    "fftc_nn_forward": (C.c_int, [_P, _P, _P, C.c_double, _P]),
+    "fftc_nn_train_step": (C.c_int, [_P, _P, _P, _P]),
+    "fftc_nn_adam_step": (C.c_int, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "fftc_nn_last_error": (C.c_char_p, [_P]),
+    "fftc_solve_judged": (C.c_int, [_P, _P, _P, C.POINTER(fftc_report), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double)]),
     "fftc_status_str": (C.c_char_p, [C.c_int]),
     "fftc_last_error": (C.c_char_p, [_P]),
 }
@@ -292,6 +309,166 @@ class Batch:
 
 
 # ---------------------------------------------------------------------------
+# learned warm start (include/fftc_nn.h)
+# ---------------------------------------------------------------------------
+
+FFTC_NN_CHANNELS = 16
+
+
+def _nncheck(nn, rc, what):
+    if rc != FFTC_OK:
+        raise FftcError(rc, f"{what}: " + load().fftc_nn_last_error(nn).decode())
+
+
+def fftc_nn_create(modes=6, blocks=4):
+    h = C.c_void_p()
+    rc = load().fftc_nn_create(C.byref(h), int(modes), int(blocks))
+    if rc != FFTC_OK:
+        raise FftcError(rc, "fftc_nn_create")
+    return h
+
+
+def fftc_nn_destroy(nn):
+    load().fftc_nn_destroy(nn)
+
+
+def fftc_nn_num_params(nn):
+    c = C.c_int64()
+    _nncheck(nn, load().fftc_nn_num_params(nn, C.byref(c)), "fftc_nn_num_params")
+    return c.value
+
+
+def fftc_nn_state_bytes(nn):
+    b = C.c_size_t()
+    _nncheck(nn, load().fftc_nn_state_bytes(nn, C.byref(b)), "fftc_nn_state_bytes")
+    return b.value
+
+
+def fftc_nn_bind_state(nn, state_dev, nbytes, stream):
+    _nncheck(nn, load().fftc_nn_bind_state(nn, _dev(state_dev), nbytes, C.c_void_p(stream)), "fftc_nn_bind_state")
+
+
+def fftc_nn_workspace_bytes(nn, N, training):
+    b = C.c_size_t()
+    Na = (C.c_int32 * 3)(*[int(v) for v in N])
+    _nncheck(nn, load().fftc_nn_workspace_bytes(nn, Na, int(training), C.byref(b)), "fftc_nn_workspace_bytes")
+    return b.value
+
+
+def fftc_nn_bind(nn, N, training, ws_dev, nbytes, stream):
+    Na = (C.c_int32 * 3)(*[int(v) for v in N])
+    _nncheck(nn, load().fftc_nn_bind(nn, Na, int(training), _dev(ws_dev), nbytes, C.c_void_p(stream)),
+             "fftc_nn_bind")
+
+
+def fftc_nn_set_params(nn, params_dev):
+    _nncheck(nn, load().fftc_nn_set_params(nn, _dev(params_dev)), "fftc_nn_set_params")
+
+
+def fftc_nn_get_params(nn, params_dev):
+    _nncheck(nn, load().fftc_nn_get_params(nn, _dev(params_dev)), "fftc_nn_get_params")
+
+
+def fftc_nn_get_grad(nn, grad_dev):
+    _nncheck(nn, load().fftc_nn_get_grad(nn, _dev(grad_dev)), "fftc_nn_get_grad")
+
+
+def fftc_nn_features(h, feat_dev):
+    _check(h, load().fftc_nn_features(h, _dev(feat_dev)), "fftc_nn_features")
+
+
+def fftc_nn_forward(nn, feat_dev, y_dev=None, s_u=1.0, u0_dev=None):
+    _nncheck(nn, load().fftc_nn_forward(nn, _dev(feat_dev), _dev(y_dev), float(s_u), _dev(u0_dev)),
+             "fftc_nn_forward")
+
+
+def fftc_nn_train_step(nn, feat_dev, target_dev, loss_dev=None):
+    _nncheck(nn, load().fftc_nn_train_step(nn, _dev(feat_dev), _dev(target_dev), _dev(loss_dev)),
+             "fftc_nn_train_step")
+
+
+def fftc_nn_adam_step(nn, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _nncheck(nn, load().fftc_nn_adam_step(nn, float(lr), float(beta1), float(beta2), float(eps)),
+             "fftc_nn_adam_step")
+
+
+def fftc_solve_judged(h, u0_dev, u_dev):
+    rep = fftc_report()
+    used = C.c_int32()
+    res = (C.c_double * 2)()
+    rc = load().fftc_solve_judged(h, _dev(u0_dev), _dev(u_dev), C.byref(rep), C.byref(used), res)
+    _check(h, rc, "fftc_solve_judged", allow=(FFTC_E_NOCONV, FFTC_E_NAN))
+    return rc, rep, bool(used.value), (res[0], res[1])
+
+
+class Net:
+    """Warm-start network on the current device: handle + torch-owned state buffer."""
+
+    def __init__(self, modes=6, blocks=4, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.h = fftc_nn_create(modes, blocks)
+        self.modes, self.blocks = modes, blocks
+        self.P = fftc_nn_num_params(self.h)
+        nb = fftc_nn_state_bytes(self.h)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.state = _aligned(torch, nb, self.device)
+        fftc_nn_bind_state(self.h, self.state, nb, self.stream.cuda_stream)
+        self.grid = None
+        self.ws = None
+
+    def bind(self, N, training=False):
+        N = tuple(int(v) for v in N)
+        if self.grid == (N, bool(training)):
+            return
+        nb = fftc_nn_workspace_bytes(self.h, N, training)
+        self.ws = _aligned(self.torch, nb, self.device)
+        fftc_nn_bind(self.h, N, training, self.ws, nb, self.stream.cuda_stream)
+        self.grid = (N, bool(training))
+
+    def set_params(self, vec):
+        t = self.torch.as_tensor(np.ascontiguousarray(vec, np.float32), device=self.device)
+        fftc_nn_set_params(self.h, t)
+        self.stream.synchronize()
+
+    def params(self):
+        t = self.torch.empty(self.P, dtype=self.torch.float32, device=self.device)
+        fftc_nn_get_params(self.h, t)
+        return t
+
+    def grad(self):
+        t = self.torch.empty(self.P, dtype=self.torch.float32, device=self.device)
+        fftc_nn_get_grad(self.h, t)
+        return t
+
+    def forward(self, feat, s_u=1.0, u0=None):
+        y = self.torch.empty((feat.shape[0], 3), dtype=self.torch.float32, device=self.device)
+        fftc_nn_forward(self.h, feat, y, s_u, u0)
+        return y
+
+    def train_step(self, feat, target, loss=None):
+        fftc_nn_train_step(self.h, feat, target, loss)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        fftc_nn_adam_step(self.h, lr, beta1, beta2, eps)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                fftc_nn_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _aligned(torch, nbytes, device):
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+# ---------------------------------------------------------------------------
 # convenience wrapper
 # ---------------------------------------------------------------------------
 
@@ -347,6 +524,15 @@ class Solver:
     def solve(self, zero_start=True):
         rc, rep = fftc_solve(self.h, self.u, zero_start)
         return rc, rep
+
+    def features(self):
+        """Network input channels, BF16 bits as int16 [Nn][16]."""
+        t = self.torch.empty((int(np.prod(self.N)), FFTC_NN_CHANNELS), dtype=self.torch.int16, device=self.device)
+        fftc_nn_features(self.h, t)
+        return t
+
+    def solve_judged(self, u0):
+        return fftc_solve_judged(self.h, u0, self.u)
 
     def move_sphere(self, center):
         fftc_move_sphere(self.h, center)

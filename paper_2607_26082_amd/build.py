@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("fftc_kernels.hip", "fftc_api.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("fftc_kernels.hip", "fftc_api.hip", "fftc_nn.hip")]
 OUT = os.path.join(HERE, "libfftc.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

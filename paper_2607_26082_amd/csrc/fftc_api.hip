@@ -9,8 +9,10 @@
 #include <vector>
 
 #include "../../include/fftc.h"
+#include "../../include/fftc_nn.h"
 #include "fftc_internal.h"
 #include "fftc_launch.h"
+#include "fftc_nn_internal.h"
 
 using namespace fftc;
 
@@ -1252,6 +1254,73 @@ int fftc_batch_solve(fftc_batch_h b, double* const* u_dev, int32_t zero_start, f
 #undef BCHK
   restore();
   return worst;
+}
+
+int fftc_nn_features(fftc_h h, uint16_t* feat_dev) {
+  if (!h || !feat_dev) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set first");
+  nnk::FeatArgs a{};
+  for (int J = 0; J < 3; ++J) {
+    a.n[J] = h->n[J];
+    a.N[J] = h->N[J];
+    a.periodic[J] = h->periodic[J];
+    a.center[J] = h->center[J];
+  }
+  a.Nn = h->Nn;
+  a.Nv = h->Nv;
+  a.aface = h->g.aface;
+  a.lam = h->lam;
+  a.mu = h->mu;
+  a.fp64 = h->precision == FFTC_FP64;
+  a.mask = h->mask;
+  a.ms = (long long)h->s_comp.size();
+  a.snode = h->d_snode;
+  a.scomp = h->d_scomp;
+  a.sval = h->d_sval;
+  a.s_u = 1e-3 * (double)std::min(h->n[0], std::min(h->n[1], h->n[2]));
+  a.has_sphere = h->has_sphere;
+  a.radius = h->radius;
+  a.face = h->face;
+  a.scratch = h->gpart;
+  a.feat = feat_dev;
+  nnk::launch_features(a, h->stream);
+  HIPCHK(h, hipGetLastError());
+  return FFTC_OK;
+}
+
+namespace {
+
+// Equilibrium residual of a start: the solver's own initialisation (proj_U, contact set),
+// then one iteration, whose convergence test measures the start.
+int start_residual(fftc_problem* h, const double* u0, double* res) {
+  int rc = solve_init(h, u0, u0 ? 0 : 1);
+  if (rc != FFTC_OK) return rc;
+  enqueue_iter(h);
+  HIPCHK(h, hipMemcpyAsync(&h->last, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *res = h->last.residual;
+  return FFTC_OK;
+}
+
+}  // namespace
+
+int fftc_solve_judged(fftc_h h, const double* u0_dev, double* u_dev, fftc_report* rep, int32_t* used_u0,
+                      double* residual_host) {
+  if (!h || !u_dev) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set before solving");
+  double r_nn = INFINITY, r_plain = INFINITY;
+  int rc;
+  if (u0_dev && (rc = start_residual(h, u0_dev, &r_nn)) != FFTC_OK) return rc;
+  if ((rc = start_residual(h, nullptr, &r_plain)) != FFTC_OK) return rc;
+  const int use = (u0_dev && r_nn < r_plain) ? 1 : 0;   // a non-finite r_nn falls back
+  if (used_u0) *used_u0 = use;
+  if (residual_host) {
+    residual_host[0] = r_nn;
+    residual_host[1] = r_plain;
+  }
+  if (use && u0_dev != u_dev)
+    HIPCHK(h, hipMemcpyAsync(u_dev, u0_dev, 8 * 3 * (size_t)h->Nn, hipMemcpyDeviceToDevice, h->stream));
+  return solve_all(h, u_dev, use ? 0 : 1, rep);
 }
 
 const char* fftc_batch_last_error(fftc_batch_h b) { return b ? b->err.c_str() : "null batch"; }
