@@ -37,8 +37,8 @@
  *   0 E / max E, E averaged over the voxels around the node; 1 nu averaged
  *   likewise; 2-4 per component 1 where the DOF is prescribed (Dirichlet
  *   face or strong constraint); 5-7 per component prescribed value / s_u;
- *   8 on the contact face of a rigid sphere clamp((|X - O| - R) / R, -1, 1),
- *   else 0.
+ *   8 on the contact face of a rigid sphere tanh(g / (8 s_u)) with g = |X - O| - R
+ *   the gap of the undeformed node, else 0.
  *
  * Conventions are those of fftc.h: int status returns, *_dev device pointers
  * borrowed for the call, caller-owned device memory (a persistent state

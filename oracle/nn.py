@@ -32,8 +32,9 @@ Input channels (all on nodes):
   2-4  per component: 1 where the DOF is prescribed (Dirichlet face or
        strong constraint), else 0
   5-7  per component: prescribed value / s_u (0 where free)
-  8  on the contact face of a rigid sphere: clamp((|X - O| - R) / R, -1, 1);
-     0 elsewhere and without a sphere
+  8  on the contact face of a rigid sphere: tanh(g / (8 s_u)), g = |X - O| - R
+     the gap of the undeformed node, so that indentation depths of a few s_u
+     map to O(1) values; 0 elsewhere and without a sphere
 """
 from __future__ import annotations
 
@@ -267,7 +268,7 @@ def features(prob):
         idx = 0 if side == 0 else prob.n[a]
         zz, yy, xx = np.meshgrid(np.arange(Nz), np.arange(Ny), np.arange(Nx), indexing="ij")
         X = np.stack([xx, yy, zz], -1).astype(np.float64)
-        g = (np.linalg.norm(X - np.asarray(sp.center, np.float64), axis=-1) - sp.radius) / sp.radius
+        g = np.linalg.norm(X - np.asarray(sp.center, np.float64), axis=-1) - sp.radius
         on = [xx, yy, zz][a] == idx
-        f[..., 8] = np.where(on, np.clip(g, -1.0, 1.0), 0.0)
+        f[..., 8] = np.where(on, np.tanh(g / (8.0 * su)), 0.0)
     return f.reshape(-1, 9)

@@ -1094,6 +1094,9 @@ int fftc_batch_create(fftc_batch_h* out, int32_t count, const fftc_h* cells, voi
   *out = nullptr;
   for (int c = 0; c < count; ++c)
     if (!cells[c] || !cells[c]->bound || !cells[c]->stiff_set) return FFTC_E_STATE;
+  // Cells with a rigid obstacle are not batched: solve them with fftc_solve.
+  for (int c = 0; c < count; ++c)
+    if (cells[c]->has_sphere) return fail(cells[c], FFTC_E_UNSUPPORTED, "contact cells are not batched");
   fftc_batch* b = new (std::nothrow) fftc_batch();
   if (!b) return FFTC_E_ARG;
   b->cells.assign(cells, cells + count);

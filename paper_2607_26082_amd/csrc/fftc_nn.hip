@@ -595,8 +595,8 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a) {
     const int idx = (a.face % 2) ? a.n[ax] : 0;
     if (X[ax] == idx) {
       const double ddx = x - a.center[0], ddy = y - a.center[1], ddz = z - a.center[2];
-      const double g = (sqrt(ddx * ddx + ddy * ddy + ddz * ddz) - a.radius) / a.radius;
-      f[8] = (float)fmin(1.0, fmax(-1.0, g));
+      const double g = sqrt(ddx * ddx + ddy * ddy + ddz * ddz) - a.radius;
+      f[8] = (float)tanh(g / (8.0 * a.s_u));
     }
   }
   uint32_t pk[8];

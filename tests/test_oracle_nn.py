@@ -127,8 +127,8 @@ def test_features_homogeneous_indentation():
     # bottom face: every component fixed; nothing else prescribed
     assert (f[0, :, :, 2:5] == 1).all() and (f[1:, :, :, 2:5] == 0).all()
     assert not f[..., 5:8].any()
-    # top node under the sphere centre: gap = (R - d) - R, i.e. -d/R
-    assert abs(f[5, 3, 4, 8] - (-0.05)) < 1e-15
+    # top node under the sphere centre: gap = (R - d) - R = -d, d = 0.05 R = 0.2, s_u = 0.005
+    assert abs(f[5, 3, 4, 8] - np.tanh(-0.2 / 0.04)) < 1e-15
     # off the top face the channel is 0; a top corner sits outside the sphere
     assert not f[:5, :, :, 8].any() and f[5, 0, 0, 8] > 0
 

@@ -287,40 +287,26 @@ def c4_batch(count=64, base_seed=BASE_SEED):
     return [random_cell(base_seed + c) for c in range(count)]
 
 
-def nn_case(seed, kind=None, scale=1, n0=(64, 64, 64)):
-    """Case for the learned warm start: a two-phase cell as in the batched workload,
-    drawn at n0 and voxelised at scale * n0 (geometry scaled with it).
-
-    kind "patch": random DTT face BCs and 1-4 local Dirichlet patches;
-    kind "indent": bottom face fixed, other faces traction-free, rigid sphere of
-    radius 0.75 nz pressed into the top face to depth d, d/R ~ U[0.002, 0.03].
-    Without kind, even seeds give patch cases and odd seeds indentation cases."""
+def nn_case_spec(seed, kind=None, n0=(64, 64, 64)):
+    """Draws of a learned-start case at resolution n0 (geometry, material, loading);
+    nn_case_build turns them into a Problem.  Without kind, even seeds give patch
+    cases and odd seeds indentation cases."""
     rng = np.random.default_rng(seed)
     if kind is None:
         kind = "patch" if seed % 2 == 0 else "indent"
-    k = int(scale)
-    n = tuple(int(v) * k for v in n0)
-    L0 = min(n0)
     phi = rng.uniform(0.1, 0.4)
-    mask0, phi_got, cen, rad = random_spheres(rng, n0, phi, return_geometry=True)
+    _, phi_got, cen, rad = random_spheres(rng, n0, phi, return_geometry=True)
     contrast = float(np.exp(rng.uniform(np.log(2.0), np.log(100.0))))
-    mask = mask0 if k == 1 else voxelize_spheres(cen * k, rad * k, n)
-    lam, mu = two_phase_lame(mask, contrast)
-    meta = {"phi": phi_got, "contrast": contrast, "kind": kind, "scale": k}
+    spec = {"seed": int(seed), "kind": kind, "n0": tuple(int(v) for v in n0), "phi": phi_got,
+            "centers": cen, "radii": rad, "contrast": contrast}
     if kind == "indent":
-        bc = bc_table(BC_N)
-        bc[:, 2, 0] = BC_D
-        R0 = 0.75 * n0[2]
-        d0 = rng.uniform(0.002, 0.03) * R0
-        sph = Sphere(np.array([n[0] / 2.0, n[1] / 2.0, n[2] + k * (R0 - d0)]), k * R0, face=5)
-        meta["d_over_R"] = d0 / R0
-        return Problem("C5-indent", n, lam, mu, bc, sphere=sph, r0_factor=5.0, tol=1e-6,
-                       max_iter=4000, meta=meta)
+        spec["d_over_R"] = float(rng.uniform(0.002, 0.03))
+        return spec
     while True:
         bc = (rng.random((3, 3, 2)) < 0.5).astype(np.int8)
         if all(bc[c].any() for c in range(3)):
             break
-    strong, used = [], []
+    patches, used = [], []
     for p in range(int(rng.integers(1, 5))):
         for _ in range(100):
             s = int(rng.integers(4, 17))
@@ -339,20 +325,59 @@ def nn_case(seed, kind=None, scale=1, n0=(64, 64, 64)):
                    for u in used):
                 continue
             used.append((axis, side, oa, ob, s))
-            # s nodes span s-1 voxels at n0; the scaled patch spans k (s-1) voxels
-            m = k * (s - 1) + 1
-            aa, bb = np.meshgrid(np.arange(k * oa, k * oa + m), np.arange(k * ob, k * ob + m), indexing="ij")
-            idx = np.zeros((m * m, 3), np.int64)
-            idx[:, ta] = aa.ravel()
-            idx[:, tb] = bb.ravel()
-            idx[:, axis] = 0 if side == 0 else n[axis]
-            for c in comps:
-                val = k * rng.uniform(-1.0, 1.0) * 1e-3 * L0 / np.sqrt(3.0)
-                strong.append(Strong(idx.copy(), np.full(len(idx), c, np.int8),
-                                     np.full(len(idx), val), set_id=len(strong)))
+            vals = [(c, float(rng.uniform(-1.0, 1.0))) for c in comps]
+            patches.append((axis, side, oa, ob, s, vals))
             break
-    return Problem("C5-patch", n, lam, mu, bc, strong=strong, r0_factor=1.0, tol=1e-6,
+    spec["bc"] = bc
+    spec["patches"] = patches
+    return spec
+
+
+def nn_case_build(spec, scale=1):
+    """Problem of a learned-start case voxelised at scale * n0 (geometry scaled with it).
+
+    patch: the drawn DTT face BCs and 1-4 local Dirichlet patches (value
+    U[-1, 1] 1e-3 L / sqrt(3) per free component, L = min n0, scaled with the cell);
+    indent: bottom face fixed, other faces traction-free, rigid sphere of radius
+    0.75 nz pressed into the top face to depth d."""
+    k = int(scale)
+    n0 = spec["n0"]
+    n = tuple(v * k for v in n0)
+    mask = voxelize_spheres(spec["centers"] * k, spec["radii"] * k, n)
+    lam, mu = two_phase_lame(mask, spec["contrast"])
+    meta = {"phi": spec["phi"], "contrast": spec["contrast"], "kind": spec["kind"], "scale": k,
+            "seed": spec["seed"]}
+    if spec["kind"] == "indent":
+        bc = bc_table(BC_N)
+        bc[:, 2, 0] = BC_D
+        R0 = 0.75 * n0[2]
+        d0 = spec["d_over_R"] * R0
+        sph = Sphere(np.array([n[0] / 2.0, n[1] / 2.0, n[2] + k * (R0 - d0)]), k * R0, face=5)
+        meta["d_over_R"] = spec["d_over_R"]
+        return Problem("C5-indent", n, lam, mu, bc, sphere=sph, r0_factor=5.0, tol=1e-6,
+                       max_iter=4000, meta=meta)
+    L0 = min(n0)
+    strong = []
+    for axis, side, oa, ob, s, vals in spec["patches"]:
+        ta, tb = [a for a in range(3) if a != axis]
+        # s nodes span s-1 voxels at n0; the scaled patch spans k (s-1) voxels
+        m = k * (s - 1) + 1
+        aa, bb = np.meshgrid(np.arange(k * oa, k * oa + m), np.arange(k * ob, k * ob + m), indexing="ij")
+        idx = np.zeros((m * m, 3), np.int64)
+        idx[:, ta] = aa.ravel()
+        idx[:, tb] = bb.ravel()
+        idx[:, axis] = 0 if side == 0 else n[axis]
+        for c, v in vals:
+            val = k * v * 1e-3 * L0 / np.sqrt(3.0)
+            strong.append(Strong(idx.copy(), np.full(len(idx), c, np.int8), np.full(len(idx), val),
+                                 set_id=len(strong)))
+    return Problem("C5-patch", n, lam, mu, spec["bc"].copy(), strong=strong, r0_factor=1.0, tol=1e-6,
                    max_iter=4000, meta=meta)
+
+
+def nn_case(seed, kind=None, scale=1, n0=(64, 64, 64)):
+    """Learned-start case: nn_case_build(nn_case_spec(seed, kind, n0), scale)."""
+    return nn_case_build(nn_case_spec(seed, kind, n0), scale)
 
 
 NN_TRAIN_SEED = BASE_SEED + 1_000_000
