@@ -22,6 +22,11 @@ constexpr uint8_t M_STRONG = 1;      // << comp
 constexpr uint8_t M_WEAK = 8;        // << comp
 constexpr uint8_t M_FACE = 64;       // potential contact node
 
+// blocks of the tiled residual pass: tx * ty node-column tiles, nseg z segments of seg planes
+struct TileGrid {
+  int tx, ty, nseg, seg;
+};
+
 struct Geo {
   int n[3];            // voxels per axis
   int N[3];            // nodes per axis

@@ -1347,6 +1347,94 @@ __device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
   return w;
 }
 
+// Per-node part of the residual pass of the residual-form iteration, once p is known:
+// singular-mode coefficients of u, contact bookkeeping or constraint masking, the norm of
+// p, p itself, and (ACV_P, from the second iteration on) R_i = p_i + K0 delta_i - e_{i-1}
+// with its differences.  kd = K0 delta at the node (read only when kd_used).
+// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}, R_{i-1}.
+template <typename T>
+struct TailIn {
+  uint8_t m;
+  T e[3], pp[3], rp[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, const T* pp,
+                                          const T* Rp, long long node, TailIn<T>& t) {
+  t.m = D.mask[node];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    t.e[c] = T(0);
+    t.pp[c] = T(0);
+    t.rp[c] = T(0);
+    if (kd_used) {
+      t.e[c] = D.e[c * Nn + node];
+      if (il >= 2) {
+        t.pp[c] = pp[c * Nn + node];
+        t.rp[c] = Rp[c * Nn + node];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, int cur,
+                                           bool kd_used, int il, int slot, T* pc, T* Rc, int i, int j, int k,
+                                           long long node, T p[3], const T kd[3], const TailIn<T>& tin,
+                                           double* acc) {
+  const long long Nn = g.Nn;
+  const int xyz[3] = {i, j, k};
+  // singular-mode coefficients of u (projection Pi of the update)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!g.sing[c]) continue;
+    const double wu = sing_weight(g, xyz) * D.u[c * Nn + node];
+    acc[8 + 2 * c] += wu;
+    if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
+  }
+  const uint8_t m = tin.m;
+  if (ct.on && (m & M_FACE)) {
+    const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
+    const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
+    const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
+    const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double gap = rr - ct.radius;
+    const double n0 = -d0 / rr, n1 = -d1 / rr, n2 = -d2 / rr;
+    const double pn = (double)p[0] * n0 + (double)p[1] * n1 + (double)p[2] * n2;
+    const double fnc = -pn / (double)(1 << bcount(g, xyz));
+    const uint8_t inC = ct.C[f];
+    if (inC) {
+      p[0] = (T)((double)p[0] - pn * n0);
+      p[1] = (T)((double)p[1] - pn * n1);
+      p[2] = (T)((double)p[2] - pn * n2);
+    }
+    ct.V[cur][f] = (uint8_t)(((!inC) && gap < 0.0) ? 1 : 0) | (uint8_t)((inC && fnc > 0.0) ? 2 : 0);
+    ct.fnc[f] = fnc;
+    ct.gap[f] = gap;
+    acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (m & (M_STRONG << c)) p[c] = T(0);
+      else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pc[c * Nn + node] = p[c];
+  if (kd_used) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long e = c * Nn + node;
+      const T Ri = p[c] + kd[c] - tin.e[c];
+      Rc[e] = Ri;
+      if (il >= 2) {
+        D.dR[slot][e] = Ri - tin.rp[c];
+        D.dY[slot][e] = p[c] - tin.pp[c] + kd[c];
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                        double* __restrict__ part) {
@@ -1360,6 +1448,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
   const int cur = ct.on ? st->vpar : 0;
   const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
   const int slot = (il + 1) % 3;   // (il - 2) mod 3
+  const bool kd_used = acvp && il >= 1;
   T* pc = D.p[par];
   const T* pp = D.p[par ^ 1];
   T* Rc = D.R[par];
@@ -1377,58 +1466,272 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     acc[1] += sn;
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
-    const int xyz[3] = {i, j, k};
-    // singular-mode coefficients of u (projection Pi of the update)
+    T kd[3] = {T(0), T(0), T(0)};
+    if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
+    TailIn<T> tin;
+    tail_load<T>(D, Nn, kd_used, il, pp, Rp, node, tin);
+    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
+  }
+  block_sum<kPartStrideD>(acc, sh);
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (!g.sing[c]) continue;
-      const double wu = sing_weight(g, xyz) * D.u[c * Nn + node];
-      acc[8 + 2 * c] += wu;
-      if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
-    }
-    const uint8_t m = D.mask[node];
-    if (ct.on && (m & M_FACE)) {
-      const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
-      const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
-      const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
-      const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      const double gap = rr - ct.radius;
-      const double n0 = -d0 / rr, n1 = -d1 / rr, n2 = -d2 / rr;
-      const double pn = (double)p[0] * n0 + (double)p[1] * n1 + (double)p[2] * n2;
-      const double fnc = -pn / (double)(1 << bcount(g, xyz));
-      const uint8_t inC = ct.C[f];
-      if (inC) {
-        p[0] = (T)((double)p[0] - pn * n0);
-        p[1] = (T)((double)p[1] - pn * n1);
-        p[2] = (T)((double)p[2] - pn * n2);
-      }
-      ct.V[cur][f] = (uint8_t)(((!inC) && gap < 0.0) ? 1 : 0) | (uint8_t)((inC && fnc > 0.0) ? 2 : 0);
-      ct.fnc[f] = fnc;
-      ct.gap[f] = gap;
-      acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
-    } else {
+    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// The same residual pass, tiled: a block owns a kTX x kTY column of nodes and marches
+// along z over a segment of node planes.  Node planes of u (FP64) and of delta (with the
+// stencil's mirrored / periodic halo) sit in LDS with a one-node halo; the stresses of the
+// two tetrahedra of every voxel of a layer are formed once per block (differences of u
+// taken in FP64 against the voxel's corner 000, then rounded) and serve the two node
+// planes that bound the layer.  Every voxel's stress-norm and mean-stress terms are
+// counted by the one block whose node column and segment contain its corner 000.
+// ---------------------------------------------------------------------------
+constexpr int kTX = 31, kTY = 7;                // 217 nodes; 32 x 8 = 256 voxels per layer
+constexpr int kHX = kTX + 2, kHY = kTY + 2;   // node tile with halo: x0-1 .. x0+kTX
+constexpr int kVX = kTX + 1, kVY = kTY + 1;   // voxels x0-1 .. x0+kTX-1
+constexpr int kPlane = 3 * kHY * kHX;         // values of one staged node plane
+constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
+
+__device__ __forceinline__ int ring3(int p) { return ((p % 3) + 3) % 3; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
+                                                     double* __restrict__ part, TileGrid tg) {
+  __shared__ double su[2][3][kHY][kHX];
+  __shared__ T sdl[3][3][kHY][kHX];
+  __shared__ T ss[2][kVY][kVX][12];
+  __shared__ double sh[kPartStrideD * 16];
+  if (st->done) return;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int bx = b % tg.tx, by = (b / tg.tx) % tg.ty, bz = b / (tg.tx * tg.ty);
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int zb = bz * tg.seg;
+  const int ze = min(zb + tg.seg, Nz);
+  const int Nn = (int)g.Nn;
+  const int cur = ct.on ? st->vpar : 0;
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;
+  const bool kd_used = acvp && il >= 1;
+  T* pc = D.p[par];
+  const T* pp = D.p[par ^ 1];
+  T* Rc = D.R[par];
+  const T* Rp = D.R[par ^ 1];
+  double acc[kPartStrideD];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (m & (M_STRONG << c)) p[c] = T(0);
-        else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
-      }
-    }
+  for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
+
+  // Node planes are fetched into registers one step ahead and committed to LDS the next
+  // step.  u: su[pz & 1], nodes outside the grid read as 0 (no voxel uses them); delta:
+  // sdl[pz mod 3] with the stencil's halo (mirror or periodic image).
+  double ru[kPR];
+  T rd[kPR];
+  auto fetch = [&](int pz) {
+    int gz = pz;
+    bool okz = true;
+    if (g.periodic[2]) gz = (pz + Nz) % Nz;
+    else okz = pz >= 0 && pz < Nz;
+    const int mz = mirror_coord(g, pz, 2);
+    const bool okm = mz >= 0 && mz < Nz;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pc[c * Nn + node] = p[c];
-    if (acvp && il >= 1) {
-      T kd[3];
-      stencil_k0<T>(g, D.delta, i, j, k, kd);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const long long e = c * Nn + node;
-        const T Ri = p[c] + kd[c] - D.e[e];
-        Rc[e] = Ri;
-        if (il >= 2) {
-          D.dR[slot][e] = Ri - Rp[e];
-          D.dY[slot][e] = p[c] - pp[e] + kd[c];
+    for (int r = 0; r < kPR; ++r) {
+      const int e = tid + 256 * r;
+      ru[r] = 0.0;
+      rd[r] = T(0);
+      if (e < kPlane) {
+        const int c = e / (kHY * kHX), q = e - c * (kHY * kHX);
+        const int hy = q / kHX, hx = q - hy * kHX;
+        int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+        bool ok = okz;
+        if (g.periodic[0]) gx = (gx + Nx) % Nx;
+        else ok = ok && gx >= 0 && gx < Nx;
+        if (g.periodic[1]) gy = (gy + Ny) % Ny;
+        else ok = ok && gy >= 0 && gy < Ny;
+        if (ok) ru[r] = D.u[c * Nn + gx + Nx * (gy + Ny * gz)];
+        if (kd_used) {
+          const int mx = mirror_coord(g, x0 - 1 + hx, 0), my = mirror_coord(g, y0 - 1 + hy, 1);
+          if (okm && mx >= 0 && mx < Nx && my >= 0 && my < Ny) rd[r] = D.delta[c * Nn + mx + Nx * (my + Ny * mz)];
         }
       }
     }
+  };
+  auto commit = [&](int pz) {
+    double* du = &su[pz & 1][0][0][0];
+    T* dd = &sdl[ring3(pz)][0][0][0];
+#pragma unroll
+    for (int r = 0; r < kPR; ++r) {
+      const int e = tid + 256 * r;
+      if (e < kPlane) {
+        du[e] = ru[r];
+        if (kd_used) dd[e] = rd[r];
+      }
+    }
+  };
+  // Every thread owns one voxel of a layer (kVX * kVY = 256): local (vlx, vly).
+  const int vly = tid / kVX, vlx = tid - (tid / kVX) * kVX;
+  const int vux = x0 - 1 + vlx, vuy = y0 - 1 + vly;   // unwrapped voxel coordinates
+  int vxw = vux, vyw = vuy;
+  bool vok = true;
+  if (g.periodic[0]) vxw = (vux + nx) % nx;
+  else vok = vux >= 0 && vux < nx;
+  if (g.periodic[1]) vyw = (vuy + ny) % ny;
+  else vok = vok && vuy >= 0 && vuy < ny;
+  // Lame values of this thread's voxel in layer lz (fetched one step ahead)
+  auto fetch_lm = [&](int lz, T& l, T& m, bool& ok) {
+    int vz = lz;
+    ok = vok;
+    if (g.periodic[2]) vz = (lz + nz) % nz;
+    else ok = ok && lz >= 0 && lz < nz;
+    l = T(0);
+    m = T(0);
+    if (ok) {
+      const int vid = vxw + nx * (vyw + ny * vz);
+      l = D.lam[vid];
+      m = D.mu[vid];
+    }
+  };
+  // voxel layer lz (between node planes lz and lz+1, held in su[lz & 1] and su[(lz+1) & 1])
+  auto layer = [&](int lz, bool own_z, T l, T m, bool ok) {
+    const int lo = lz & 1, hi = (lz + 1) & 1;
+    {
+      const int ly = vly, lx = vlx;
+      T* out = &ss[lz & 1][ly][lx][0];
+      const int ux = vux, uy = vuy;
+      if (!ok) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) out[q] = T(0);
+        return;
+      }
+      T d[8][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ref = su[lo][c][ly][lx];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+          d[cc][c] = cc == 0 ? T(0) : (T)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
+        }
+      }
+      const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        T G[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) G[r][q] = T(0);
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+          if (((cx + cy + cz) & 1) != t) continue;
+          const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            G[r][0] += sx * d[cc][r];
+            G[r][1] += sy * d[cc][r];
+            G[r][2] += sz * d[cc][r];
+          }
+        }
+        const T tr = G[0][0] + G[1][1] + G[2][2];
+        const T s00 = l * tr + T(2) * m * G[0][0];
+        const T s11 = l * tr + T(2) * m * G[1][1];
+        const T s22 = l * tr + T(2) * m * G[2][2];
+        const T s01 = m * (G[0][1] + G[1][0]);
+        const T s02 = m * (G[0][2] + G[2][0]);
+        const T s12 = m * (G[1][2] + G[2][1]);
+        out[t * 6 + 0] = s00;
+        out[t * 6 + 1] = s11;
+        out[t * 6 + 2] = s22;
+        out[t * 6 + 3] = s01;
+        out[t * 6 + 4] = s02;
+        out[t * 6 + 5] = s12;
+        if (own) {
+          const double d00 = s00, d11 = s11, d22 = s22, d01 = s01, d02 = s02, d12 = s12;
+          acc[1] += 0.5 * (d00 * d00 + d11 * d11 + d22 * d22 + 2.0 * (d01 * d01 + d02 * d02 + d12 * d12));
+          acc[2] += 0.5 * d00;
+          acc[3] += 0.5 * d11;
+          acc[4] += 0.5 * d22;
+          acc[5] += 0.5 * d12;
+          acc[6] += 0.5 * d02;
+          acc[7] += 0.5 * d01;
+        }
+      }
+    }
+  };
+  const int nlx = tid % kTX, nly = tid / kTX;
+  const bool nact = tid < kTX * kTY && x0 + nlx < Nx && y0 + nly < Ny;
+  TailIn<T> tin;
+  auto nodes = [&](int z) {
+    if (!nact) return;
+    const int lx = nlx, ly = nly;
+    const int i = x0 + lx, j = y0 + ly;
+    T F[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      // voxel (i - ax, j - ay, z - az): local voxel (lx + 1 - ax, ly + 1 - ay), layer z - az;
+      // the node is its corner (ax, ay, az), in tetrahedron T1 (even) or T2 (odd)
+      const T* sv = &ss[(z - az) & 1][ly + 1 - ay][lx + 1 - ax][((ax + ay + az) & 1) * 6];
+      const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
+      F[0] += bxw * sv[0] + byw * sv[3] + bzw * sv[4];
+      F[1] += bxw * sv[3] + byw * sv[1] + bzw * sv[5];
+      F[2] += bxw * sv[4] + byw * sv[5] + bzw * sv[2];
+    }
+    const int xyz[3] = {i, j, z};
+    const T w2b = T(1 << bcount(g, xyz));
+    T p[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+    T kd[3] = {T(0), T(0), T(0)};
+    if (kd_used) {
+      const int zm = ring3(z - 1), z0 = ring3(z), zp = ring3(z + 1);
+      const int hx = lx + 1, hy = ly + 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T sxy = sdl[z0][c][hy - 1][hx - 1] + sdl[z0][c][hy - 1][hx + 1] + sdl[z0][c][hy + 1][hx - 1] +
+                      sdl[z0][c][hy + 1][hx + 1];
+        const T sxz = sdl[zm][c][hy][hx - 1] + sdl[zm][c][hy][hx + 1] + sdl[zp][c][hy][hx - 1] +
+                      sdl[zp][c][hy][hx + 1];
+        const T syz = sdl[zm][c][hy - 1][hx] + sdl[zm][c][hy + 1][hx] + sdl[zp][c][hy - 1][hx] +
+                      sdl[zp][c][hy + 1][hx];
+        kd[c] = T(g.st[c][0]) * sdl[z0][c][hy][hx] + T(g.st[c][1]) * sxy + T(g.st[c][2]) * sxz +
+                T(g.st[c][3]) * syz;
+      }
+    }
+    const long long node = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * z);
+    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
+  };
+
+  T lcur, mcur, lnext, mnext;
+  bool okcur, oknext;
+  fetch(zb - 1);
+  commit(zb - 1);
+  fetch(zb);
+  commit(zb);
+  fetch(zb + 1);
+  fetch_lm(zb - 1, lcur, mcur, okcur);
+  fetch_lm(zb, lnext, mnext, oknext);
+  __syncthreads();
+  layer(zb - 1, false, lcur, mcur, okcur);
+  for (int z = zb; z < ze; ++z) {
+    __syncthreads();
+    commit(z + 1);
+    if (z + 2 <= ze) fetch(z + 2);
+    lcur = lnext;
+    mcur = mnext;
+    okcur = oknext;
+    if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
+    if (nact) {
+      const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
+      tail_load<T>(D, g.Nn, kd_used, il, pp, Rp, node, tin);
+    }
+    __syncthreads();
+    layer(z, true, lcur, mcur, okcur);
+    __syncthreads();
+    nodes(z);
   }
   block_sum<kPartStrideD>(acc, sh);
   if (threadIdx.x == 0)
@@ -1729,12 +2032,37 @@ void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double
   hipLaunchKernelGGL(k_contact_force<T>, dim3(nblk), dim3(kBlock), 0, s, g, u, ct, out);
 }
 
+TileGrid residual_tiles(const Geo& g);
+
 template <typename T>
 void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
                                   DevState* st, double* part, double* wpart, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+  const TileGrid tg = residual_tiles(g);
+  if (tg.tx > 0) {
+    nblk = tg.tx * tg.ty * tg.nseg;
+    hipLaunchKernelGGL(k_residual_dt<T>, dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+  } else {
+    hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+  }
   if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, D, w, st);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, w.m, ct, kPartStrideD);
+}
+
+// Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
+// segments so that the block count stays within the 2048 partial-sum rows; tx = 0 when
+// the node plane alone needs more tiles than that.
+TileGrid residual_tiles(const Geo& g) {
+  TileGrid t{0, 0, 0, 0};
+  const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
+  if ((long long)tx * ty > 2048) return t;
+  int nseg = std::max(1, std::min(g.N[2], 2048 / (tx * ty)));
+  const int seg = (g.N[2] + nseg - 1) / nseg;
+  nseg = (g.N[2] + seg - 1) / seg;
+  t.tx = tx;
+  t.ty = ty;
+  t.nseg = nseg;
+  t.seg = seg;
+  return t;
 }
 
 template <typename T>
