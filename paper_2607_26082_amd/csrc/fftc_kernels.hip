@@ -620,6 +620,18 @@ __device__ __forceinline__ double paux_symbol(const double a[3], double sx, doub
 // Residual-form update in the last inverse pass: delta = K0^+ e - (I - Pi) u, u += delta,
 // at node (i, j, k) of component c.
 template <typename T>
+__device__ __forceinline__ double dtt_update_d(const DttArgs<T>& a, int c, int i, int j, int k, T v) {
+  double d = (double)v;
+  const int sg = a.g.sing[c];
+  if (sg) {
+    const double s0 = a.st->sing[2 * c], s1 = a.st->sing[2 * c + 1];
+    const int parity = (i + j + k) & 1;
+    d -= a.g.sing_scale[c] * (s0 + ((sg & 2) ? (parity ? -s1 : s1) : 0.0));
+  }
+  return d;
+}
+
+template <typename T>
 __device__ __forceinline__ void dtt_update(const DttArgs<T>& a, int c, int i, int j, int k, long long addr, T v) {
   double d = (double)v;
   const int sg = a.g.sing[c];
@@ -849,27 +861,39 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   constexpr int LB = S::LB, NN = S::NN, CS = S::CS, RS = S::RS, NT = S::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   if (!a.force && a.st->done) return;
-  const int c = blockIdx.z;
+  // Blocks are dispatched to the 8 XCDs round-robin in linear order; renumber them so that
+  // every XCD works on a contiguous range of (chunk, plane, component) and the chunks that
+  // share 128-byte lines of a y or z line meet in one L2.
+  unsigned bxi, byi, c;
+  {
+    const unsigned G = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned p = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned q = G / 8, r = G % 8, xcd = p % 8, slot = p / 8;
+    const unsigned L = xcd * q + (xcd < r ? xcd : r) + slot;
+    bxi = L % gridDim.x;
+    byi = (L / gridDim.x) % gridDim.y;
+    c = L / (gridDim.x * gridDim.y);
+  }
   const int axis = a.axis;
   const int Nx = a.g.N[0], Ny = a.g.N[1];
   long long base;
   int nl, lstride, estride;
   if (axis == 0) {
-    const int y0 = blockIdx.x * LB;
+    const int y0 = (int)bxi * LB;
     nl = Ny - y0;
-    base = ((long long)blockIdx.y * Ny + y0) * Nx;
+    base = ((long long)(int)byi * Ny + y0) * Nx;
     lstride = Nx;
     estride = 1;
   } else if (axis == 1) {
-    const int x0 = blockIdx.x * LB;
+    const int x0 = (int)bxi * LB;
     nl = Nx - x0;
-    base = (long long)blockIdx.y * Nx * Ny + x0;
+    base = (long long)(int)byi * Nx * Ny + x0;
     lstride = 1;
     estride = Nx;
   } else {
-    const int x0 = blockIdx.x * LB;
+    const int x0 = (int)bxi * LB;
     nl = Nx - x0;
-    base = (long long)blockIdx.y * Nx + x0;
+    base = (long long)(int)byi * Nx + x0;
     lstride = 1;
     estride = Nx * Ny;
   }
@@ -907,16 +931,26 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
           } else {
             v = a.B.X[addr];
           }
-          if (a.store_s) a.B.S[slot][addr] = v;
         }
         vals[i] = v;
       }
+      // the stores of S after all loads (see the residual-form source below)
+      if (a.store_s)
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+          const int w = tid + i * NT;
+          int l, m;
+          if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+          if (w < LB * NN && l < nl) a.B.S[slot][base + (long long)(l * lstride + m * estride)] = vals[i];
+        }
     } else if (a.src == SRC_DELTA) {
       const T* pcur = a.dp2[a.st->it & 1];
       const int acc_ok = a.st->accel_ok;
       const T g0 = acc_ok ? (T)a.st->gamma[0] : T(0), g1 = acc_ok ? (T)a.st->gamma[1] : T(0),
               g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
-#pragma unroll 4
+      // all loads first, then the stores of e: a store between the loads would keep
+      // the next load from being issued before it (the pointers may alias)
+#pragma unroll
       for (int i = 0; i < NO; ++i) {
         const int w = tid + i * NT;
         int l, m;
@@ -926,9 +960,15 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
           const long long addr = base + (long long)(l * lstride + m * estride);
           v = pcur[addr];
           if (acc_ok) v = v - (g0 * a.dY[0][addr] + g1 * a.dY[1][addr] + g2 * a.dY[2][addr]);
-          a.de[addr] = v;
         }
         vals[i] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < NO; ++i) {
+        const int w = tid + i * NT;
+        int l, m;
+        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+        if (w < LB * NN && l < nl) a.de[base + (long long)(l * lstride + m * estride)] = vals[i];
       }
     } else {
 #pragma unroll
@@ -965,8 +1005,8 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     const double* qyT = a.cosT + ((c * 3 + 1) * 2 + 1) * a.maxN;
     const double* szT = a.cosT + ((c * 3 + 2) * 2 + 0) * a.maxN;
     const double* qzT = a.cosT + ((c * 3 + 2) * 2 + 1) * a.maxN;
-    const double sy = syT[blockIdx.y], qy = qyT[blockIdx.y];
-    const int x0 = blockIdx.x * LB;
+    const double sy = syT[(int)byi], qy = qyT[(int)byi];
+    const int x0 = (int)bxi * LB;
 #pragma unroll
     for (int i = 0; i < NO; ++i) {
       const int w = tid + i * NT;
@@ -997,6 +1037,36 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   }
   // phase 4: post-process and scatter
   const int inv_out = (a.mode != PASS_FWD);
+  // (the FP64 displacement update only exists in the FP32 residual form)
+  if constexpr (sizeof(T) == 4) if (a.dst == DST_UPDATE) {
+    // read every old u of the thread first, then write u and delta
+    constexpr int NO = (LB * NN + NT - 1) / NT;
+    double uo[NO];
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      const int w = tid + i * NT;
+      int l, m;
+      if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+      uo[i] = (w < LB * NN && l < nl) ? a.u64[base + (long long)(l * lstride + m * estride)] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NO; ++i) {
+      const int w = tid + i * NT;
+      int l, m;
+      if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+      if (w >= LB * NN || l >= nl) continue;
+      const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
+      const long long addr = base + (long long)(l * lstride + m * estride);
+      int xi, yj, zk;
+      if (axis == 0) { xi = m; yj = (int)bxi * LB + l; zk = (int)byi; }
+      else if (axis == 1) { xi = (int)bxi * LB + l; yj = m; zk = (int)byi; }
+      else { xi = (int)bxi * LB + l; yj = (int)byi; zk = m; }
+      const double d = dtt_update_d<T>(a, c, xi, yj, zk, v);
+      a.u64[addr] = uo[i] + d;
+      a.delta[addr] = (T)d;
+    }
+    return;
+  }
 #pragma unroll 4
   for (int w = tid; w < LB * NN; w += NT) {
     int l, m;
@@ -1006,9 +1076,9 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     const long long addr = base + (long long)(l * lstride + m * estride);
     if (a.dst == DST_UPDATE) {
       int xi, yj, zk;
-      if (axis == 0) { xi = m; yj = blockIdx.x * LB + l; zk = blockIdx.y; }
-      else if (axis == 1) { xi = blockIdx.x * LB + l; yj = m; zk = blockIdx.y; }
-      else { xi = blockIdx.x * LB + l; yj = blockIdx.y; zk = m; }
+      if (axis == 0) { xi = m; yj = (int)bxi * LB + l; zk = (int)byi; }
+      else if (axis == 1) { xi = (int)bxi * LB + l; yj = m; zk = (int)byi; }
+      else { xi = (int)bxi * LB + l; yj = (int)byi; zk = m; }
       dtt_update<T>(a, c, xi, yj, zk, addr, v);
     } else {
       a.buf[addr] = v;
@@ -1500,11 +1570,18 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
                                                      double* __restrict__ part, TileGrid tg) {
   __shared__ double su[2][3][kHY][kHX];
   __shared__ T sdl[3][3][kHY][kHX];
-  __shared__ T ss[2][kVY][kVX][12];
+  __shared__ T ss[2][12][kVY][kVX];   // stress component q of the voxels of a layer
   __shared__ double sh[kPartStrideD * 16];
   if (st->done) return;
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
+  // contiguous ranges of tiles per XCD (blocks go to the 8 XCDs round-robin), so that
+  // neighbouring tiles share their halo lines in one L2
+  int b;
+  {
+    const unsigned G = gridDim.x, p = blockIdx.x;
+    const unsigned q = G / 8, r = G % 8, xcd = p % 8, slot = p / 8;
+    b = (int)(xcd * q + (xcd < r ? xcd : r) + slot);
+  }
   const int bx = b % tg.tx, by = (b / tg.tx) % tg.ty, bz = b / (tg.tx * tg.ty);
   const int x0 = bx * kTX, y0 = by * kTY;
   const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
@@ -1598,11 +1675,11 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     const int lo = lz & 1, hi = (lz + 1) & 1;
     {
       const int ly = vly, lx = vlx;
-      T* out = &ss[lz & 1][ly][lx][0];
+      T (*out)[kVY][kVX] = ss[lz & 1];
       const int ux = vux, uy = vuy;
       if (!ok) {
 #pragma unroll
-        for (int q = 0; q < 12; ++q) out[q] = T(0);
+        for (int q = 0; q < 12; ++q) out[q][ly][lx] = T(0);
         return;
       }
       T d[8][3];
@@ -1616,6 +1693,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         }
       }
       const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
+      T vs[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         T G[3][3];
@@ -1642,23 +1720,26 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         const T s01 = m * (G[0][1] + G[1][0]);
         const T s02 = m * (G[0][2] + G[2][0]);
         const T s12 = m * (G[1][2] + G[2][1]);
-        out[t * 6 + 0] = s00;
-        out[t * 6 + 1] = s11;
-        out[t * 6 + 2] = s22;
-        out[t * 6 + 3] = s01;
-        out[t * 6 + 4] = s02;
-        out[t * 6 + 5] = s12;
+        out[t * 6 + 0][ly][lx] = s00;
+        out[t * 6 + 1][ly][lx] = s11;
+        out[t * 6 + 2][ly][lx] = s22;
+        out[t * 6 + 3][ly][lx] = s01;
+        out[t * 6 + 4][ly][lx] = s02;
+        out[t * 6 + 5][ly][lx] = s12;
         if (own) {
-          const double d00 = s00, d11 = s11, d22 = s22, d01 = s01, d02 = s02, d12 = s12;
-          acc[1] += 0.5 * (d00 * d00 + d11 * d11 + d22 * d22 + 2.0 * (d01 * d01 + d02 * d02 + d12 * d12));
-          acc[2] += 0.5 * d00;
-          acc[3] += 0.5 * d11;
-          acc[4] += 0.5 * d22;
-          acc[5] += 0.5 * d12;
-          acc[6] += 0.5 * d02;
-          acc[7] += 0.5 * d01;
+          // the voxel's two tetrahedra in T, added to the FP64 block sums once per voxel
+          vs[0] += s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
+          vs[1] += s00;
+          vs[2] += s11;
+          vs[3] += s22;
+          vs[4] += s12;
+          vs[5] += s02;
+          vs[6] += s01;
         }
       }
+      if (own)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) acc[1 + q] += 0.5 * (double)vs[q];
     }
   };
   const int nlx = tid % kTX, nly = tid / kTX;
@@ -1674,11 +1755,14 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       // voxel (i - ax, j - ay, z - az): local voxel (lx + 1 - ax, ly + 1 - ay), layer z - az;
       // the node is its corner (ax, ay, az), in tetrahedron T1 (even) or T2 (odd)
-      const T* sv = &ss[(z - az) & 1][ly + 1 - ay][lx + 1 - ax][((ax + ay + az) & 1) * 6];
+      const int q0 = ((ax + ay + az) & 1) * 6, vy = ly + 1 - ay, vx = lx + 1 - ax;
+      T (*sv)[kVY][kVX] = ss[(z - az) & 1];
+      const T s00 = sv[q0 + 0][vy][vx], s11 = sv[q0 + 1][vy][vx], s22 = sv[q0 + 2][vy][vx];
+      const T s01 = sv[q0 + 3][vy][vx], s02 = sv[q0 + 4][vy][vx], s12 = sv[q0 + 5][vy][vx];
       const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
-      F[0] += bxw * sv[0] + byw * sv[3] + bzw * sv[4];
-      F[1] += bxw * sv[3] + byw * sv[1] + bzw * sv[5];
-      F[2] += bxw * sv[4] + byw * sv[5] + bzw * sv[2];
+      F[0] += bxw * s00 + byw * s01 + bzw * s02;
+      F[1] += bxw * s01 + byw * s11 + bzw * s12;
+      F[2] += bxw * s02 + byw * s12 + bzw * s22;
     }
     const int xyz[3] = {i, j, z};
     const T w2b = T(1 << bcount(g, xyz));
