@@ -1,0 +1,94 @@
+"""Full-size configurations on the GPU, checked by properties that hold at any size
+(the oracle cannot solve these grids in test time; it is pinned to the same GPU path
+at small sizes in test_gpu_parity.py).
+
+C2  compact-tension plate 256 x 256 x 16: the two pin sets' y-reactions balance
+    (global equilibrium, Section 4.3), prescribed DOFs hold exactly, and FP32
+    reactions agree with FP64 ones.
+C3  Hertz indentation 256 x 256 x 128, R = 96, d/R = 0.002 k, k = 1..10, each
+    increment warm-started from the previous one (Algorithm 2).  The block is
+    bonded to a fixed base 128 voxels below the contact, so the force follows Hertz
+    (F_H = 4/3 E* sqrt(R) d^1.5, Section 5.2) times the published finite-thickness
+    factor of a sphere on a bonded layer (Dimitriadis et al., Biophys. J. 82, 2002:
+    1 - 2 a0/pi chi + 4 a0^2/pi^2 chi^2 - 8/pi^3 (a0^3 + 4 pi^2/15 b0) chi^3,
+    chi = sqrt(R d)/h); checked within 2 % of that, with the raw ratio F/F_H
+    printed.  The area-equivalent contact radius is within one voxel of sqrt(R d)
+    for d/R >= 0.006, the two force evaluations F = -A0 <sigma_zz> and F = sum of
+    contact forces agree, and the active set satisfies the KKT sign conditions (no
+    penetration off the set, no tension on it)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.contact import hertz_force, hertz_radius
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2607_26082_amd as F
+    F.load()
+    return F
+
+
+def test_c2_compact_tension_reactions():
+    F = _lib()
+    prob = W.c2_compact_tension()
+    tot = {}
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-6)):
+        print(f"[c2] {prec} n={prob.n}", flush=True)
+        g = F.Solver.from_problem(prob, precision=prec, tol=tol, max_iter=20000)
+        rc, rep = g.solve()
+        assert rc == 0, rc
+        _, _, t = g.reactions()
+        tot[prec] = t
+        print(f"[c2] {prec} iterations {rep.iterations} reactions y {t[0, 1]:.6e} {t[1, 1]:.6e}", flush=True)
+        assert abs(t[0, 1] + t[1, 1]) <= (1e-6 if prec == "fp64" else 1e-3) * abs(t[0, 1])
+        u = g.u.cpu().numpy()
+        for s in prob.strong:
+            got = u[s.comp, s.node[:, 2], s.node[:, 1], s.node[:, 0]]
+            assert np.array_equal(got, s.value)
+    r64, r32 = tot["fp64"][:, 1], tot["fp32"][:, 1]
+    assert np.max(np.abs(r32 - r64)) <= 1e-4 * np.max(np.abs(r64))
+
+
+def bonded_layer_factor(nu, chi):
+    """Finite-thickness factor of Hertz for a sphere on a layer bonded to a rigid base."""
+    a0 = -(1.2876 - 1.4678 * nu + 1.3442 * nu * nu) / (1.0 - nu)
+    b0 = (0.6387 - 1.0277 * nu + 1.5164 * nu * nu) / (1.0 - nu)
+    return (1.0 - 2.0 * a0 / np.pi * chi + 4.0 * a0 * a0 / np.pi ** 2 * chi ** 2
+            - 8.0 / np.pi ** 3 * (a0 ** 3 + 4.0 * np.pi ** 2 / 15.0 * b0) * chi ** 3)
+
+
+def test_c3_hertz_indentation_fp32():
+    F = _lib()
+    n, R = (256, 256, 128), 96.0
+    prob = W.c3_indentation(n=n, R=R, d_over_R=0.002)
+    g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=20000)
+    rows = []
+    for k in range(1, 11):
+        d = 0.002 * k * R
+        g.move_sphere(np.array([n[0] / 2.0, n[1] / 2.0, n[2] + R - d]))
+        rc, rep = g.solve(zero_start=(k == 1))
+        assert rc == 0, (k, rc)
+        mask, fnc, gap = g.contact()
+        C = mask.reshape(-1).astype(bool)
+        fnc, gap = fnc.reshape(-1), gap.reshape(-1)
+        FH = hertz_force(1.0, 0.3, R, d)
+        aH = hertz_radius(R, d)
+        corr = bonded_layer_factor(0.3, aH / n[2])
+        a_eq = np.sqrt(C.sum() / np.pi)
+        fmax = np.abs(fnc[C]).max()
+        kkt = bool((gap[~C] >= -1e-6 * R).all() and (np.abs(gap[C]) <= 1e-5 * R).all()
+                   and (fnc[C] <= 1e-6 * fmax).all())
+        rows.append(dict(dR=d / R, it=rep.iterations, F=rep.force_contact, Fs=rep.force_mean_stress,
+                         ratio=rep.force_contact / FH, corr=corr, a=a_eq, aH=aH, kkt=kkt))
+        print(f"[c3] d/R={d / R:.3f} it={rep.iterations} F={rep.force_contact:.5e} "
+              f"F_sigma={rep.force_mean_stress:.5e} F/F_H={rep.force_contact / FH:.4f} "
+              f"layer-corrected {corr:.4f} a={a_eq:.2f} a_H={aH:.2f} kkt={kkt}", flush=True)
+    for r in rows:
+        assert abs(r["F"] - r["Fs"]) <= 1e-3 * r["F"], r
+        assert r["kkt"], r
+        assert abs(r["ratio"] / r["corr"] - 1) <= 0.02, r
+        if r["dR"] >= 0.006 - 1e-12:
+            assert abs(r["a"] - r["aH"]) <= 1.0, r
