@@ -11,16 +11,20 @@
  * answer beyond the solver tolerance.
  *
  * Network (width W = 32, head H = 64, m modes per axis, B blocks):
- *   x0  = f Wl^T + bl                                  (9 -> 32, per node)
+ *   x0  = f Wl^T + bl                                  (12 -> 32, per node)
  *   x_b = GELU(S_b(x_{b-1}) + x_{b-1} W_b^T + c_b)      b = 1..B
  *   h   = GELU(x_B Wp1^T + bp1);  y = h Wp2^T + bp2     (32 -> 64 -> 3)
  *   S(x)[i, o] = sum_k phi_k(i) sum_c Ws[k, o, c] xh[k, c],
  *   xh[k, c]   = (1 / Nn) sum_i phi_k(i) x[i, c],
  *   phi_k(i)   = cos(pi kx (x + 1/2) / Nx) cos(pi ky (y + 1/2) / Ny) cos(pi kz (z + 1/2) / Nz),
  *   k = (kz m + ky) m + kx with every index below m;  GELU(z) = z Phi(z) (erf form).
- * The start is u0 = s_u y with s_u = 1e-3 min(n).  Training minimises the
- * relative squared L2 misfit sum (y - t)^2 / sum t^2 to t = u* / s_u, u* a
- * converged solve, with Adam (Kingma & Ba, Algorithm 1).
+ * The network predicts a correction of the solver's own first iterate u1 (one
+ * iteration from the plain start, i.e. the reference medium's response to the
+ * prescribed data): the start is u0 = u1 + s_u y with s_u = 1e-3 min(n).
+ * Training minimises the squared L2 misfit sum (y - t)^2 / (sum t^2 + sum b^2) to
+ * t = (u* - u1) / s_u, u* a converged solve, relative to the size of the whole
+ * field (b = u1 / s_u as stored in the input channels), with Adam (Kingma & Ba,
+ * Algorithm 1).
  *
  * Arithmetic: GEMM-shaped steps (lift, spectral synthesis + pointwise term,
  * head, and every weight-gradient reduction over nodes) run on BF16 MFMA with
@@ -28,17 +32,17 @@
  * output layer, the loss and Adam run in FP32.
  *
  * Parameter vector (FP32, in this order, each row-major):
- *   Wl[32][9], bl[32], then per block b: Ws_b[m^3][32][32] (mode, out, in),
+ *   Wl[32][12], bl[32], then per block b: Ws_b[m^3][32][32] (mode, out, in),
  *   W_b[32][32], c_b[32]; then Wp1[64][32], bp1[64], Wp2[3][64], bp2[3].
  *   Gradients use the same layout.
  *
  * Input channels (FFTC_NN_CHANNELS = 16 BF16 values per node, node-major,
- * channels 9..15 zero):
+ * channels 12..15 zero):
  *   0 E / max E, E averaged over the voxels around the node; 1 nu averaged
  *   likewise; 2-4 per component 1 where the DOF is prescribed (Dirichlet
  *   face or strong constraint); 5-7 per component prescribed value / s_u;
  *   8 on the contact face of a rigid sphere tanh(g / (8 s_u)) with g = |X - O| - R
- *   the gap of the undeformed node, else 0.
+ *   the gap of the undeformed node, else 0; 9-11 the first iterate u1 / s_u.
  *
  * Conventions are those of fftc.h: int status returns, *_dev device pointers
  * borrowed for the call, caller-owned device memory (a persistent state
@@ -91,16 +95,22 @@ int fftc_nn_get_grad(fftc_nn_h nn, float* grad_dev);
 
 /* Input channels of a bound solver problem (stiffness set), written to
  * feat_dev[Nn][FFTC_NN_CHANNELS] (BF16 bits, round to nearest even) on the
- * problem's stream. */
-int fftc_nn_features(fftc_h prob, uint16_t* feat_dev);
+ * problem's stream.  Runs the solver's initialisation and one iteration from
+ * the plain start (Algorithm 1; Algorithm 2 with a sphere) and writes that
+ * first iterate to u1_dev (FP64 component-planar [3][Nn], required); the
+ * handle's iteration state is left there (the next solve starts afresh). */
+int fftc_nn_features(fftc_h prob, uint16_t* feat_dev, double* u1_dev);
 
 /* Forward pass on the bound grid.  y_dev (may be NULL): FP32 [Nn][3] network
- * output; u0_dev (may be NULL): FP64 component-planar [3][Nn] start s_u * y. */
-int fftc_nn_forward(fftc_nn_h nn, const uint16_t* feat_dev, float* y_dev, double s_u, double* u0_dev);
+ * output; u0_dev (may be NULL): FP64 component-planar [3][Nn] start
+ * base + s_u * y, with base_dev the first iterate of fftc_nn_features (NULL
+ * reads as zero). */
+int fftc_nn_forward(fftc_nn_h nn, const uint16_t* feat_dev, float* y_dev, double s_u, const double* base_dev,
+                    double* u0_dev);
 
 /* One training sample: forward, loss and backward on a workspace bound with
- * training != 0.  target_dev: FP32 component-planar [3][Nn], t = u* / s_u
- * (not all zero).  The gradient of the loss replaces the stored gradient;
+ * training != 0.  target_dev: FP32 component-planar [3][Nn],
+ * t = (u* - u1) / s_u (not all zero).  The gradient of the loss replaces the stored gradient;
  * loss_dev (may be NULL) receives the loss as one FP64 value. */
 int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* target_dev, double* loss_dev);
 

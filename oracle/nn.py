@@ -13,7 +13,7 @@ Grid: the solver's node grid, N = (Nx, Ny, Nz), flat index x + Nx (y + Ny z);
 activations are [Nn, C] (node-major).
 
 Network (defaults width 32, modes m = 6, 4 blocks, head width 64):
-  x0 = f Wl^T + bl                                  lift, f = 9 input channels
+  x0 = f Wl^T + bl                                  lift, f = 12 input channels
   x_b = GELU( S_b(x_{b-1}) + x_{b-1} W_b^T + c_b )  b = 1..4
   h  = GELU( x_4 Wp1^T + bp1 )
   y  = h Wp2^T + bp2                                 3 outputs, in units of s_u
@@ -23,8 +23,10 @@ Spectral operator S (modes k = (kz, ky, kx), each < m):
   yh[k, o] = sum_c Ws[k, o, c] xh[k, c]
   S(x)[i, o] = sum_k phi_kz(z) phi_ky(y) phi_kx(x) yh[k, o]
 GELU(z) = z Phi(z), Phi the standard normal CDF (erf form).
-Loss per sample: L = sum (y - t)^2 / sum t^2 (relative squared L2), t = u*/s_u.
-Displacement start: u0 = s_u y, s_u = 1e-3 min(n).
+Loss per sample: L = sum (y - t)^2 / (sum t^2 + sum b^2), t = (u* - u1)/s_u
+with u1 the solver's first iterate from the plain start and b = u1/s_u (the
+misfit of the correction relative to the size of the whole field).
+Displacement start: u0 = u1 + s_u y, s_u = 1e-3 min(n).
 
 Input channels (all on nodes):
   0  E / max E, E averaged over the voxels around the node
@@ -35,6 +37,8 @@ Input channels (all on nodes):
   8  on the contact face of a rigid sphere: tanh(g / (8 s_u)), g = |X - O| - R
      the gap of the undeformed node, so that indentation depths of a few s_u
      map to O(1) values; 0 elsewhere and without a sphere
+  9-11 per component: the first iterate u1 / s_u (one iteration of Algorithm 1,
+       or Algorithm 2 with a sphere, from the plain start)
 """
 from __future__ import annotations
 
@@ -46,14 +50,14 @@ from .plan import Plan
 SQRT2 = np.sqrt(2.0)
 INV_SQRT_2PI = 1.0 / np.sqrt(2.0 * np.pi)
 
-DEFAULT_SHAPE = dict(width=32, modes=6, blocks=4, hidden=64, cin=9, cout=3)
+DEFAULT_SHAPE = dict(width=32, modes=6, blocks=4, hidden=64, cin=12, cout=3)
 
 
 # ---------------------------------------------------------------------------
 # parameters
 # ---------------------------------------------------------------------------
 
-def param_layout(width=32, modes=6, blocks=4, hidden=64, cin=9, cout=3):
+def param_layout(width=32, modes=6, blocks=4, hidden=64, cin=12, cout=3):
     """Ordered (name, shape) list; the flat parameter vector concatenates them
     in this order, each row-major."""
     w, M = width, modes ** 3
@@ -163,9 +167,9 @@ def forward(p, f, N, blocks=None, m=None):
     return y, cache
 
 
-def loss(y, t):
-    """Relative squared L2 and its gradient with respect to y."""
-    s = float((t * t).sum())
+def loss(y, t, b=None):
+    """sum (y - t)^2 / (sum t^2 + sum b^2) and its gradient with respect to y."""
+    s = float((t * t).sum()) + (0.0 if b is None else float((b * b).sum()))
     d = y - t
     return float((d * d).sum()) / s, 2.0 * d / s
 
@@ -215,8 +219,22 @@ def start_scale(n):
     return 1e-3 * float(min(n))
 
 
-def features(prob):
-    """[Nn, 9] input channels of a problem (see the module header)."""
+def first_iterate(prob):
+    """u after one iteration from the plain start, [3, Nz, Ny, Nx]."""
+    if prob.sphere is None:
+        from .solver import Solver
+        s = Solver.from_problem(prob)
+        return s.solve(tol=0.0, max_iter=1, acv=prob.acv, period=prob.acv_period)["u"]
+    from .contact import ContactSolver
+    sp = prob.sphere
+    cs = ContactSolver(prob.n, prob.lam, prob.mu, prob.bc, face=sp.face, radius=sp.radius,
+                       strong=prob.strong, average=prob.average, r0_factor=prob.r0_factor)
+    return cs.solve_increment(None, sp.center, tol=0.0, max_iter=1, acv=prob.acv, period=prob.acv_period)["u"]
+
+
+def features(prob, u1=None):
+    """[Nn, 12] input channels of a problem (see the module header); u1 is the first
+    iterate (computed when not given)."""
     plan = Plan(prob.n, prob.bc)
     nx, ny, nz = prob.n
     Nx, Ny, Nz = plan.N
@@ -252,7 +270,7 @@ def features(prob):
                         Esum[z, y, row] += E[vz, ys[y], xs[row]]
                         nusum[z, y, row] += nu[vz, ys[y], xs[row]]
                         cnt[z, y, row] += 1
-    f = np.zeros((Nz, Ny, Nx, 9))
+    f = np.zeros((Nz, Ny, Nx, 12))
     f[..., 0] = Esum / cnt / Emax
     f[..., 1] = nusum / cnt
     su = start_scale(prob.n)
@@ -271,4 +289,9 @@ def features(prob):
         g = np.linalg.norm(X - np.asarray(sp.center, np.float64), axis=-1) - sp.radius
         on = [xx, yy, zz][a] == idx
         f[..., 8] = np.where(on, np.tanh(g / (8.0 * su)), 0.0)
-    return f.reshape(-1, 9)
+    if u1 is None:
+        u1 = first_iterate(prob)
+    u1 = np.asarray(u1, np.float64).reshape(3, Nz, Ny, Nx)
+    for c in range(3):
+        f[..., 9 + c] = u1[c] / su
+    return f.reshape(-1, 12)

@@ -82,8 +82,8 @@ _SIGS = {
     "fftc_nn_set_params": (C.c_int, [_P, _P]),
     "fftc_nn_get_params": (C.c_int, [_P, _P]),
     "fftc_nn_get_grad": (C.c_int, [_P, _P]),
-    "fftc_nn_features": (C.c_int, [_P, _P]),
-    "fftc_nn_forward": (C.c_int, [_P, _P, _P, C.c_double, _P]),
+    "fftc_nn_features": (C.c_int, [_P, _P, _P]),
+    "fftc_nn_forward": (C.c_int, [_P, _P, _P, C.c_double, _P, _P]),
     "fftc_nn_train_step": (C.c_int, [_P, _P, _P, _P]),
     "fftc_nn_adam_step": (C.c_int, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "fftc_nn_last_error": (C.c_char_p, [_P]),
@@ -373,13 +373,13 @@ def fftc_nn_get_grad(nn, grad_dev):
     _nncheck(nn, load().fftc_nn_get_grad(nn, _dev(grad_dev)), "fftc_nn_get_grad")
 
 
-def fftc_nn_features(h, feat_dev):
-    _check(h, load().fftc_nn_features(h, _dev(feat_dev)), "fftc_nn_features")
+def fftc_nn_features(h, feat_dev, u1_dev):
+    _check(h, load().fftc_nn_features(h, _dev(feat_dev), _dev(u1_dev)), "fftc_nn_features")
 
 
-def fftc_nn_forward(nn, feat_dev, y_dev=None, s_u=1.0, u0_dev=None):
-    _nncheck(nn, load().fftc_nn_forward(nn, _dev(feat_dev), _dev(y_dev), float(s_u), _dev(u0_dev)),
-             "fftc_nn_forward")
+def fftc_nn_forward(nn, feat_dev, y_dev=None, s_u=1.0, base_dev=None, u0_dev=None):
+    _nncheck(nn, load().fftc_nn_forward(nn, _dev(feat_dev), _dev(y_dev), float(s_u), _dev(base_dev),
+                                        _dev(u0_dev)), "fftc_nn_forward")
 
 
 def fftc_nn_train_step(nn, feat_dev, target_dev, loss_dev=None):
@@ -442,9 +442,9 @@ class Net:
         fftc_nn_get_grad(self.h, t)
         return t
 
-    def forward(self, feat, s_u=1.0, u0=None):
+    def forward(self, feat, s_u=1.0, base=None, u0=None):
         y = self.torch.empty((feat.shape[0], 3), dtype=self.torch.float32, device=self.device)
-        fftc_nn_forward(self.h, feat, y, s_u, u0)
+        fftc_nn_forward(self.h, feat, y, s_u, base, u0)
         return y
 
     def train_step(self, feat, target, loss=None):
@@ -526,10 +526,13 @@ class Solver:
         return rc, rep
 
     def features(self):
-        """Network input channels, BF16 bits as int16 [Nn][16]."""
-        t = self.torch.empty((int(np.prod(self.N)), FFTC_NN_CHANNELS), dtype=self.torch.int16, device=self.device)
-        fftc_nn_features(self.h, t)
-        return t
+        """Network input channels (BF16 bits as int16 [Nn][16]) and the first iterate
+        (FP64 [3][Nn]) they carry."""
+        Nn = int(np.prod(self.N))
+        t = self.torch.empty((Nn, FFTC_NN_CHANNELS), dtype=self.torch.int16, device=self.device)
+        u1 = self.torch.empty((3, Nn), dtype=self.torch.float64, device=self.device)
+        fftc_nn_features(self.h, t, u1)
+        return t, u1
 
     def solve_judged(self, u0):
         return fftc_solve_judged(self.h, u0, self.u)

@@ -1259,10 +1259,23 @@ int fftc_batch_solve(fftc_batch_h b, double* const* u_dev, int32_t zero_start, f
   return worst;
 }
 
-int fftc_nn_features(fftc_h h, uint16_t* feat_dev) {
-  if (!h || !feat_dev) return FFTC_E_ARG;
+int fftc_nn_features(fftc_h h, uint16_t* feat_dev, double* u1_dev) {
+  if (!h || !feat_dev || !u1_dev) return FFTC_E_ARG;
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set first");
+  // first iterate from the plain start
+  int rc = solve_init(h, nullptr, 1);
+  if (rc != FFTC_OK) return rc;
+  enqueue_iter(h);
+  const long long n3 = 3 * h->Nn;
+  if (h->delta_mode) {
+    HIPCHK(h, hipMemcpyAsync(u1_dev, dbufs(h).u, 8 * n3, hipMemcpyDeviceToDevice, h->stream));
+  } else if (h->precision == FFTC_FP64) {
+    HIPCHK(h, hipMemcpyAsync(u1_dev, bufs<double>(h).u, 8 * n3, hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    launch_convert<float, double>(bufs<float>(h).u, u1_dev, n3, h->stream);
+  }
   nnk::FeatArgs a{};
+  a.u1 = u1_dev;
   for (int J = 0; J < 3; ++J) {
     a.n[J] = h->n[J];
     a.N[J] = h->N[J];

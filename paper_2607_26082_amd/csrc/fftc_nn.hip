@@ -29,7 +29,7 @@ namespace nnk {
 constexpr int kW = FFTC_NN_WIDTH;     // 32
 constexpr int kH = FFTC_NN_HIDDEN;    // 64
 constexpr int kCh = FFTC_NN_CHANNELS; // 16
-constexpr int kCin = 9;
+constexpr int kCin = 12;
 constexpr int kCout = 3;
 constexpr int kMaxN = 257;
 constexpr int kMaxM = 6;
@@ -336,6 +336,7 @@ struct HeadArgs {
   const uint16_t* h;      // [Nn][64]
   float* y;               // [Nn][3] or null
   double* u0;             // [3][Nn] or null
+  const double* base;     // [3][Nn] or null: u0 = base + s_u y
   double s_u;
   // training
   const uint16_t* hpre;   // [Nn][64]
@@ -380,7 +381,8 @@ __global__ __launch_bounds__(kHeadBlock) void k_head(HeadArgs a) {
 #pragma unroll
       for (int c = 0; c < kCout; ++c) {
         if (a.y) a.y[(size_t)node * kCout + c] = y[c];
-        if (a.u0) a.u0[(size_t)c * a.Nn + node] = a.s_u * (double)y[c];
+        if (a.u0)
+          a.u0[(size_t)c * a.Nn + node] = (a.base ? a.base[(size_t)c * a.Nn + node] : 0.0) + a.s_u * (double)y[c];
       }
     } else {
       const float ti = *a.tinv;
@@ -444,6 +446,22 @@ __global__ __launch_bounds__(256) void k_sq_partial(const float* t, long long n,
     const double v = t[i];
     s += v * v;
   }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// per-block sums of b^2 over the first-iterate channels 9..11 of the input
+__global__ __launch_bounds__(256) void k_sq_feat(const uint16_t* feat, int Nn, double* part) {
+  __shared__ double sred[4];
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < Nn; i += gridDim.x * 256)
+#pragma unroll
+    for (int c = 9; c < 12; ++c) {
+      const double v = bf2f(feat[(size_t)i * kCh + c]);
+      s += v * v;
+    }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -579,6 +597,7 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a) {
   float f[kCh];
   for (int c = 0; c < kCh; ++c) f[c] = 0.0f;
   f[0] = (float)(Es / cnt / a.scratch[256]);
+  for (int c = 0; c < 3; ++c) f[9 + c] = (float)(a.u1[c * a.Nn + nd] / a.s_u);
   f[1] = (float)(ns / cnt);
   const uint8_t mk = a.mask[nd];
   for (int c = 0; c < 3; ++c) {
@@ -706,7 +725,7 @@ size_t ws_layout(const fftc_nn* nn, const int N[3], int training, size_t* off /*
   off[q++] = o; o += al(4 * (size_t)kRedGrid * 4 * std::max(nn->KP * kW, kH * (kW + 1)));  // part
   off[q++] = o; o += al(2 * (size_t)kW * nn->KP);                                // P16
   const size_t nhead = (Nn + kHeadBlock - 1) / kHeadBlock;
-  off[q++] = o; o += al(8 * (std::max<size_t>(nhead, 1024) + 8));               // dsc
+  off[q++] = o; o += al(8 * (std::max<size_t>(nhead, 1024) + 16));              // dsc
   off[q++] = o; o += al(16);                                                     // tinv
   return o;
 }
@@ -929,7 +948,8 @@ int fftc_nn_get_grad(fftc_nn_h nn, float* grad_dev) {
   return FFTC_OK;
 }
 
-int fftc_nn_forward(fftc_nn_h nn, const uint16_t* feat_dev, float* y_dev, double s_u, double* u0_dev) {
+int fftc_nn_forward(fftc_nn_h nn, const uint16_t* feat_dev, float* y_dev, double s_u, const double* base_dev,
+                    double* u0_dev) {
   if (!nn || !feat_dev) return FFTC_E_ARG;
   if (!nn->state_bound || !nn->bound) return nfail(nn, FFTC_E_STATE, "state and workspace must be bound");
   const int tr = nn->training;
@@ -943,6 +963,7 @@ int fftc_nn_forward(fftc_nn_h nn, const uint16_t* feat_dev, float* y_dev, double
   a.h = nn->h;
   a.y = y_dev;
   a.u0 = u0_dev;
+  a.base = base_dev;
   a.s_u = s_u;
   hipLaunchKernelGGL(k_head<false>, dim3((nn->d.Nn + kHeadBlock - 1) / kHeadBlock), dim3(kHeadBlock), 0, nn->stream,
                      a);
@@ -967,7 +988,8 @@ int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* targ
   double* lossd = nn->dsc + 1;
   double* dpart = nn->dsc + 8;
   hipLaunchKernelGGL(k_sq_partial, dim3(nsq), dim3(256), 0, s, target_dev, 3ll * Nn, dpart);
-  hipLaunchKernelGGL(k_sq_final, dim3(1), dim3(64), 0, s, (const double*)dpart, nsq, tsum, nn->tinv);
+  hipLaunchKernelGGL(k_sq_feat, dim3(nsq), dim3(256), 0, s, feat_dev, Nn, dpart + nsq);
+  hipLaunchKernelGGL(k_sq_final, dim3(1), dim3(64), 0, s, (const double*)dpart, 2 * nsq, tsum, nn->tinv);
   // output layer: loss, dy, dhpre
   const int nh = (Nn + kHeadBlock - 1) / kHeadBlock;
   HeadArgs a{};

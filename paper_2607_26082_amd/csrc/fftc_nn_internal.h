@@ -23,6 +23,7 @@ struct FeatArgs {
   int has_sphere;
   double center[3], radius;
   int face;
+  const double* u1;        // first iterate, FP64 [3][Nn]
   double* scratch;         // >= 257 doubles of device scratch
   uint16_t* feat;          // [Nn][16] BF16
 };

@@ -2,7 +2,8 @@
 
 Training data are solves of the library itself: learned-start cases
 (workloads.nn_case, two-phase cells with Dirichlet patches or a rigid-sphere
-indentation) solved in the FP32 form to 1e-6.  Input channels, the network's
+indentation) solved in the FP32 form to 1e-6; the target is the converged
+field's difference to the first iterate, in units of s_u.  Input channels, the network's
 forward and backward passes, Adam and the judged start all run in the
 library's kernels; this module only schedules calls and keeps the data on the
 device.
@@ -56,7 +57,7 @@ def _log(msg):
 
 def make_dataset(specs, n0=N0, log=_log):
     """Solve every case (FP32 form, tol 1e-6, one at a time) and keep its input
-    channels and its converged displacement / s_u on the device."""
+    channels and (converged field - first iterate) / s_u on the device."""
     import torch
     import paper_2607_26082_amd as F
     N = tuple(v + 1 for v in n0)
@@ -67,12 +68,13 @@ def make_dataset(specs, n0=N0, log=_log):
     tgt = torch.empty((S, 3, Nn), dtype=torch.float32, device="cuda")
     ok = np.zeros(S, bool)
     iters = np.zeros(S, np.int64)
+    u1 = torch.empty((3, Nn), dtype=torch.float64, device="cuda")
     t0 = time.perf_counter()
     for i, prob in enumerate(cases(specs)):
         g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=4000)
+        F.fftc_nn_features(g.h, feat[i], u1)
         rc, r = g.solve()
-        F.fftc_nn_features(g.h, feat[i])
-        tgt[i].copy_((g.u.reshape(3, Nn) / su).to(torch.float32))
+        tgt[i].copy_(((g.u.reshape(3, Nn) - u1) / su).to(torch.float32))
         ok[i] = r.status == 0
         iters[i] = r.iterations
         del g
@@ -127,8 +129,8 @@ def evaluate(net, specs, scale=1, ref64=0, log=_log):
         t_plain = time.perf_counter() - t0
         u_plain = g.u.clone()
         t0 = time.perf_counter()
-        feat = g.features()
-        net.forward(feat, s_u=su, u0=u0)
+        feat, u1 = g.features()
+        net.forward(feat, s_u=su, base=u1, u0=u0)
         rc_n, rep_n, used, res = g.solve_judged(u0)
         torch.cuda.synchronize()
         t_nn = time.perf_counter() - t0
@@ -245,7 +247,7 @@ def main(argv=None):
 
 def _layout(net):
     """Parameter shapes in the order of include/fftc_nn.h."""
-    m3, out = net.modes ** 3, [(32, 9), (32,)]
+    m3, out = net.modes ** 3, [(32, 12), (32,)]
     for _ in range(net.blocks):
         out += [(m3, 32, 32), (32, 32), (32,)]
     return out + [(64, 32), (64,), (3, 64), (3,)]

@@ -35,7 +35,7 @@ def _torch():
 def _feat_dev(torch, f):
     bits = np.zeros((f.shape[0], 16), np.uint16)
     bits[:, :f.shape[1]] = _bf16_bits(f)
-    return torch.as_tensor(bits.view(np.int16), device="cuda"), _bf16_val(bits[:, :9])
+    return torch.as_tensor(bits.view(np.int16), device="cuda"), _bf16_val(bits[:, :f.shape[1]])
 
 
 def _rel(a, b):
@@ -60,29 +60,37 @@ def test_features_match_oracle(case):
         prob.bc[:, 0, :] = W.BC_P
     print(f"[nn features] {case} n={prob.n}", flush=True)
     g = F.Solver.from_problem(prob, precision=prec)
-    got = g.features().cpu().numpy().view(np.uint16)
-    ref = onn.features(prob)
+    feat, u1 = g.features()
+    got = feat.cpu().numpy().view(np.uint16)
+    u1 = u1.cpu().numpy()
     if prec == "fp32":
         # the solver keeps FP32 Lame fields: the oracle sees the same rounded inputs
         import dataclasses
-        prob32 = dataclasses.replace(prob, lam=prob.lam.astype(np.float32).astype(np.float64),
-                                     mu=prob.mu.astype(np.float32).astype(np.float64))
-        ref = onn.features(prob32)
+        prob = dataclasses.replace(prob, lam=prob.lam.astype(np.float32).astype(np.float64),
+                                   mu=prob.mu.astype(np.float32).astype(np.float64))
+    u1_ref = onn.first_iterate(prob).reshape(3, -1)
+    # the first iterate: FP64 path to rounding, FP32 form to its arithmetic
+    assert np.linalg.norm(u1 - u1_ref) <= (1e-12 if prec == "fp64" else 1e-5) * np.linalg.norm(u1_ref)
+    ref = onn.features(prob, u1=u1_ref)
     want = _bf16_bits(ref)
     np.testing.assert_array_equal(got[:, 2:5], want[:, 2:5])
-    assert not got[:, 9:].any()
-    d = np.abs(got[:, :9].astype(np.int64) - want.astype(np.int64))
+    assert not got[:, 12:].any()
+    d = np.abs(got[:, :9].astype(np.int64) - want[:, :9].astype(np.int64))
     assert d.max() <= 1, (case, int(d.max()))
+    # first-iterate channels: BF16 of u1 / s_u (the FP32 form differs from FP64 below 1e-5)
+    gv, wv = _bf16_val(got[:, 9:12]), ref[:, 9:12]
+    assert (np.abs(gv - wv) <= 2.0 ** -8 * np.abs(wv) + 1e-5 * np.abs(wv).max()).all(), case
 
 
 def _net_case(seed, N, modes=6, blocks=4):
-    shape = dict(width=32, modes=modes, blocks=blocks, hidden=64, cin=9, cout=3)
+    shape = dict(width=32, modes=modes, blocks=blocks, hidden=64, cin=12, cout=3)
     shapes = [s for _, s in onn.param_layout(**shape)]
     vec = W.nn_init(seed, shapes).astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(seed + 1)
     Nn = int(np.prod(N))
     f = np.concatenate([rng.uniform(0, 1, (Nn, 2)), (rng.random((Nn, 3)) < 0.2).astype(float),
-                        rng.standard_normal((Nn, 3)), rng.uniform(-0.2, 0.2, (Nn, 1))], 1)
+                        rng.standard_normal((Nn, 3)), rng.uniform(-0.2, 0.2, (Nn, 1)),
+                        rng.standard_normal((Nn, 3))], 1)
     t = rng.standard_normal((Nn, 3)).astype(np.float32).astype(np.float64)
     return shape, vec, f, t
 
@@ -101,12 +109,13 @@ def test_forward_matches_oracle(N, modes, blocks):
     net.bind(N, training=False)
     fd, fval = _feat_dev(torch, f)
     u0 = torch.zeros((3, int(np.prod(N))), dtype=torch.float64, device="cuda")
-    y = net.forward(fd, s_u=0.5, u0=u0)
+    base = torch.randn((3, int(np.prod(N))), dtype=torch.float64, device="cuda")
+    y = net.forward(fd, s_u=0.5, base=base, u0=u0)
     torch.cuda.synchronize()
     y = y.cpu().numpy().astype(np.float64)
     yr, _ = onn.forward(onn.unflatten(vec, **shape), fval, N, blocks=blocks, m=modes)
     assert _rel(y, yr) <= 1e-2, _rel(y, yr)
-    np.testing.assert_allclose(u0.cpu().numpy(), 0.5 * y.T, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(u0.cpu().numpy(), base.cpu().numpy() + 0.5 * y.T, rtol=1e-6, atol=1e-7)
 
 
 @pytest.mark.parametrize("N,modes,blocks", NETS)
@@ -124,7 +133,7 @@ def test_gradient_matches_oracle(N, modes, blocks):
     g = net.grad().cpu().numpy().astype(np.float64)
     p = onn.unflatten(vec, **shape)
     y, cache = onn.forward(p, fval, N, blocks=blocks, m=modes)
-    L, dy = onn.loss(y, t)
+    L, dy = onn.loss(y, t, fval[:, 9:12])
     gr = onn.flatten(onn.backward(p, cache, dy), **shape)
     assert abs(loss.item() - L) <= 1e-2 * L
     assert _cos(g, gr) >= 0.999 and _rel(g, gr) <= 1e-2, (_cos(g, gr), _rel(g, gr))
@@ -167,8 +176,9 @@ def test_training_reduces_loss():
     rc, rep = g.solve()
     assert rc == 0
     su = onn.start_scale(prob.n)
-    tt = (g.u / su).to(torch.float32).contiguous()
-    feat = g.features()
+    ustar = g.u.reshape(3, -1).clone()
+    feat, u1 = g.features()
+    tt = ((ustar - u1) / su).to(torch.float32).contiguous()
     net = F.Net(6, 4)
     net.set_params(W.nn_init(3, [s for _, s in onn.param_layout()]))
     net.bind(N, training=True)

@@ -16,9 +16,9 @@ from oracle.plan import Plan
 
 
 def test_param_count_closed_form():
-    w, m, B, H, cin, cout = 32, 6, 4, 64, 9, 3
+    w, m, B, H, cin, cout = 32, 6, 4, 64, 12, 3
     expect = w * cin + w + B * (m ** 3 * w * w + w * w + w) + H * w + H + cout * H + cout
-    assert nn.num_params() == expect == 891587
+    assert nn.num_params() == expect == 891683
 
 
 def test_analysis_is_truncated_dct2():
@@ -107,6 +107,9 @@ def test_loss_zero_at_target_and_gradient_direction():
     l1, d1 = nn.loss(2 * t, t)
     assert abs(l1 - 1.0) < 1e-15
     np.testing.assert_allclose(d1, 2 * t / (t * t).sum(), rtol=1e-15)
+    # with b the normaliser is the size of t and b together: here half of it
+    l2, _ = nn.loss(2 * t, t, t)
+    assert abs(l2 - 0.5) < 1e-15
 
 
 def test_adam_first_step_closed_form():
@@ -121,7 +124,7 @@ def test_adam_first_step_closed_form():
 
 def test_features_homogeneous_indentation():
     prob = W.c3_indentation(n=(8, 6, 5), R=4.0, d_over_R=0.05)
-    f = nn.features(prob).reshape(6, 7, 9, 9)          # [Nz, Ny, Nx, ch]
+    f = nn.features(prob).reshape(6, 7, 9, 12)         # [Nz, Ny, Nx, ch]
     np.testing.assert_allclose(f[..., 0], 1.0, rtol=1e-15)
     np.testing.assert_allclose(f[..., 1], 0.3, rtol=1e-14)
     # bottom face: every component fixed; nothing else prescribed
@@ -131,6 +134,9 @@ def test_features_homogeneous_indentation():
     assert abs(f[5, 3, 4, 8] - np.tanh(-0.2 / 0.04)) < 1e-15
     # off the top face the channel is 0; a top corner sits outside the sphere
     assert not f[:5, :, :, 8].any() and f[5, 0, 0, 8] > 0
+    # the first iterate: held at 0 on the fixed bottom, pressed down under the sphere
+    u1 = f[..., 9:12] * 0.005
+    assert not u1[0].any() and u1[5, 3, 4, 2] < 0
 
 
 def test_features_patch_cell():
@@ -152,6 +158,8 @@ def test_features_patch_cell():
     E = prob.mu * (3 * prob.lam + 2 * prob.mu) / (prob.lam + prob.mu)
     assert np.isclose(f[:, 0], E.min() / E.max(), rtol=1e-14).any()
     assert not f[:, 8].any()
+    # the first iterate satisfies the prescribed values exactly (proj_U ends the iteration)
+    np.testing.assert_allclose(f[:, 9:12][fixed], val[fixed], rtol=1e-13, atol=1e-15)
 
 
 def test_nn_init_scales():
