@@ -1,0 +1,105 @@
+"""The 256^3 benchmark workload at full size.
+
+- FP32 residual form (the benchmarked path: tiled residual pass, autotuned transform
+  blocks) against the FP64 path on the same problem: relative L2 of the converged
+  displacements <= 1e-5 (GPU FP32 to 1e-6, FP64 to 1e-10; the FP64 path is pinned to the
+  oracle at small sizes).
+- FP64 residual pass at full size against the oracle node by node: the residual of a
+  node depends only on u in its 3x3x3 node neighbourhood and on its 8 voxels, so the
+  oracle evaluates it on a 4x4x4-voxel sub-block cut around the node (the faces of the
+  sub-block that are not faces of the cell are traction-free; the node is at least one
+  voxel away from them, so they do not enter its residual)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tetra2
+from oracle.plan import Plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2607_26082_amd as F
+    F.load()
+    return F
+
+
+def _sub_residual(prob, u, node):
+    """Oracle residual p (boundary weight included, before proj_P) at one node."""
+    nx, ny, nz = prob.n
+    lo, hi, loc = [], [], []
+    bc = np.full((3, 3, 2), W.BC_N, np.int8)
+    for J, (c, nJ) in enumerate(zip(node, (nx, ny, nz))):
+        a, b = max(c - 2, 0), min(c + 2, nJ)
+        lo.append(a)
+        hi.append(b)
+        loc.append(c - a)
+        if a == 0:
+            bc[:, J, 0] = prob.bc[:, J, 0]
+        if b == nJ:
+            bc[:, J, 1] = prob.bc[:, J, 1]
+    sub_n = tuple(h - l for l, h in zip(lo, hi))
+    plan = Plan(sub_n, bc)
+    us = u[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+    lam = prob.lam[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+    mu = prob.mu[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+    G = tetra2.tet_gradients(us, plan)
+    p = plan.w2b[None] * tetra2.divergence(tetra2.stress(G, lam, mu), plan)
+    p[plan.amask] = 0.0
+    return p[:, loc[2], loc[1], loc[0]]
+
+
+def test_m256_fp32_form_matches_fp64():
+    F = _lib()
+    prob = W.m256_metric()
+    print("[m256] fp64 solve", flush=True)
+    g64 = F.Solver.from_problem(prob, precision="fp64", tol=1e-10, max_iter=20000)
+    rc, rep64 = g64.solve()
+    assert rc == 0
+    u64 = g64.u.clone()
+    _, _, t64 = g64.reactions()
+    del g64
+    print(f"[m256] fp64 {rep64.iterations} iterations; fp32 solve", flush=True)
+    g32 = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=20000)
+    rc, rep32 = g32.solve()
+    assert rc == 0
+    rel = float((g32.u - u64).norm() / u64.norm())
+    _, _, t32 = g32.reactions()
+    print(f"[m256] fp32 {rep32.iterations} iterations, rel-L2 {rel:.3e}, reaction z {t32[0, 2]:.6e} vs {t64[0, 2]:.6e}",
+          flush=True)
+    assert rel <= 1e-5
+    assert abs(t32[0, 2] - t64[0, 2]) <= 1e-4 * abs(t64[0, 2])
+
+
+def test_m256_residual_sampled_against_oracle():
+    F = _lib()
+    prob = W.m256_metric()
+    nx, ny, nz = prob.n
+    rng = np.random.default_rng(41)
+    # a smooth field plus noise, so that every term of the stencil matters
+    z, y, x = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    u = np.stack([np.sin(0.05 * x + 0.02 * y) * z / nz, np.cos(0.03 * y) * x / nx, 0.01 * z * y / ny])
+    u = u + 1e-2 * rng.standard_normal(u.shape)
+    u[:, 0] = 0.0                                   # bottom face: every component fixed
+    g = F.Solver.from_problem(prob, precision="fp64", tol=1e-10)
+    print("[m256] fp64 residual pass on a 256^3 field", flush=True)
+    p, _, _ = g.stage_residual(u)
+    strong = np.zeros((3, nz + 1, ny + 1, nx + 1), bool)
+    for s in prob.strong:
+        strong[s.comp, s.node[:, 2], s.node[:, 1], s.node[:, 0]] = True
+    nodes = [tuple(int(v) for v in rng.integers(1, [nx, ny, nz])) for _ in range(150)]
+    nodes += [(int(a), int(b), nz) for a, b in rng.integers(0, [nx + 1, ny + 1], (50, 2))]   # top face
+    nodes += [(0, int(b), int(c)) for b, c in rng.integers(1, [ny, nz], (25, 2))]          # x = 0 face
+    worst = 0.0
+    for nd in nodes:
+        ref = _sub_residual(prob, u, nd)
+        got = p[:, nd[2], nd[1], nd[0]]
+        for c in range(3):
+            if strong[c, nd[2], nd[1], nd[0]]:
+                assert got[c] == 0.0
+                continue
+            scale = max(abs(ref[c]), 1e-3 * np.abs(ref).max(), 1e-12)
+            worst = max(worst, abs(got[c] - ref[c]) / scale)
+    print(f"[m256] sampled residual worst relative difference {worst:.2e}", flush=True)
+    assert worst <= 1e-11
