@@ -100,6 +100,32 @@ def cpu_baseline(prob, iters=2):
                       f"(default workers=1) single-threaded"}
 
 
+def bench_warmstart(args):
+    """Held-out learned-start cases (64^3, or 128^3 with --n 128): per case the plain solve
+    and the judged network start (input channels and inference charged), FP32 form to 1e-6."""
+    import workloads as W
+    from paper_2607_26082_amd import warmstart as WS
+    scale = max(1, args.n // 64)
+    specs = WS.make_specs([W.NN_EVAL_SEED + j for j in range(args.cells)], workers=8)
+    import torch
+    import paper_2607_26082_amd as F
+    torch.cuda.set_device(0)
+    net = F.Net(6, 4)
+    net.set_params(WS.load_weights())
+    rows = WS.evaluate(net, specs, scale=scale)
+    s = WS.summary(rows)
+    n = 64 * scale
+    out = {
+        "metric": METRIC, "value": s["time_ratio_total"], "unit": "time-to-1e-6 ratio plain/learned",
+        "n_gpus": 1, "steps": len(rows), "warmup": 1, "ms_per_step": 1e3 * s["time_nn_median_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(rows)} held-out learned-start cells at {n}^3 (Dirichlet patches / indentation), "
+                               "FP32 form, tol 1e-6, judged start", "precision": "fp32"},
+        "summary": s,
+    }
+    print(json.dumps(out))
+
+
 def bench_batch(args):
     """64 two-phase cells of uneven size, FP32 form, solved together to 1e-6 as one batch.
 
@@ -165,8 +191,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=5)
-    ap.add_argument("--workload", default="m256", choices=["m256", "c4"],
-                    help="m256: 256^3 iteration throughput; c4: 64 uneven cells solved as one batch")
+    ap.add_argument("--workload", default="m256", choices=["m256", "c4", "c5"],
+                    help="m256: 256^3 iteration throughput; c4: 64 uneven cells solved as one batch; "
+                         "c5: time to 1e-6 with the learned start vs the plain start on held-out cases")
     ap.add_argument("--cells", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -174,6 +201,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload == "c5":
+        return bench_warmstart(args)
 
     import torch
     import paper_2607_26082_amd as F

@@ -206,3 +206,24 @@ def test_judged_start_uses_good_start_and_falls_back_on_bad():
     assert not used3 and r_bad >= r_plain3
     assert rep3.iterations == rep.iterations and rc3 == 0
     np.testing.assert_array_equal(g.u.cpu().numpy(), good.cpu().numpy())
+
+
+def test_trained_network_judged_start_on_held_out_cases():
+    """What the trained network (paper_2607_26082_amd/data, trained by warmstart.py on
+    1881 converged 64^3 solves) gains on held-out 64^3 cases: the judged start never
+    costs more than the two judge iterations per case over the plain start, and the
+    converged answer is the plain one to the solver tolerance.  The measured gain is
+    printed (on this workload it is about 1.0: the network's start is rarely chosen)."""
+    torch, F = _torch()
+    from paper_2607_26082_amd import warmstart as WS
+    net = F.Net(6, 4)
+    net.set_params(WS.load_weights())
+    specs = [W.nn_case_spec(W.NN_EVAL_SEED + j) for j in range(8)]
+    rows = WS.evaluate(net, specs, scale=1)
+    s = WS.summary(rows)
+    print(f"[nn gain] {s}", flush=True)
+    plain = sum(r["iters_plain"] for r in rows)
+    judged = sum(r["iters_nn"] for r in rows)
+    assert all(r["status"] == [0, 0] for r in rows)
+    assert judged <= 1.1 * plain + 2 * len(rows)
+    assert s["rel_nn_vs_plain_max"] <= 1e-3
