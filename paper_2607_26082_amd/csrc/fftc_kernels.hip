@@ -900,7 +900,13 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   base += (long long)c * a.g.Nn;
   T* rb = (T*)smem;
   cplx<T>* cb = (cplx<T>*)smem;
-  const cplx<T>* tw = (const cplx<T>*)a.ap.tw;
+  // twiddle table e^{-2 pi i s / 4NF}, s < 4NF, staged in LDS after the line buffer
+  cplx<T>* tws = (cplx<T>*)smem + LB * CS;
+  {
+    const cplx<T>* twg = (const cplx<T>*)a.ap.tw;
+    for (int s = threadIdx.x; s < 4 * NF; s += NT) tws[s] = twg[s];
+  }
+  const cplx<T>* tw = tws;
   const int type = a.types[c];
   const int tid = threadIdx.x;
   // phase 1: gather the real lines (each node once; x lines element-fastest, y/z lines
@@ -1005,7 +1011,11 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     const double* qyT = a.cosT + ((c * 3 + 1) * 2 + 1) * a.maxN;
     const double* szT = a.cosT + ((c * 3 + 2) * 2 + 0) * a.maxN;
     const double* qzT = a.cosT + ((c * 3 + 2) * 2 + 1) * a.maxN;
-    const double sy = syT[(int)byi], qy = qyT[(int)byi];
+    // symbol in the transform's precision: M = qz A(x, y) + sz B(x, y) with
+    // A = 4 (a0 sx qy + a1 sy qx + a2 sx sy), B = 4 (a0 qx sy + a1 qy sx + a2 qx qy)
+    const T sy = (T)syT[(int)byi], qy = (T)qyT[(int)byi];
+    const T a0 = (T)a.g.ac[c][0], a1 = (T)a.g.ac[c][1], a2 = (T)a.g.ac[c][2];
+    const T thr = (T)a.thr[c];
     const int x0 = (int)bxi * LB;
 #pragma unroll
     for (int i = 0; i < NO; ++i) {
@@ -1015,8 +1025,11 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
         const int l = w / NN, m = w - l * NN;
         if (l < nl) {
           v = post_ct<T, NF>(type, 0, cb + l * CS, m, tw);
-          const double M = paux_symbol(a.g.ac[c], sxT[x0 + l], qxT[x0 + l], sy, qy, szT[m], qzT[m]);
-          v = (M > a.thr[c]) ? (T)((double)v / M) : T(0);
+          const T sx = (T)sxT[x0 + l], qx = (T)qxT[x0 + l];
+          const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + a2 * sx * sy);
+          const T B = T(4) * (a0 * qx * sy + a1 * qy * sx + a2 * qx * qy);
+          const T M = (T)qzT[m] * A + (T)szT[m] * B;
+          v = (M > thr) ? v / M : T(0);
         }
       }
       vals[i] = v;
@@ -2054,7 +2067,7 @@ static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
   if (a.axis == 0) grid = dim3((Ny + S::LB - 1) / S::LB, Nz, 3);
   else if (a.axis == 1) grid = dim3((Nx + S::LB - 1) / S::LB, Nz, 3);
   else grid = dim3((Nx + S::LB - 1) / S::LB, Ny, 3);
-  const size_t sm = sizeof(cplx<T>) * (size_t)S::LB * S::CS;
+  const size_t sm = sizeof(cplx<T>) * ((size_t)S::LB * S::CS + 4 * NF);
   hipLaunchKernelGGL((k_dtt2<T, NF, NTH>), grid, dim3(S::NT), sm, s, a);
 }
 
