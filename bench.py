@@ -64,7 +64,7 @@ def kernel_source_digest():
 def measured_traffic(precision, kernel):
     """HBM bytes per launch of the dominant kernel from the committed PMC summary, only if
     the kernel sources are unchanged since the counters were taken (else None)."""
-    path = os.path.join(ROOT, "profiles", "residual_d_m256_fp32_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "residual_dt_m256_fp32_traffic.txt")
     if precision != "fp32" or kernel != "residual" or not os.path.exists(path):
         return None
     vals = {}

@@ -855,7 +855,7 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
 // ---------------------------------------------------------------------------
 // DTT pass with a compile-time length (non-periodic axes, n in {16,32,48,64,96,128,256})
 // ---------------------------------------------------------------------------
-template <typename T, int NF, int NTH>
+template <typename T, int NF, int NTH, int TY = -1>
 __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   using S = DttShape<NF, NTH>;
   constexpr int LB = S::LB, NN = S::NN, CS = S::CS, RS = S::RS, NT = S::NT;
@@ -907,7 +907,8 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     for (int s = threadIdx.x; s < 4 * NF; s += NT) tws[s] = twg[s];
   }
   const cplx<T>* tw = tws;
-  const int type = a.types[c];
+  // TY >= 0: every component of this pass has transform type TY (fixed at compile time)
+  const int type = TY >= 0 ? TY : a.types[c];
   const int tid = threadIdx.x;
   // phase 1: gather the real lines (each node once; x lines element-fastest, y/z lines
   // line-fastest).  All loads of a thread are issued before the LDS stores so that many
@@ -921,7 +922,7 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
       double al[4] = {0, 0, 0, 0};
       if (acc_ok)
         for (int q = 0; q < 4; ++q) al[q] = a.st->alpha[q];
-#pragma unroll 2
+#pragma unroll
       for (int i = 0; i < NO; ++i) {
         const int w = tid + i * NT;
         int l, m;
@@ -2059,7 +2060,7 @@ size_t dtt_smem(const AxisPlan& ap) {
   return sizeof(cplx<T>) * (size_t)ap.L * (ap.n + 1) + sizeof(T) * (size_t)ap.L * (ap.N + 1);
 }
 
-template <typename T, int NF, int NTH>
+template <typename T, int NF, int NTH, int TY = -1>
 static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
   using S = DttShape<NF, NTH>;
   const int Nx = a.g.N[0], Ny = a.g.N[1], Nz = a.g.N[2];
@@ -2068,7 +2069,26 @@ static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
   else if (a.axis == 1) grid = dim3((Nx + S::LB - 1) / S::LB, Nz, 3);
   else grid = dim3((Nx + S::LB - 1) / S::LB, Ny, 3);
   const size_t sm = sizeof(cplx<T>) * ((size_t)S::LB * S::CS + 4 * NF);
-  hipLaunchKernelGGL((k_dtt2<T, NF, NTH>), grid, dim3(S::NT), sm, s, a);
+  hipLaunchKernelGGL((k_dtt2<T, NF, NTH, TY>), grid, dim3(S::NT), sm, s, a);
+}
+
+// FP32 passes of the long lines with one transform type for all components get a kernel
+// with that type fixed at compile time (no per-element type dispatch).
+template <typename T, int NF, int NTH>
+static void launch_dtt2_typed(const DttArgs<T>& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4 && (NF == 128 || NF == 256)) {
+    const int t0 = a.types[0];
+    if (a.types[1] == t0 && a.types[2] == t0) {
+      switch (t0) {
+        case T_DCT1: launch_dtt2<T, NF, NTH, T_DCT1>(a, s); return;
+        case T_DCT3: launch_dtt2<T, NF, NTH, T_DCT3>(a, s); return;
+        case T_DST1: launch_dtt2<T, NF, NTH, T_DST1>(a, s); return;
+        case T_DST3: launch_dtt2<T, NF, NTH, T_DST3>(a, s); return;
+        default: break;
+      }
+    }
+  }
+  launch_dtt2<T, NF, NTH>(a, s);
 }
 
 template <typename T>
@@ -2080,8 +2100,8 @@ void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s) {
     const bool hi = a.nt >= NHI;
 #define FFTC_DTT_CASE(L)                                   \
   case L:                                                  \
-    if (hi) launch_dtt2<T, L, NHI>(a, s);                  \
-    else launch_dtt2<T, L, NLO>(a, s);                     \
+    if (hi) launch_dtt2_typed<T, L, NHI>(a, s);            \
+    else launch_dtt2_typed<T, L, NLO>(a, s);               \
     return;
     switch (a.ap.n) {
       FFTC_DTT_CASE(16)

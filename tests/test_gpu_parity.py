@@ -170,3 +170,31 @@ def test_contact_increments(prec):
         tol = 1e-10 if prec == "fp64" else 1e-5
         assert np.linalg.norm(u - o["u"]) <= tol * np.linalg.norm(o["u"])
         assert abs(rep.force_contact - o["force_contact"]) <= 1e-6 * o["force_contact"] + (0 if prec == "fp64" else 1e-4 * o["force_contact"])
+
+
+# (face 0, face 1) codes per transform type, Table 2: SS DCT1, SA DCT3, AA DST1, AS DST3
+_TYPE_BC = {"DCT1": (0, 0), "DCT3": (0, 1), "DST1": (1, 1), "DST3": (1, 0)}
+
+
+@pytest.mark.parametrize("tx,ty", [("DCT1", "DST1"), ("DCT3", "DST3"), ("DST1", "DCT3"), ("DST3", "DCT1")])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_green_uniform_types(tx, ty, prec):
+    """Lines of 256 (x) and 128 (y) whose transform type is the same for all components
+    (the FP32 transform kernels then fix the type at compile time)."""
+    F = _lib()
+    n = (256, 128, 8)
+    print(f"[stage_green uniform] {tx}/{ty} prec={prec}", flush=True)
+    rng = np.random.default_rng(7)
+    lam = rng.uniform(0.3, 3, n[::-1]); mu = rng.uniform(0.2, 2, n[::-1])
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[:, 0, :] = _TYPE_BC[tx]
+    bc[:, 1, :] = _TYPE_BC[ty]
+    bc[:, 2, :] = _TYPE_BC["DST3"]
+    o = OSolver(n, lam, mu, bc, r0_factor=0.9)
+    g = F.Solver(n, lam, mu, bc, r0_factor=0.9, precision=prec)
+    p = rng.standard_normal(o.zeros().shape)
+    p[o.plan.amask] = 0.0
+    ref = o.green.apply(p)
+    out = g.stage_green(p)
+    tol = 1e-12 if prec == "fp64" else 3e-5
+    assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
