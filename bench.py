@@ -105,7 +105,7 @@ def bench_warmstart(args):
     and the judged network start (input channels and inference charged), FP32 form to 1e-6."""
     import workloads as W
     from paper_2607_26082_amd import warmstart as WS
-    scale = max(1, args.n // 64)
+    scale = 2 if args.n == 128 else 1          # held-out cells at 64^3, or at 128^3 with --n 128
     specs = WS.make_specs([W.NN_EVAL_SEED + j for j in range(args.cells)], workers=8)
     import torch
     import paper_2607_26082_amd as F

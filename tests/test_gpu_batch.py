@@ -69,3 +69,23 @@ def test_batch_equals_solo_and_oracle(prec):
         # sides are converged solutions (oracle at 1e-9)
         tol = 1e-5 if prec == "fp32" else 1e-7
         assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref), f"cell {c}"
+
+
+def test_c4_full_batch_equals_solo():
+    """The 64-cell batched workload at full size (27.4M voxels, FP32 form, tol 1e-6): every
+    cell of the batched solve is bitwise the cell solved alone, and every cell converges."""
+    import paper_2607_26082_amd as F
+    F.load()
+    import workloads as W
+    cells = W.c4_batch(64)
+    print(f"[c4] {len(cells)} cells generated", flush=True)
+    solvers = [F.Solver.from_problem(p, precision="fp32", tol=1e-6, max_iter=4000) for p in cells]
+    rc, reps = F.Batch(solvers).solve()
+    assert rc == 0 and all(r.status == 0 for r in reps)
+    ub = [g.u.clone() for g in solvers]
+    its = [r.iterations for r in reps]
+    print(f"[c4] batched iterations {min(its)}..{max(its)}", flush=True)
+    for k, g in enumerate(solvers):
+        rc1, rep1 = g.solve()
+        assert rc1 == 0 and rep1.iterations == reps[k].iterations
+        assert bool((g.u == ub[k]).all()), k
