@@ -2072,11 +2072,11 @@ static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL((k_dtt2<T, NF, NTH, TY>), grid, dim3(S::NT), sm, s, a);
 }
 
-// FP32 passes of the long lines with one transform type for all components get a kernel
-// with that type fixed at compile time (no per-element type dispatch).
+// Passes of the long lines with one transform type for all components get a kernel with
+// that type fixed at compile time (no per-element type dispatch).
 template <typename T, int NF, int NTH>
 static void launch_dtt2_typed(const DttArgs<T>& a, hipStream_t s) {
-  if constexpr (sizeof(T) == 4 && (NF == 128 || NF == 256)) {
+  if constexpr (NF == 128 || NF == 256) {
     const int t0 = a.types[0];
     if (a.types[1] == t0 && a.types[2] == t0) {
       switch (t0) {
