@@ -1,0 +1,127 @@
+"""Host-side logic of the C ABI, checked without a GPU: argument validation and error
+codes of the set-up calls (include/fftc.h, include/fftc_nn.h), constraint bookkeeping and
+workspace sizing.  No call here touches device memory."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+import paper_2607_26082_amd as F
+from oracle import nn as onn
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    if not os.path.exists(F.LIB_PATH):
+        from paper_2607_26082_amd import build
+        build.build()
+    F.load()
+
+
+def _code(fn, *a):
+    try:
+        fn(*a)
+    except F.FftcError as e:
+        return e.code
+    return F.FFTC_OK
+
+
+def test_create_sizes():
+    assert _code(F.fftc_create, (14, 8, 8)) == F.FFTC_E_UNSUPPORTED        # prime factor 7
+    assert _code(F.fftc_create, (1, 8, 8)) == F.FFTC_E_ARG
+    assert _code(F.fftc_create, (8, 8, 5000)) == F.FFTC_E_ARG
+    assert _code(F.fftc_create, (8, 8, 8), 5) == F.FFTC_E_UNSUPPORTED
+    # 3 x nodes must fit 32-bit indices
+    assert _code(F.fftc_create, (1024, 1024, 1024)) == F.FFTC_E_UNSUPPORTED
+    h = F.fftc_create((30, 12, 20))
+    F.fftc_destroy(h)
+
+
+def test_boundary_table_rules():
+    h = F.fftc_create((8, 8, 8))
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[0, 0, 0] = 3
+    assert _code(F.fftc_set_bc, h, bc) == F.FFTC_E_ARG
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[:, 1, 0] = 2                                  # periodic on one face of y only
+    assert _code(F.fftc_set_bc, h, bc) == F.FFTC_E_BC
+    bc[:, 1, 1] = 2
+    F.fftc_set_bc(h, bc)
+    F.fftc_add_dirichlet(h, np.array([[1, 1, 1]]), np.array([0], np.int8), np.array([0.1]))
+    assert _code(F.fftc_set_bc, h, bc) == F.FFTC_E_STATE     # after constraints
+    F.fftc_destroy(h)
+
+
+def test_dirichlet_validation_and_bookkeeping():
+    h = F.fftc_create((8, 6, 4))
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[2, 2, 0] = 1                                  # u_z = 0 on z = 0
+    F.fftc_set_bc(h, bc)
+    add = lambda node, comp, val, sid=0: F.fftc_add_dirichlet(h, np.array(node), np.array(comp, np.int8),
+                                                              np.array(val, np.float64), sid)
+    assert _code(add, [[9, 0, 0]], [0], [0.0]) == F.FFTC_E_ARG          # node outside 0..8
+    assert _code(add, [[1, 1, 1]], [3], [0.0]) == F.FFTC_E_ARG          # component
+    assert _code(add, [[1, 1, 1]], [0], [np.nan]) == F.FFTC_E_ARG
+    assert _code(add, [[1, 1, 1]], [0], [0.1], 64) == F.FFTC_E_ARG      # set id
+    assert _code(add, [[2, 2, 0]], [2], [0.5]) == F.FFTC_E_BC          # nonzero on a held DOF
+    add([[2, 2, 0]], [2], [0.0])                                        # zero there: dropped
+    add([[1, 1, 1], [1, 1, 1]], [0, 1], [0.1, 0.2])
+    assert _code(add, [[1, 1, 1]], [1], [0.3]) == F.FFTC_E_ARG          # DOF constrained twice
+    assert _code(add, [[3, 3, 3], [3, 3, 3]], [2, 2], [0.0, 0.0]) == F.FFTC_E_ARG   # twice in one call
+    ns, nw = C.c_int64(), C.c_int64()
+    F.load().fftc_num_constraints(h, C.byref(ns), C.byref(nw))
+    assert ns.value == 2 and nw.value == 0
+    F.fftc_destroy(h)
+
+
+def test_average_sphere_solver_reference_validation():
+    h = F.fftc_create((8, 8, 8))
+    sup = np.stack(np.meshgrid([2, 3], [2, 3], [2, 3], indexing="ij"), -1).reshape(1, 8, 3)
+    assert _code(F.fftc_add_average, h, sup[:, :6], [0], [0.0]) == F.FFTC_E_ARG   # support of 6
+    F.fftc_add_average(h, sup, [0], [0.01])
+    assert _code(F.fftc_add_average, h, sup, [0], [0.02]) == F.FFTC_E_OVERLAP
+    assert _code(F.fftc_set_sphere, h, [4.0, 4.0, 12.0], -1.0, 5) == F.FFTC_E_ARG
+    assert _code(F.fftc_set_sphere, h, [4.0, 4.0, 12.0], 4.0, 6) == F.FFTC_E_ARG
+    F.fftc_set_sphere(h, [4.0, 4.0, 12.0], 4.0, 5)
+    assert _code(F.fftc_set_solver, h, 1e-6, 100, F.FFTC_ACV_P, 3) == F.FFTC_E_UNSUPPORTED
+    assert _code(F.fftc_set_reference_factor, h, 0.0) == F.FFTC_E_ARG
+    assert _code(F.fftc_set_reference, h, 1.0, -1.0) == F.FFTC_E_ARG
+    F.fftc_destroy(h)
+
+
+def test_workspace_sizes_grow_with_the_grid_and_precision():
+    sizes = {}
+    for n in ((16, 16, 16), (32, 16, 16)):
+        for p in (F.FFTC_FP64, F.FFTC_FP32):
+            h = F.fftc_create(n, p)
+            sizes[n, p] = F.fftc_workspace_bytes(h)
+            F.fftc_destroy(h)
+    for p in (F.FFTC_FP64, F.FFTC_FP32):
+        assert sizes[(32, 16, 16), p] > sizes[(16, 16, 16), p]
+    # at least the fields of each form: 10 node fields (FP64) / FP64 u + 13 FP32 node fields
+    Nn = 17 ** 3
+    assert sizes[(16, 16, 16), F.FFTC_FP64] >= 10 * 3 * Nn * 8
+    assert sizes[(16, 16, 16), F.FFTC_FP32] >= 3 * Nn * 8 + 13 * 3 * Nn * 4
+
+
+@pytest.mark.parametrize("modes,blocks", [(6, 4), (2, 1), (6, 0), (1, 8)])
+def test_network_parameter_count_matches_layout(modes, blocks):
+    nn = F.fftc_nn_create(modes, blocks)
+    assert F.fftc_nn_num_params(nn) == onn.num_params(width=32, modes=modes, blocks=blocks, hidden=64, cin=12, cout=3)
+    assert F.fftc_nn_state_bytes(nn) >= 16 * F.fftc_nn_num_params(nn)
+    F.fftc_nn_destroy(nn)
+
+
+def test_network_shape_limits():
+    assert _code(F.fftc_nn_create, 7, 4) == F.FFTC_E_UNSUPPORTED
+    assert _code(F.fftc_nn_create, 0, 4) == F.FFTC_E_UNSUPPORTED
+    assert _code(F.fftc_nn_create, 6, 9) == F.FFTC_E_UNSUPPORTED
+    nn = F.fftc_nn_create(6, 4)
+    assert _code(F.fftc_nn_workspace_bytes, nn, (1, 8, 8), 0) == F.FFTC_E_UNSUPPORTED
+    assert _code(F.fftc_nn_workspace_bytes, nn, (258, 8, 8), 0) == F.FFTC_E_UNSUPPORTED
+    small = F.fftc_nn_workspace_bytes(nn, (17, 13, 11), 0)
+    train = F.fftc_nn_workspace_bytes(nn, (17, 13, 11), 1)
+    big = F.fftc_nn_workspace_bytes(nn, (65, 65, 65), 0)
+    assert small < train and small < big
+    F.fftc_nn_destroy(nn)
