@@ -198,3 +198,37 @@ def test_stage_green_uniform_types(tx, ty, prec):
     out = g.stage_green(p)
     tol = 1e-12 if prec == "fp64" else 3e-5
     assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
+
+
+DEGENERATE = [((2, 16, 12), None), ((16, 2, 8), 1), ((8, 8, 8), "all"), ((12, 10, 2), 2), ((2, 2, 2), None)]
+
+
+@pytest.mark.parametrize("idx", range(len(DEGENERATE)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_degenerate_grids(idx, prec):
+    """Two-voxel axes (non-periodic and periodic), a fully periodic cell (every
+    singular mode of the symbol present) and a 2x2x2 cell, without constraints."""
+    F = _lib()
+    n, per = DEGENERATE[idx]
+    print(f"[stage degenerate] n={n} periodic={per} prec={prec}", flush=True)
+    rng = np.random.default_rng(300 + idx)
+    lam = rng.uniform(0.3, 3, n[::-1]); mu = rng.uniform(0.2, 2, n[::-1])
+    bc = rng.integers(0, 2, (3, 3, 2)).astype(np.int8)
+    if per == "all":
+        bc[:] = 2
+    elif per is not None:
+        bc[:, per, :] = 2
+    o = OSolver(n, lam, mu, bc, r0_factor=1.1)
+    g = F.Solver(n, lam, mu, bc, r0_factor=1.1, precision=prec)
+    u = rng.standard_normal(o.zeros().shape) * 1e-2
+    u[o.plan.amask] = 0.0
+    parts = o.iterate_parts(u)
+    p, pt, sums = g.stage_residual(u)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.abs(pt - parts["ptil"]).max() <= tol * np.abs(parts["ptil"]).max()
+    q = rng.standard_normal(o.zeros().shape)
+    q[o.plan.amask] = 0.0
+    ref = o.green.apply(q)
+    out = g.stage_green(q)
+    tol = 1e-12 if prec == "fp64" else 3e-5
+    assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
