@@ -188,7 +188,7 @@ __device__ __forceinline__ cplx<T> pre_ct(int type, int inv, const T* x, int k, 
 // that the strided accesses of both FFT passes and of the post-processing fall on
 // distinct LDS banks.
 template <int NF>
-__device__ __forceinline__ int cpad(int i) { return i + i / FftPlan<NF>::R1; }
+__device__ __forceinline__ unsigned cpad(unsigned i) { return i + i / (unsigned)FftPlan<NF>::R1; }
 
 template <typename T, int NF>
 __device__ __forceinline__ T post_ct(int type, int inv, const cplx<T>* Zb, int m, const cplx<T>* tw) {

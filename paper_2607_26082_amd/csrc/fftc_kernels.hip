@@ -15,6 +15,7 @@
 #include "fftc_dtt.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace fftc {
 
@@ -620,18 +621,6 @@ __device__ __forceinline__ double paux_symbol(const double a[3], double sx, doub
 // Residual-form update in the last inverse pass: delta = K0^+ e - (I - Pi) u, u += delta,
 // at node (i, j, k) of component c.
 template <typename T>
-__device__ __forceinline__ double dtt_update_d(const DttArgs<T>& a, int c, int i, int j, int k, T v) {
-  double d = (double)v;
-  const int sg = a.g.sing[c];
-  if (sg) {
-    const double s0 = a.st->sing[2 * c], s1 = a.st->sing[2 * c + 1];
-    const int parity = (i + j + k) & 1;
-    d -= a.g.sing_scale[c] * (s0 + ((sg & 2) ? (parity ? -s1 : s1) : 0.0));
-  }
-  return d;
-}
-
-template <typename T>
 __device__ __forceinline__ void dtt_update(const DttArgs<T>& a, int c, int i, int j, int k, long long addr, T v) {
   double d = (double)v;
   const int sg = a.g.sing[c];
@@ -909,92 +898,109 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   const cplx<T>* tw = tws;
   // TY >= 0: every component of this pass has transform type TY (fixed at compile time)
   const int type = TY >= 0 ? TY : a.types[c];
-  const int tid = threadIdx.x;
-  // phase 1: gather the real lines (each node once; x lines element-fastest, y/z lines
-  // line-fastest).  All loads of a thread are issued before the LDS stores so that many
-  // requests are in flight per wave.
-  {
-    constexpr int NO = (LB * NN + NT - 1) / NT;
-    T vals[NO];
-    if (a.src == SRC_ANDERSON) {
-      const int slot = a.st->i_local & 3;
-      const int acc_ok = a.st->accel_ok;
-      double al[4] = {0, 0, 0, 0};
-      if (acc_ok)
-        for (int q = 0; q < 4; ++q) al[q] = a.st->alpha[q];
-#pragma unroll
-      for (int i = 0; i < NO; ++i) {
-        const int w = tid + i * NT;
-        int l, m;
-        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-        T v = T(0);
-        if (w < LB * NN && l < nl) {
-          const long long addr = base + (long long)(l * lstride + m * estride);
-          if (acc_ok) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sacc += al[q] * ((double)a.B.S[q][addr] + (double)a.B.R[q][addr]);
-            v = (T)sacc;
-          } else {
-            v = a.B.X[addr];
-          }
-        }
-        vals[i] = v;
-      }
-      // the stores of S after all loads (see the residual-form source below)
-      if (a.store_s)
-#pragma unroll
-        for (int i = 0; i < NO; ++i) {
-          const int w = tid + i * NT;
-          int l, m;
-          if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-          if (w < LB * NN && l < nl) a.B.S[slot][base + (long long)(l * lstride + m * estride)] = vals[i];
-        }
-    } else if (a.src == SRC_DELTA) {
-      const T* pcur = a.dp2[a.st->it & 1];
-      const int acc_ok = a.st->accel_ok;
-      const T g0 = acc_ok ? (T)a.st->gamma[0] : T(0), g1 = acc_ok ? (T)a.st->gamma[1] : T(0),
-              g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
-      // all loads first, then the stores of e: a store between the loads would keep
-      // the next load from being issued before it (the pointers may alias)
-#pragma unroll
-      for (int i = 0; i < NO; ++i) {
-        const int w = tid + i * NT;
-        int l, m;
-        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-        T v = T(0);
-        if (w < LB * NN && l < nl) {
-          const long long addr = base + (long long)(l * lstride + m * estride);
-          v = pcur[addr];
-          if (acc_ok) v = v - (g0 * a.dY[0][addr] + g1 * a.dY[1][addr] + g2 * a.dY[2][addr]);
-        }
-        vals[i] = v;
-      }
-#pragma unroll
-      for (int i = 0; i < NO; ++i) {
-        const int w = tid + i * NT;
-        int l, m;
-        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-        if (w < LB * NN && l < nl) a.de[base + (long long)(l * lstride + m * estride)] = vals[i];
-      }
+  const unsigned tid = threadIdx.x;
+  constexpr int TL = NF / FftPlan<NF>::R1;   // threads per line in the FFT passes
+  constexpr int NB = FftPlan<NF>::R1;        // body nodes (m < NF) per thread: LB NF = NT NB
+  // Node ownership, the same in every phase: thread tid owns NB body nodes of the block's LB
+  // lines and, when tid < LB, the last node (m = NF) of line tid.  y and z lines: the line
+  // l = tid % LB is fixed and m = tid / LB + i TL, so that consecutive threads take
+  // consecutive x.  x lines: m = tid % NF is fixed and l = tid / NF + i NT / NF (NF dividing
+  // NT), else the flat index tid + i NT split into (line, node).  Offsets within one component
+  // field fit in 32 bits (3 x nodes < 2^32 is checked at set-up).
+  auto body = [&](auto mk, int i, unsigned& l, unsigned& m) {
+    if constexpr (decltype(mk)::value == 1) {
+      l = tid % LB;
+      m = tid / LB + (unsigned)(i * TL);
+    } else if constexpr (NT % NF == 0) {
+      l = tid / NF + (unsigned)(i * (NT / NF));
+      m = tid % NF;
     } else {
-#pragma unroll
-      for (int i = 0; i < NO; ++i) {
-        const int w = tid + i * NT;
-        int l, m;
-        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-        vals[i] = (w < LB * NN && l < nl) ? a.in[base + (long long)(l * lstride + m * estride)] : T(0);
-      }
+      const unsigned w = tid + (unsigned)(i * NT);
+      l = w / NF;
+      m = w % NF;
     }
+  };
+  // the element loops are compiled once per ownership map (axis is uniform), so that the
+  // fixed line or node of a thread is loop-invariant
+  auto by_map = [&](auto&& f) {
+    if (axis != 0) f(std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 0>{});
+  };
+  const unsigned ls = (unsigned)lstride, es = (unsigned)estride;
+  const bool has_tail = tid < (unsigned)LB;
+  const bool tail_ok = has_tail && (int)tid < nl;
+  const unsigned tail_off = tid * ls + (unsigned)NF * es;
+  // gather the real lines into LDS: all loads of a thread are issued before any store (the
+  // stores of S or e would otherwise hold back the next loads: the pointers may alias)
+  auto gather = [&](auto fetch, auto keep) {
+    by_map([&](auto mk) {
+      T vals[NB + 1];
 #pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      const int w = tid + i * NT;
-      if (w < LB * NN) {
-        int l, m;
-        if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
+      for (int i = 0; i < NB; ++i) {
+        unsigned l, m;
+        body(mk, i, l, m);
+        vals[i] = ((int)l < nl) ? fetch(l * ls + m * es) : T(0);
+      }
+      vals[NB] = tail_ok ? fetch(tail_off) : T(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        unsigned l, m;
+        body(mk, i, l, m);
+        if ((int)l < nl) keep(l * ls + m * es, vals[i]);
+      }
+      if (tail_ok) keep(tail_off, vals[NB]);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        unsigned l, m;
+        body(mk, i, l, m);
         rb[l * RS + m] = vals[i];
       }
-    }
+      if (has_tail) rb[tid * RS + NF] = vals[NB];
+    });
+  };
+  if (a.src == SRC_ANDERSON) {
+    const int slot = a.st->i_local & 3;
+    const int acc_ok = a.st->accel_ok;
+    double al[4] = {0, 0, 0, 0};
+    if (acc_ok)
+      for (int q = 0; q < 4; ++q) al[q] = a.st->alpha[q];
+    T* Sout = a.B.S[slot] + base;
+    const int store_s = a.store_s;
+    const T *S0 = a.B.S[0] + base, *S1 = a.B.S[1] + base, *S2 = a.B.S[2] + base, *S3 = a.B.S[3] + base;
+    const T *R0 = a.B.R[0] + base, *R1 = a.B.R[1] + base, *R2 = a.B.R[2] + base, *R3 = a.B.R[3] + base;
+    const T* X = a.B.X + base;
+    const double al0 = al[0], al1 = al[1], al2 = al[2], al3 = al[3];
+    gather(
+        [&](unsigned off) -> T {
+          if (acc_ok) {
+            double s = al0 * ((double)S0[off] + (double)R0[off]);
+            s += al1 * ((double)S1[off] + (double)R1[off]);
+            s += al2 * ((double)S2[off] + (double)R2[off]);
+            s += al3 * ((double)S3[off] + (double)R3[off]);
+            return (T)s;
+          }
+          return X[off];
+        },
+        [&](unsigned off, T v) {
+          if (store_s) Sout[off] = v;
+        });
+  } else if (a.src == SRC_DELTA) {
+    const T* pcur = a.dp2[a.st->it & 1] + base;
+    const int acc_ok = a.st->accel_ok;
+    const T g0 = acc_ok ? (T)a.st->gamma[0] : T(0), g1 = acc_ok ? (T)a.st->gamma[1] : T(0),
+            g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
+    const T *y0 = a.dY[0] + base, *y1 = a.dY[1] + base, *y2 = a.dY[2] + base;
+    T* de = a.de + base;
+    gather(
+        [&](unsigned off) -> T {
+          T v = pcur[off];
+          if (acc_ok) v = v - (g0 * y0[off] + g1 * y1[off] + g2 * y2[off]);
+          return v;
+        },
+        [&](unsigned off, T v) { de[off] = v; });
+  } else {
+    const T* in = a.in + base;
+    gather([&](unsigned off) -> T { return in[off]; }, [&](unsigned, T) {});
   }
   __syncthreads();
   const int inv_first = (a.mode == PASS_INV);
@@ -1004,8 +1010,7 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     else fft_ct<T, NF, +1, NT>(cb, CS, tw, ld);
   }
   if (a.mode == PASS_FWD_GREEN_INV) {
-    constexpr int NO = (LB * NN + NT - 1) / NT;
-    T vals[NO];
+    // (z lines: block = x chunk bxi of the y plane byi)
     const double* sxT = a.cosT + ((c * 3 + 0) * 2 + 0) * a.maxN;
     const double* qxT = a.cosT + ((c * 3 + 0) * 2 + 1) * a.maxN;
     const double* syT = a.cosT + ((c * 3 + 1) * 2 + 0) * a.maxN;
@@ -1017,87 +1022,100 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     const T sy = (T)syT[(int)byi], qy = (T)qyT[(int)byi];
     const T a0 = (T)a.g.ac[c][0], a1 = (T)a.g.ac[c][1], a2 = (T)a.g.ac[c][2];
     const T thr = (T)a.thr[c];
-    const int x0 = (int)bxi * LB;
+    const unsigned x0 = bxi * LB;
+    auto green = [&](unsigned l, unsigned m) -> T {
+      const T v = post_ct<T, NF>(type, 0, cb + l * CS, m, tw);
+      const T sx = (T)sxT[x0 + l], qx = (T)qxT[x0 + l];
+      const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + a2 * sx * sy);
+      const T B = T(4) * (a0 * qx * sy + a1 * qy * sx + a2 * qx * qy);
+      const T M = (T)qzT[m] * A + (T)szT[m] * B;
+      return (M > thr) ? v / M : T(0);
+    };
+    T vals[NB + 1];
 #pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      const int w = tid + i * NT;
-      T v = T(0);
-      if (w < LB * NN) {
-        const int l = w / NN, m = w - l * NN;
-        if (l < nl) {
-          v = post_ct<T, NF>(type, 0, cb + l * CS, m, tw);
-          const T sx = (T)sxT[x0 + l], qx = (T)qxT[x0 + l];
-          const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + a2 * sx * sy);
-          const T B = T(4) * (a0 * qx * sy + a1 * qy * sx + a2 * qx * qy);
-          const T M = (T)qzT[m] * A + (T)szT[m] * B;
-          v = (M > thr) ? v / M : T(0);
-        }
-      }
-      vals[i] = v;
+    for (int i = 0; i < NB; ++i) {
+      unsigned l, m;
+      body(std::integral_constant<int, 1>{}, i, l, m);
+      vals[i] = ((int)l < nl) ? green(l, m) : T(0);
     }
+    vals[NB] = tail_ok ? green(tid, NF) : T(0);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      const int w = tid + i * NT;
-      if (w < LB * NN) {
-        const int l = w / NN, m = w - l * NN;
-        rb[l * RS + m] = vals[i];
-      }
+    for (int i = 0; i < NB; ++i) {
+      unsigned l, m;
+      body(std::integral_constant<int, 1>{}, i, l, m);
+      rb[l * RS + m] = vals[i];
     }
+    if (has_tail) rb[tid * RS + NF] = vals[NB];
     __syncthreads();
     auto ld = [&](int l, int k) { return pre_ct<T, NF>(type, 1, rb + l * RS, k, tw); };
     if (fft_sign(type, 1) < 0) fft_ct<T, NF, -1, NT>(cb, CS, tw, ld);
     else fft_ct<T, NF, +1, NT>(cb, CS, tw, ld);
   }
-  // phase 4: post-process and scatter
+  // post-process and scatter
   const int inv_out = (a.mode != PASS_FWD);
-  // (the FP64 displacement update only exists in the FP32 residual form)
-  if constexpr (sizeof(T) == 4) if (a.dst == DST_UPDATE) {
-    // read every old u of the thread first, then write u and delta
-    constexpr int NO = (LB * NN + NT - 1) / NT;
-    double uo[NO];
+  if (a.dst == DST_UPDATE) {
+    // residual form, last inverse pass: read every old u of the thread first, then write u
+    // and delta
+    const double* u64r = a.u64 + base;
+    double* u64w = a.u64 + base;
+    T* dw = a.delta + base;
+    // delta = K0^+ e minus the singular-mode part (I - Pi) u (null modes of K0), whose
+    // coefficients are read once
+    const int sg = a.g.sing[c];
+    const double sc = a.g.sing_scale[c];
+    const double s0 = sg ? a.st->sing[2 * c] : 0.0, s1 = sg ? a.st->sing[2 * c + 1] : 0.0;
+    auto upd = [&](T v, unsigned l, unsigned m, unsigned off, double old) {
+      double d = (double)v;
+      if (sg) {
+        const unsigned lg = bxi * LB + l;
+        const unsigned parity = (m + lg + byi) & 1u;   // (i + j + k) mod 2 on every axis
+        d -= sc * (s0 + ((sg & 2) ? (parity ? -s1 : s1) : 0.0));
+      }
+      u64w[off] = old + d;
+      dw[off] = (T)d;
+    };
+    auto update = [&](auto mk, auto guarded) {
+      constexpr bool G = decltype(guarded)::value;
+      double uo[NB + 1];
 #pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      const int w = tid + i * NT;
-      int l, m;
-      if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-      uo[i] = (w < LB * NN && l < nl) ? a.u64[base + (long long)(l * lstride + m * estride)] : 0.0;
-    }
+      for (int i = 0; i < NB; ++i) {
+        unsigned l, m;
+        body(mk, i, l, m);
+        uo[i] = (!G || (int)l < nl) ? u64r[l * ls + m * es] : 0.0;
+      }
+      uo[NB] = tail_ok ? u64r[tail_off] : 0.0;
+      // (the LDS reads are in bounds for every line of the block: only the stores are guarded)
 #pragma unroll
-    for (int i = 0; i < NO; ++i) {
-      const int w = tid + i * NT;
-      int l, m;
-      if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-      if (w >= LB * NN || l >= nl) continue;
-      const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
-      const long long addr = base + (long long)(l * lstride + m * estride);
-      int xi, yj, zk;
-      if (axis == 0) { xi = m; yj = (int)bxi * LB + l; zk = (int)byi; }
-      else if (axis == 1) { xi = (int)bxi * LB + l; yj = m; zk = (int)byi; }
-      else { xi = (int)bxi * LB + l; yj = (int)byi; zk = m; }
-      const double d = dtt_update_d<T>(a, c, xi, yj, zk, v);
-      a.u64[addr] = uo[i] + d;
-      a.delta[addr] = (T)d;
-    }
+      for (int i = 0; i < NB; ++i) {
+        unsigned l, m;
+        body(mk, i, l, m);
+        const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
+        if (!G || (int)l < nl) upd(v, l, m, l * ls + m * es, uo[i]);
+      }
+      if (tail_ok) upd(post_ct<T, NF>(type, inv_out, cb + tid * CS, NF, tw), tid, NF, tail_off, uo[NB]);
+    };
+    if (axis != 0) update(std::integral_constant<int, 1>{}, std::true_type{});
+    else if (nl >= LB) update(std::integral_constant<int, 0>{}, std::false_type{});
+    else update(std::integral_constant<int, 0>{}, std::true_type{});
     return;
   }
-#pragma unroll 4
-  for (int w = tid; w < LB * NN; w += NT) {
-    int l, m;
-    if (axis == 0) { l = w / NN; m = w - l * NN; } else { m = w / LB; l = w - m * LB; }
-    if (l >= nl) continue;
-    const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
-    const long long addr = base + (long long)(l * lstride + m * estride);
-    if (a.dst == DST_UPDATE) {
-      int xi, yj, zk;
-      if (axis == 0) { xi = m; yj = (int)bxi * LB + l; zk = (int)byi; }
-      else if (axis == 1) { xi = (int)bxi * LB + l; yj = m; zk = (int)byi; }
-      else { xi = (int)bxi * LB + l; yj = (int)byi; zk = m; }
-      dtt_update<T>(a, c, xi, yj, zk, addr, v);
-    } else {
-      a.buf[addr] = v;
+  T* out = a.buf + base;
+  // guarded: some lines of the block lie beyond the grid (last chunk only); x lines of a
+  // full block take the unguarded copy, where the thread's fixed node is loop-invariant
+  auto store = [&](auto mk, auto guarded) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      unsigned l, m;
+      body(mk, i, l, m);
+      const T v = post_ct<T, NF>(type, inv_out, cb + l * CS, m, tw);
+      if (!decltype(guarded)::value || (int)l < nl) out[l * ls + m * es] = v;
     }
-  }
+  };
+  if (axis != 0) store(std::integral_constant<int, 1>{}, std::true_type{});
+  else if (nl >= LB) store(std::integral_constant<int, 0>{}, std::false_type{});
+  else store(std::integral_constant<int, 0>{}, std::true_type{});
+  if (tail_ok) out[tail_off] = post_ct<T, NF>(type, inv_out, cb + tid * CS, NF, tw);
 }
 
 // ---------------------------------------------------------------------------
