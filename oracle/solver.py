@@ -183,12 +183,14 @@ class Solver:
         return float(np.sqrt(pnorm2) / np.sqrt(sig2))
 
     # -- Algorithm 1 --------------------------------------------------------
-    def solve(self, u0=None, tol=1e-8, max_iter=2000, acv="P", period=2, history=False):
+    def solve(self, u0=None, tol=1e-8, max_iter=2000, acv="P", period=2, history=False, snapshots=()):
+        """snapshots: iteration counts after which a copy of u is kept (out["snapshots"][k])."""
         u = self.zeros() if u0 is None else np.array(u0, dtype=np.float64, copy=True)
         u[self.plan.amask] = 0.0
         self.cons.proj_U(u)
         acc = Anderson(4, period)
         hist = []
+        snap = {}
         it = 0
         converged = False
         parts = None
@@ -213,10 +215,14 @@ class Solver:
             u[self.plan.amask] = 0.0
             self.cons.proj_U(u)
             it += 1
+            if it in snapshots:
+                snap[it] = u.copy()
         tot = self.cons.totals(parts["f_strong"], parts["f_weak"], self.nsets)
         out = dict(u=u, iterations=it, converged=converged, residual=hist[-1], totals=tot,
                    f_strong=parts["f_strong"], f_weak=parts["f_weak"],
                    mean_stress=tetra2.mean_stress(parts["sig"]))
         if history:
             out["history"] = np.array(hist)
+        if snapshots:
+            out["snapshots"] = snap
         return out

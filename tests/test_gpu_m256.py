@@ -4,6 +4,16 @@
   blocks) against the FP64 path on the same problem: relative L2 of the converged
   displacements <= 1e-5 (GPU FP32 to 1e-6, FP64 to 1e-10; the FP64 path is pinned to the
   oracle at small sizes).
+- The first iterations from the zero start against the oracle's, in the launch
+  configuration the benchmark times: FP64 path, 5 iterations (one accelerated combination
+  at the fifth), to 1e-10; FP32 residual form (tiled residual pass, typed 256-point
+  transform kernels with the autotuned block sizes), 4 iterations, to 1e-5 (relative L2 of
+  u).  The 4 iterations exercise every output of the residual-form pass (K0 delta, R, and
+  the Anderson differences from the third iteration); from the first accelerated
+  combination on, the FP32 iterates depart from the FP64 ones by the sensitivity of the
+  least squares (about 1e-4 at 64^3 to 256^3: its Gram matrix of nearly collinear residual
+  differences, stored in FP32), and the FP32 form is held to solution parity instead
+  (first test above).
 - FP64 residual pass at full size against the oracle node by node: the residual of a
   node depends only on u in its 3x3x3 node neighbourhood and on its 8 voxels, so the
   oracle evaluates it on a 4x4x4-voxel sub-block cut around the node (the faces of the
@@ -15,6 +25,7 @@ import pytest
 import workloads as W
 from oracle import tetra2
 from oracle.plan import Plan
+from oracle.solver import Solver as OSolver
 
 pytestmark = pytest.mark.gpu
 
@@ -70,6 +81,28 @@ def test_m256_fp32_form_matches_fp64():
           flush=True)
     assert rel <= 1e-5
     assert abs(t32[0, 2] - t64[0, 2]) <= 1e-4 * abs(t64[0, 2])
+
+
+def test_m256_iterates_match_oracle():
+    """Rounding bounds: the FP64 path differs from the oracle by the order of its operations
+    (1e-16 per step, a handful of steps); the FP32 form keeps u in FP64 and computes each
+    update in FP32 (transforms of 257-point lines: about log2(256) eps32 = 5e-7 relative)."""
+    F = _lib()
+    prob = W.m256_metric()
+    print("[m256] oracle 5 iterations (FP64, host)", flush=True)
+    o = OSolver.from_problem(prob).solve(tol=0.0, max_iter=5, snapshots=(4, 5))
+    assert o["iterations"] == 5
+    for prec, K, bound in (("fp64", 5, 1e-10), ("fp32", 4, 1e-5)):
+        ref = o["snapshots"][K]
+        print(f"[m256] {prec} {K} iterations", flush=True)
+        g = F.Solver.from_problem(prob, precision=prec, tol=0.0, max_iter=K)
+        rc, rep = g.solve()
+        assert rep.iterations == K, (rc, rep.iterations)
+        u = g.u.cpu().numpy().reshape(ref.shape)
+        rel = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+        print(f"[m256] {prec} rel-L2(u) after {K} iterations {rel:.3e}", flush=True)
+        assert rel <= bound
+        del g
 
 
 def test_m256_residual_sampled_against_oracle():
