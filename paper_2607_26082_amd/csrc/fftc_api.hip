@@ -965,6 +965,7 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     // LDS budget: keep one block within 64 KiB
     const size_t cs = h->precision == FFTC_FP64 ? 16 : 8, rs = cs / 2;
     while (ap.L > 1 && ap.L * ((n + 1) * cs + (ap.N + 1) * rs) > 65536) ap.L /= 2;
+    if (!dtt_covered(h->ept, ap)) return fail(h, FFTC_E_UNSUPPORTED, "transform line too long for one block");
   }
   // symbol tables cos(theta) per (comp, axis)
   std::vector<double> cosT(18 * (size_t)h->maxN, 0.0);

@@ -70,6 +70,23 @@ struct AxisPlan {
   const void* tw;          // e^{-2 pi i t / 4n}, t = 0..4n-1, as (re, im) pairs of the working type
 };
 
+// Runtime-length transform kernel: each Stockham stage of radix R holds its L n / R
+// butterflies in registers, ceil(EPT / R) per thread, so a block covers ceil(EPT / R) kBlock
+// of them.  Elements per thread for a plan: the precision's default (8 FP64, 16 FP32), or 16
+// when the block's L n points exceed 8 kBlock (lines longer than 2048 points).
+__host__ __device__ inline int dtt_ept(int ept, const AxisPlan& ap) {
+  return (ept <= 8 && (long long)ap.L * ap.n <= 8LL * kBlock) ? 8 : 16;
+}
+// true when every stage of the plan is covered by one block
+__host__ __device__ inline bool dtt_covered(int ept, const AxisPlan& ap) {
+  const int e = dtt_ept(ept, ap);
+  for (int s = 0; s < ap.nrad; ++s) {
+    const int r = ap.rad[s];
+    if ((long long)ap.L * ap.n / r > (long long)((e + r - 1) / r) * kBlock) return false;
+  }
+  return true;
+}
+
 template <typename T>
 struct Bufs {
   T* u;        // displacement (also the transform buffer)

@@ -2137,7 +2137,7 @@ void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s) {
   const long long nlines = a.axis == 0 ? (long long)Ny * Nz : a.axis == 1 ? (long long)Nx * Nz : (long long)Nx * Ny;
   const long long nb = (nlines + a.ap.L - 1) / a.ap.L;
   const size_t sm = dtt_smem<T>(a.ap);
-  if (ept <= 8)
+  if (dtt_ept(ept, a.ap) <= 8)
     hipLaunchKernelGGL((k_dtt<T, 8>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
   else
     hipLaunchKernelGGL((k_dtt<T, 16>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);

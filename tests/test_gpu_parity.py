@@ -200,6 +200,39 @@ def test_stage_green_uniform_types(tx, ty, prec):
     assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
 
 
+LONG = [((512, 3, 2), None), ((3, 1000, 2), None), ((2, 3, 4096), None), ((1536, 2, 3), 0), ((2, 3000, 2), None)]
+
+
+@pytest.mark.parametrize("idx", range(len(LONG)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stage_long_lines(idx, prec):
+    """Lines longer than the compile-time transform lengths, up to the largest axis the
+    library accepts (4096 voxels), through the runtime-length transform kernel: residual
+    and Green stages element by element (random BCs; one periodic axis)."""
+    F = _lib()
+    n, per = LONG[idx]
+    print(f"[stage long] n={n} periodic={per} prec={prec}", flush=True)
+    rng = np.random.default_rng(400 + idx)
+    lam = rng.uniform(0.3, 3, n[::-1]); mu = rng.uniform(0.2, 2, n[::-1])
+    bc = rng.integers(0, 2, (3, 3, 2)).astype(np.int8)
+    if per is not None:
+        bc[:, per, :] = 2
+    o = OSolver(n, lam, mu, bc, r0_factor=1.3)
+    g = F.Solver(n, lam, mu, bc, r0_factor=1.3, precision=prec)
+    u = rng.standard_normal(o.zeros().shape)
+    u[o.plan.amask] = 0.0
+    parts = o.iterate_parts(u)
+    p, _, _ = g.stage_residual(u)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.abs(p - parts["p"]).max() <= tol * np.abs(parts["p"]).max()
+    x = rng.standard_normal(o.zeros().shape)
+    x[o.plan.amask] = 0.0
+    ref = o.green.apply(x)
+    out = g.stage_green(x)
+    tol = 1e-12 if prec == "fp64" else 3e-5
+    assert np.abs(out - ref).max() <= tol * np.abs(ref).max()
+
+
 DEGENERATE = [((2, 16, 12), None), ((16, 2, 8), 1), ((8, 8, 8), "all"), ((12, 10, 2), 2), ((2, 2, 2), None)]
 
 
