@@ -172,6 +172,76 @@ def test_contact_increments(prec):
         assert abs(rep.force_contact - o["force_contact"]) <= 1e-6 * o["force_contact"] + (0 if prec == "fp64" else 1e-4 * o["force_contact"])
 
 
+@pytest.mark.parametrize("face", [0, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_contact_other_faces(face, prec):
+    """Potential contact on the x = 0 face and on the y = max face (the opposite face fully
+    fixed, the rest traction-free), two warm-started increments: active sets bit-exact,
+    displacements and contact force against the oracle as on the top face."""
+    F = _lib()
+    n = (16, 24, 20); R = 10.0
+    axis, side = divmod(face, 2)
+    print(f"[contact face {face}] {prec}", flush=True)
+    rng = np.random.default_rng(50 + face)
+    lam = rng.uniform(0.5, 1.5, n[::-1]); mu = rng.uniform(0.4, 1.2, n[::-1])
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[:, axis, 1 - side] = 1
+    cs = ContactSolver(n, lam, mu, bc, face=face, radius=R, r0_factor=5.0)
+    mid = np.array([n[0] / 2.0, n[1] / 2.0, n[2] / 2.0])
+    out = -1.0 if side == 0 else 1.0
+
+    def centre(d):
+        c = mid.copy()
+        c[axis] = (0.0 if side == 0 else n[axis]) + out * (R - d)
+        return c
+
+    g = F.Solver(n, lam, mu, bc, sphere=W.Sphere(centre(0.0), R, face), r0_factor=5.0, precision=prec,
+                 tol=1e-6 if prec == "fp32" else 1e-12)
+    # FP32 bar: 1e-5, or twice the distance from the oracle's own solution stopped at the same
+    # 1e-6 residual to its converged one where the body's conditioning makes that larger
+    # (the y = max face here: 2.4e-5 and 2.0e-5)
+    cs6 = ContactSolver(n, lam, mu, bc, face=face, radius=R, r0_factor=5.0) if prec == "fp32" else None
+    u_o = u_6 = None
+    for k in range(1, 3):
+        c = centre(0.01 * k * R)
+        o = cs.solve_increment(u_o, c, tol=1e-12 if prec == "fp64" else 1e-11)
+        u_o = o["u"]
+        tol = 1e-10
+        if prec == "fp32":
+            u_6 = cs6.solve_increment(u_6, c, tol=1e-6)["u"]
+            tol = max(1e-5, 2.0 * np.linalg.norm(u_6 - u_o) / np.linalg.norm(u_o))
+        g.move_sphere(c)
+        rc, rep = g.solve(zero_start=(k == 1))
+        assert rc == 0
+        mask, fnc, gap = g.contact()
+        assert o["C"].sum() > 0
+        assert np.array_equal(mask.reshape(-1).astype(bool), o["C"])
+        u = g.u.cpu().numpy()
+        print(f"[contact face {face}] {prec} increment {k}: rel-L2 {np.linalg.norm(u - u_o) / np.linalg.norm(u_o):.2e} "
+              f"(bar {tol:.1e})", flush=True)
+        assert np.linalg.norm(u - u_o) <= tol * np.linalg.norm(u_o)
+        assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
+
+
+@pytest.mark.parametrize("acv,period", [("P", 3), ("U", 2), ("NONE", 2)])
+def test_acceleration_variants_fp32(acv, period):
+    """The FP32 forms of the acceleration variants (ACV_U runs the FP32 literal form, the
+    others the residual form): solution parity, GPU at 1e-6 against the oracle at 1e-11."""
+    F = _lib()
+    n = (8, 8, 8)
+    lam, mu, bc, strong, avg = _case(7, n, None)
+    bc[:, 2, 0] = 1
+    print(f"[acv fp32] {acv} {period}", flush=True)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=2.0).solve(tol=1e-11, acv=acv, period=period, max_iter=6000)
+    assert o["converged"]
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=2.0, precision="fp32", tol=1e-6, acv=acv,
+                 period=period, max_iter=6000)
+    rc, rep = g.solve()
+    assert rc == 0 and rep.residual < 1e-6
+    u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-5 * np.linalg.norm(o["u"])
+
+
 # (face 0, face 1) codes per transform type, Table 2: SS DCT1, SA DCT3, AA DST1, AS DST3
 _TYPE_BC = {"DCT1": (0, 0), "DCT3": (0, 1), "DST1": (1, 1), "DST3": (1, 0)}
 
