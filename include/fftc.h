@@ -117,8 +117,8 @@ int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node_host, const int8
                        const double* value_host, int32_t set_id);
 
 /* Kinematic relations: mean of u[comp[r]] over the k nodes of support r equals value[r]
- * (Section 4.2.1, eq 10-14; k = 8 voxel corners or k = 4 face corners).  support_host:
- * m*k triples.  Errors: FFTC_E_ARG, FFTC_E_BC (support node eliminated for comp),
+ * (Section 4.2.1, eq 10-14; k = 8 voxel corners or k = 4 face corners; calls of either
+ * size may be combined in one problem).  support_host: m*k triples.  Errors: FFTC_E_ARG, FFTC_E_BC (support node eliminated for comp),
  * FFTC_E_OVERLAP (a DOF in two supports or also strongly constrained). */
 int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support_host,
                      const int8_t* comp_host, const double* value_host, int32_t set_id);

@@ -30,8 +30,7 @@ struct fftc_problem {
   std::vector<int8_t> s_comp;
   std::vector<double> s_val;
   std::vector<int> s_set;
-  std::vector<long long> w_nodes;
-  int w_k = 0;
+  std::vector<long long> w_nodes;   // kWeakSlots per relation, unused slots -1
   std::vector<int8_t> w_comp;
   std::vector<double> w_val;
   std::vector<int> w_set;
@@ -329,7 +328,7 @@ StrongDev strong_dev(fftc_problem* h) {
 }
 
 WeakDev weak_dev(fftc_problem* h) {
-  WeakDev w{(long long)h->w_comp.size(), h->w_k, h->d_wnodes, h->d_wcomp, h->d_wval, h->wpart, h->wreact};
+  WeakDev w{(long long)h->w_comp.size(), kWeakSlots, h->d_wnodes, h->d_wcomp, h->d_wval, h->wpart, h->wreact};
   return w;
 }
 
@@ -820,7 +819,6 @@ int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, con
   if (!h || m < 0 || (m > 0 && (!support || !comp || !value))) return FFTC_E_ARG;
   if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
   if (k != 4 && k != 8) return fail(h, FFTC_E_ARG, "support size must be 4 or 8");
-  if (h->w_k != 0 && h->w_k != k) return fail(h, FFTC_E_UNSUPPORTED, "all average relations of a problem share one support size");
   if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
   std::unordered_set<long long> mine;
   for (int64_t r = 0; r < m; ++r) {
@@ -836,11 +834,10 @@ int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, con
       mine.insert(key);
     }
   }
-  h->w_k = k;
   for (int64_t r = 0; r < m; ++r) {
-    for (int q = 0; q < k; ++q) {
+    for (int q = 0; q < kWeakSlots; ++q) {
       const int64_t* p = support + (r * k + q) * 3;
-      h->w_nodes.push_back(node_flat(h, p[0], p[1], p[2]));
+      h->w_nodes.push_back(q < k ? node_flat(h, p[0], p[1], p[2]) : -1);
     }
     h->w_comp.push_back(comp[r]);
     h->w_val.push_back(value[r]);
@@ -904,6 +901,7 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     }
     for (size_t e = 0; e < h->w_nodes.size(); ++e) {
       long long nd = h->w_nodes[e];
+      if (nd < 0) continue;
       const long long xyz[3] = {nd % h->N[0], (nd / h->N[0]) % h->N[1], nd / ((long long)h->N[0] * h->N[1])};
       if (xyz[a] == fc) return fail(h, FFTC_E_OVERLAP, "average relation on a potential contact node");
     }
@@ -986,7 +984,8 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
   std::vector<uint8_t> mask(h->Nn, 0);
   for (size_t e = 0; e < h->s_node.size(); ++e) mask[h->s_node[e]] |= (uint8_t)(M_STRONG << h->s_comp[e]);
   for (size_t r = 0; r < h->w_comp.size(); ++r)
-    for (int q = 0; q < h->w_k; ++q) mask[h->w_nodes[r * h->w_k + q]] |= (uint8_t)(M_WEAK << h->w_comp[r]);
+    for (int q = 0; q < kWeakSlots; ++q)
+      if (h->w_nodes[r * kWeakSlots + q] >= 0) mask[h->w_nodes[r * kWeakSlots + q]] |= (uint8_t)(M_WEAK << h->w_comp[r]);
   if (h->has_sphere) {
     const int a = h->face / 2;
     const long long fc = (h->face % 2) ? h->n[a] : 0;

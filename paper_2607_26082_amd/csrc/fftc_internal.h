@@ -118,15 +118,22 @@ struct StrongDev {
   const double* val;
 };
 
+// Average relations: every relation's support (4 or 8 nodes) is stored in kWeakSlots
+// node slots; the unused slots of a 4-node support hold -1.
+constexpr int kWeakSlots = 8;
+
 struct WeakDev {
   long long m;
-  int k;
-  const long long* nodes;   // m*k
+  int k;                    // slots per relation (kWeakSlots)
+  const long long* nodes;   // m*k, unused slots -1
   const int8_t* comp;
   const double* val;
   double* part;             // per relation partial ||p||^2 after projection
   double* react;            // per relation reaction
 };
+
+// support size of relation r (4 or 8)
+__host__ __device__ inline int weak_size(const WeakDev& w, long long r) { return w.nodes[r * w.k + 4] < 0 ? 4 : 8; }
 
 template <typename T>
 struct DttArgs {

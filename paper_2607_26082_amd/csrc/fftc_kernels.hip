@@ -269,9 +269,10 @@ __global__ __launch_bounds__(kBlock) void k_weak(Geo g, Bufs<T> B, WeakDev w, De
   const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (r >= w.m) return;
   const int c = w.comp[r];
+  const int k = weak_size(w, r);
   double phys[8], wb[8];
   double sum = 0.0;
-  for (int s = 0; s < w.k; ++s) {
+  for (int s = 0; s < k; ++s) {
     T p[3];
     int b;
     node_p<T>(g, B, w.nodes[r * w.k + s], p, b);
@@ -279,9 +280,9 @@ __global__ __launch_bounds__(kBlock) void k_weak(Geo g, Bufs<T> B, WeakDev w, De
     phys[s] = (double)p[c] / wb[s];
     sum += phys[s];
   }
-  const double mean = sum / w.k;
+  const double mean = sum / k;
   double pn = 0.0;
-  for (int s = 0; s < w.k; ++s) {
+  for (int s = 0; s < k; ++s) {
     const long long node = w.nodes[r * w.k + s];
     const double pnew = (phys[s] - mean) * wb[s];
     pn += pnew * pnew;
@@ -1127,10 +1128,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_weak(Geo g, T* u, WeakDev w, De
   const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (r >= w.m) return;
   const int c = w.comp[r];
+  const int k = weak_size(w, r);
   double s = 0.0;
-  for (int q = 0; q < w.k; ++q) s += (double)u[c * g.Nn + w.nodes[r * w.k + q]];
-  const double corr = w.val[r] - s / w.k;
-  for (int q = 0; q < w.k; ++q) {
+  for (int q = 0; q < k; ++q) s += (double)u[c * g.Nn + w.nodes[r * w.k + q]];
+  const double corr = w.val[r] - s / k;
+  for (int q = 0; q < k; ++q) {
     const long long idx = c * g.Nn + w.nodes[r * w.k + q];
     u[idx] = (T)((double)u[idx] + corr);
   }
@@ -1864,9 +1866,10 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
   const int c = w.comp[r];
   const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
   const int slot = (il + 1) % 3;
+  const int ks = weak_size(w, r);
   double phys[8], wb[8];
   double sum = 0.0;
-  for (int s = 0; s < w.k; ++s) {
+  for (int s = 0; s < ks; ++s) {
     const long long node = w.nodes[r * w.k + s];
     const int i = (int)(node % g.N[0]);
     const long long q = node / g.N[0];
@@ -1879,9 +1882,9 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
     phys[s] = (double)p[c] / wb[s];
     sum += phys[s];
   }
-  const double mean = sum / w.k;
+  const double mean = sum / ks;
   double pn = 0.0;
-  for (int s = 0; s < w.k; ++s) {
+  for (int s = 0; s < ks; ++s) {
     const long long e = c * g.Nn + w.nodes[r * w.k + s];
     const double pnew = (phys[s] - mean) * wb[s];
     pn += pnew * pnew;
@@ -1988,10 +1991,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_d(Geo g, DeltaBufs<T> D, Strong
   // average relations
   if (e < w.m) {
     const int c = w.comp[e];
+    const int k = weak_size(w, e);
     double sum = 0.0;
-    for (int q = 0; q < w.k; ++q) sum += D.u[c * g.Nn + w.nodes[e * w.k + q]];
-    const double corr = w.val[e] - sum / w.k;
-    for (int q = 0; q < w.k; ++q) {
+    for (int q = 0; q < k; ++q) sum += D.u[c * g.Nn + w.nodes[e * w.k + q]];
+    const double corr = w.val[e] - sum / k;
+    for (int q = 0; q < k; ++q) {
       const long long idx = c * g.Nn + w.nodes[e * w.k + q];
       D.u[idx] += corr;
       D.delta[idx] = (T)((double)D.delta[idx] + corr);

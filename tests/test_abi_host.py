@@ -81,6 +81,11 @@ def test_average_sphere_solver_reference_validation():
     assert _code(F.fftc_add_average, h, sup[:, :6], [0], [0.0]) == F.FFTC_E_ARG   # support of 6
     F.fftc_add_average(h, sup, [0], [0.01])
     assert _code(F.fftc_add_average, h, sup, [0], [0.02]) == F.FFTC_E_OVERLAP
+    face = np.stack(np.meshgrid([5, 6], [5, 6], [8], indexing="ij"), -1).reshape(1, 4, 3)
+    F.fftc_add_average(h, face, [2], [-0.01])           # a 4-node support beside an 8-node one
+    ns, nw = C.c_int64(), C.c_int64()
+    F.load().fftc_num_constraints(h, C.byref(ns), C.byref(nw))
+    assert nw.value == 2
     assert _code(F.fftc_set_sphere, h, [4.0, 4.0, 12.0], -1.0, 5) == F.FFTC_E_ARG
     assert _code(F.fftc_set_sphere, h, [4.0, 4.0, 12.0], 4.0, 6) == F.FFTC_E_ARG
     F.fftc_set_sphere(h, [4.0, 4.0, 12.0], 4.0, 5)

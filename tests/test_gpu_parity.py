@@ -223,6 +223,87 @@ def test_contact_other_faces(face, prec):
         assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
 
 
+def _box(xs, ys, zs):
+    return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
+
+
+def _fp32_bar(u_stop, u_ref):
+    """Solution-parity bar of the FP32 path: 1e-5, or twice the distance from the oracle's
+    own solution stopped at the same 1e-6 residual where the conditioning makes it larger."""
+    return max(1e-5, 2.0 * np.linalg.norm(u_stop - u_ref) / np.linalg.norm(u_ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_weak_face_and_interior_supports(prec):
+    """Average relations with a 4-node face support (pressing the top face) and an 8-node
+    interior support, solved to the end: displacements and the reaction totals of each set."""
+    F = _lib()
+    n = (8, 8, 8)
+    print(f"[weak supports] {prec}", flush=True)
+    rng = np.random.default_rng(61)
+    lam = rng.uniform(0.5, 2, n[::-1]); mu = rng.uniform(0.4, 1.5, n[::-1])
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[:, 2, 0] = 1
+    avg = [W.Average(_box([2, 3], [2, 3], [8])[None], np.array([2], np.int8), np.array([-0.02]), set_id=1),
+           W.Average(_box([4, 5], [3, 4], [3, 4])[None], np.array([0], np.int8), np.array([0.01]), set_id=2)]
+    os_ = OSolver(n, lam, mu, bc, (), avg, r0_factor=1.5)
+    o = os_.solve(tol=1e-12, max_iter=5000)
+    assert o["converged"]
+    g = F.Solver(n, lam, mu, bc, (), avg, r0_factor=1.5, precision=prec, tol=1e-12 if prec == "fp64" else 1e-6,
+                 max_iter=5000)
+    rc, rep = g.solve()
+    assert rc == 0
+    u = g.u.cpu().numpy()
+    _, _, tot = g.reactions()
+    if prec == "fp64":
+        assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
+        assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()
+    else:
+        o6 = OSolver(n, lam, mu, bc, (), avg, r0_factor=1.5).solve(tol=1e-6, max_iter=5000)
+        assert np.linalg.norm(u - o["u"]) <= _fp32_bar(o6["u"], o["u"]) * np.linalg.norm(o["u"])
+        assert np.abs(tot - o["totals"]).max() <= 1e-4 * np.abs(o["totals"]).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_contact_periodic_lateral(prec):
+    """Contact on the top face of a block periodic in x and y (bottom fixed), two
+    warm-started increments: active sets bit-exact, displacements and contact force."""
+    F = _lib()
+    n = (16, 16, 12); R = 8.0
+    print(f"[contact periodic] {prec}", flush=True)
+    rng = np.random.default_rng(62)
+    lam = rng.uniform(0.5, 1.5, n[::-1]); mu = rng.uniform(0.4, 1.2, n[::-1])
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[:, 0, :] = 2
+    bc[:, 1, :] = 2
+    bc[:, 2, 0] = 1
+    cs = ContactSolver(n, lam, mu, bc, face=5, radius=R, r0_factor=5.0)
+    cs6 = ContactSolver(n, lam, mu, bc, face=5, radius=R, r0_factor=5.0) if prec == "fp32" else None
+    centre = lambda d: np.array([8.0, 8.0, 12 + R - d])
+    g = F.Solver(n, lam, mu, bc, sphere=W.Sphere(centre(0.0), R, 5), r0_factor=5.0, precision=prec,
+                 tol=1e-6 if prec == "fp32" else 1e-12)
+    u_o = u_6 = None
+    for k in range(1, 3):
+        c = centre(0.01 * k * R)
+        o = cs.solve_increment(u_o, c, tol=1e-12 if prec == "fp64" else 1e-11)
+        u_o = o["u"]
+        tol = 1e-10
+        if prec == "fp32":
+            u_6 = cs6.solve_increment(u_6, c, tol=1e-6)["u"]
+            tol = _fp32_bar(u_6, u_o)
+        g.move_sphere(c)
+        rc, rep = g.solve(zero_start=(k == 1))
+        assert rc == 0
+        mask, fnc, gap = g.contact()
+        assert o["C"].sum() > 0
+        assert np.array_equal(mask.reshape(-1).astype(bool), o["C"])
+        u = g.u.cpu().numpy()
+        print(f"[contact periodic] {prec} increment {k}: rel-L2 {np.linalg.norm(u - u_o) / np.linalg.norm(u_o):.2e} "
+              f"(bar {tol:.1e})", flush=True)
+        assert np.linalg.norm(u - u_o) <= tol * np.linalg.norm(u_o)
+        assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
+
+
 @pytest.mark.parametrize("acv,period", [("P", 3), ("U", 2), ("NONE", 2)])
 def test_acceleration_variants_fp32(acv, period):
     """The FP32 forms of the acceleration variants (ACV_U runs the FP32 literal form, the
