@@ -96,6 +96,8 @@ class ContactSolver(Solver):
             pf[:, self.face_nodes] = pface_proj.T
             res = self.residual(float(np.sum(p * p)), s2)
             hist.append(res)
+            if not np.isfinite(res):
+                break
             Vgap = (~C) & (g < 0.0)
             Vreact = C & (f_nc > 0.0)
             if res < tol and not Vgap.any() and not Vreact.any():

@@ -176,6 +176,10 @@ class Solver:
 
     @staticmethod
     def residual(pnorm2, sig2):
+        """Equilibrium measure of eq (5), ||p|| / ||sigma||; undefined (NaN) once either norm
+        is no longer finite: the iteration has diverged, whatever the quotient would say."""
+        if not (np.isfinite(pnorm2) and np.isfinite(sig2)):
+            return np.nan
         if pnorm2 == 0.0:
             return 0.0
         if sig2 == 0.0:

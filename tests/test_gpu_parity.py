@@ -223,6 +223,38 @@ def test_contact_other_faces(face, prec):
         assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_solves(prec):
+    """Degenerate inputs of the method: no loads (the solution is 0, found without an
+    iteration), a start at the converged solution (no iteration, u kept), a reference medium
+    far too soft (the iteration diverges and reports it, as the oracle does), and a cell
+    with every voxel void (rejected: no reference medium)."""
+    F = _lib()
+    print(f"[degenerate solves] {prec}", flush=True)
+    p = W.c1_inclusion_patch()
+    g = F.Solver(p.n, p.lam, p.mu, p.bc, precision=prec, tol=1e-6)
+    rc, rep = g.solve()
+    assert rc == 0 and rep.iterations == 0 and not bool(g.u.any())
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    g = F.Solver.from_problem(p, precision=prec, tol=tol)
+    rc, rep = g.solve()
+    assert rc == 0
+    u1 = g.u.clone()
+    rc, rep = g.solve(zero_start=False)
+    assert rc == 0 and rep.iterations == 0
+    assert float((g.u - u1).abs().max()) <= 1e-14 * float(u1.abs().max())
+    o = OSolver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02).solve(tol=p.tol, max_iter=3000)
+    assert not o["converged"]
+    g = F.Solver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02, precision=prec, tol=p.tol,
+                 max_iter=3000)
+    rc, rep = g.solve()
+    assert rc == F.FFTC_E_NAN and rep.iterations < 3000
+    zero = np.zeros_like(p.lam)
+    with pytest.raises(F.FftcError) as e:
+        F.Solver(p.n, zero, zero, p.bc, precision=prec)
+    assert e.value.code == F.FFTC_E_ARG
+
+
 def _box(xs, ys, zs):
     return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
 

@@ -165,3 +165,16 @@ def test_anderson_reduces_to_secant_on_linear_map():
             break
         x = A @ x + b
     assert np.linalg.norm(x - xs) < 1e-8 * np.linalg.norm(xs)
+
+
+def test_too_soft_reference_medium_diverges():
+    """With the reference medium far softer than the stiffest phase the fixed-point map is no
+    contraction and the iterate grows without bound.  The solve must report divergence
+    (an undefined equilibrium measure), never convergence, also when the stress norm
+    overflows before the residual norm (their quotient alone would read 0)."""
+    p = W.c1_inclusion_patch()
+    with np.errstate(over="ignore", invalid="ignore"):
+        o = Solver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02).solve(tol=p.tol, max_iter=3000)
+    assert not o["converged"] and not np.isfinite(o["residual"]) and o["iterations"] < 3000
+    assert np.isnan(Solver.residual(1e307, np.inf)) and np.isnan(Solver.residual(np.inf, 1.0))
+    assert Solver.residual(0.0, 0.0) == 0.0
