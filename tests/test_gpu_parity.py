@@ -255,6 +255,41 @@ def test_degenerate_solves(prec):
     assert e.value.code == F.FFTC_E_ARG
 
 
+@pytest.mark.parametrize("case", ["x", "xy"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_periodic_solves(case, prec):
+    """Full solves with periodic axes (DFT lines, singular modes of the symbol) and strong
+    plus average constraints: one periodic axis with random D/N faces elsewhere, and two
+    periodic axes over a fixed bottom face.  FP64 to 1e-10 at tol 1e-12; FP32 to the
+    solution-parity bar."""
+    F = _lib()
+    print(f"[periodic solve] {case} {prec}", flush=True)
+    if case == "x":
+        n = (12, 10, 8)
+        lam, mu, bc, strong, avg = _case(71, n, 0)
+    else:
+        n = (8, 10, 12)
+        lam, mu, bc, strong, avg = _case(72, n, None)
+        bc[:, 0, :] = 2
+        bc[:, 1, :] = 2
+        bc[:, 2, 0] = 1
+        bc[:, 2, 1] = 0
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.5).solve(tol=1e-12, max_iter=8000)
+    assert o["converged"]
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=1.5, precision=prec,
+                 tol=1e-12 if prec == "fp64" else 1e-6, max_iter=8000)
+    rc, rep = g.solve()
+    assert rc == 0
+    u = g.u.cpu().numpy()
+    _, _, tot = g.reactions()
+    if prec == "fp64":
+        assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
+        assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()
+    else:
+        o6 = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.5).solve(tol=1e-6, max_iter=8000)
+        assert np.linalg.norm(u - o["u"]) <= _fp32_bar(o6["u"], o["u"]) * np.linalg.norm(o["u"])
+
+
 def _box(xs, ys, zs):
     return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
 
