@@ -290,6 +290,34 @@ def test_periodic_solves(case, prec):
         assert np.linalg.norm(u - o["u"]) <= _fp32_bar(o6["u"], o["u"]) * np.linalg.norm(o["u"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_stiffness_reset(prec):
+    """A bound problem whose stiffness is set again (doubled) between two solves: with all
+    loading prescribed as displacements the solution does not change and the reactions
+    double; the reference medium scales along, so the iteration is the same."""
+    F = _lib()
+    import torch
+    print(f"[stiffness reset] {prec}", flush=True)
+    p = W.c1_inclusion_patch()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    g = F.Solver.from_problem(p, precision=prec, tol=tol)
+    rc, rep1 = g.solve()
+    assert rc == 0
+    u1 = g.u.cpu().numpy()
+    _, _, t1 = g.reactions()
+    lam2 = torch.as_tensor(2.0 * p.lam, device=g.device).contiguous()
+    mu2 = torch.as_tensor(2.0 * p.mu, device=g.device).contiguous()
+    F.fftc_set_stiffness(g.h, lam2, mu2)
+    rc, rep2 = g.solve()
+    assert rc == 0
+    u2 = g.u.cpu().numpy()
+    _, _, t2 = g.reactions()
+    assert abs(rep2.iterations - rep1.iterations) <= (0 if prec == "fp64" else 2)
+    bound = 1e-10 if prec == "fp64" else 1e-5
+    assert np.linalg.norm(u2 - u1) <= bound * np.linalg.norm(u1)
+    assert np.abs(t2 - 2.0 * t1).max() <= (1e-9 if prec == "fp64" else 1e-4) * np.abs(t2).max()
+
+
 def _box(xs, ys, zs):
     return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
 
