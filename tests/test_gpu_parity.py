@@ -227,8 +227,9 @@ def test_contact_other_faces(face, prec):
 def test_degenerate_solves(prec):
     """Degenerate inputs of the method: no loads (the solution is 0, found without an
     iteration), a start at the converged solution (no iteration, u kept), a reference medium
-    far too soft (the iteration diverges and reports it, as the oracle does), and a cell
-    with every voxel void (rejected: no reference medium)."""
+    far too soft (the iteration diverges and reports it, as the oracle does), a cell with
+    every voxel void (rejected: no reference medium), and an obstacle that does not reach
+    the contact face (empty active set)."""
     F = _lib()
     print(f"[degenerate solves] {prec}", flush=True)
     p = W.c1_inclusion_patch()
@@ -253,6 +254,15 @@ def test_degenerate_solves(prec):
     with pytest.raises(F.FftcError) as e:
         F.Solver(p.n, zero, zero, p.bc, precision=prec)
     assert e.value.code == F.FFTC_E_ARG
+    # an obstacle that does not reach the face: empty active set, u = 0, no force
+    n, R = (16, 16, 8), 6.0
+    q = W.c3_indentation(n=n, R=R, d_over_R=0.01)
+    g = F.Solver.from_problem(q, precision=prec, tol=1e-6)
+    g.move_sphere(np.array([8.0, 8.0, n[2] + R + 3.0]))
+    rc, rep = g.solve()
+    mask, fnc, gap = g.contact()
+    assert rc == 0 and rep.iterations == 0 and not bool(g.u.any())
+    assert not mask.any() and rep.force_contact == 0.0 and (gap > 0).all()
 
 
 @pytest.mark.parametrize("case", ["x", "xy"])
