@@ -328,6 +328,39 @@ def test_stiffness_reset(prec):
     assert np.abs(t2 - 2.0 * t1).max() <= (1e-9 if prec == "fp64" else 1e-4) * np.abs(t2).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_uniaxial_strain_closed_form(prec):
+    """Homogeneous block on lateral rollers, top face pressed by delta: the exact field
+    u_z = delta z / L, the top reaction total sigma_zz nx ny and the reported mean stress
+    (lam, lam, lam + 2 mu) delta / L with no shear (closed forms, no oracle involved)."""
+    F = _lib()
+    n = (16, 12, 32)
+    nx, ny, nz = n
+    print(f"[uniaxial strain] {prec}", flush=True)
+    lam0, mu0, delta = 1.2, 0.8, 0.03
+    lam = np.full(n[::-1], lam0); mu = np.full(n[::-1], mu0)
+    bc = np.zeros((3, 3, 2), np.int8)
+    bc[0, 0, :] = 1
+    bc[1, 1, :] = 1
+    bc[2, 2, 0] = 1
+    top = _box(np.arange(nx + 1), np.arange(ny + 1), [nz])
+    strong = [W.Strong(top, np.full(len(top), 2, np.int8), np.full(len(top), delta))]
+    g = F.Solver(n, lam, mu, bc, strong, (), r0_factor=1.0, precision=prec, tol=1e-12 if prec == "fp64" else 1e-6)
+    rc, rep = g.solve()
+    assert rc == 0
+    u = g.u.cpu().numpy().reshape(3, nz + 1, ny + 1, nx + 1)
+    exact = delta * np.arange(nz + 1)[:, None, None] / nz * np.ones((nz + 1, ny + 1, nx + 1))
+    e = 1e-12 if prec == "fp64" else 1e-5
+    assert np.abs(u[2] - exact).max() <= e * delta
+    assert np.abs(u[:2]).max() <= e * delta
+    szz = (lam0 + 2 * mu0) * delta / nz
+    _, _, tot = g.reactions()
+    assert abs(tot[0, 2] - szz * nx * ny) <= e * szz * nx * ny
+    ms = np.array(rep.mean_stress)
+    want = np.array([lam0, lam0, lam0 + 2 * mu0, 0, 0, 0]) * delta / nz
+    assert np.abs(ms - want).max() <= e * szz
+
+
 def _box(xs, ys, zs):
     return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
 
