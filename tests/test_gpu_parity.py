@@ -244,7 +244,8 @@ def test_degenerate_solves(prec):
     rc, rep = g.solve(zero_start=False)
     assert rc == 0 and rep.iterations == 0
     assert float((g.u - u1).abs().max()) <= 1e-14 * float(u1.abs().max())
-    o = OSolver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02).solve(tol=p.tol, max_iter=3000)
+    with np.errstate(over="ignore", invalid="ignore"):
+        o = OSolver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02).solve(tol=p.tol, max_iter=3000)
     assert not o["converged"]
     g = F.Solver(p.n, p.lam, p.mu, p.bc, p.strong, p.average, r0_factor=0.02, precision=prec, tol=p.tol,
                  max_iter=3000)
