@@ -126,6 +126,78 @@ def bench_warmstart(args):
     print(json.dumps(out))
 
 
+def nn_flops_per_node(modes=6, blocks=4, width=32, hidden=64, cin=12, cout=3):
+    """Algorithmic FLOPs of one network forward per node: lift, per block the analysis onto
+    modes^3 cosine modes and the synthesis back (each 2 M3 width) plus the pointwise map,
+    then the two head layers."""
+    m3 = modes ** 3
+    return (2 * cin * width + blocks * (2 * (2 * m3 * width) + 2 * width * width)
+            + 2 * width * hidden + 2 * hidden * cout)
+
+
+def bench_nn(args):
+    """The learned-start network alone on one held-out case at 65^3 nodes (129^3 with
+    --n 128): input channels (one plain iteration and the channel build), inference (the
+    start u0 = u1 + s_u y) and one training step (forward, backward, Adam)."""
+    import torch
+    import workloads as W
+    import paper_2607_26082_amd as F
+    from paper_2607_26082_amd import warmstart as WS
+    scale = 2 if args.n == 128 else 1
+    torch.cuda.set_device(0)
+    prob = W.nn_case(W.NN_EVAL_SEED, None, scale)
+    g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=4000)
+    net = F.Net(6, 4)
+    net.set_params(WS.load_weights())
+    Nn = int(np.prod(g.N))
+    su = 1e-3 * min(prob.n)
+    feat = torch.empty((Nn, F.FFTC_NN_CHANNELS), dtype=torch.int16, device="cuda")
+    u1 = torch.empty((3, Nn), dtype=torch.float64, device="cuda")
+    u0 = torch.empty_like(u1)
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    print(f"[bench] network on {g.N} nodes", file=sys.stderr, flush=True)
+    t_feat = timed(lambda: F.fftc_nn_features(g.h, feat, u1), args.steps)
+    net.bind(g.N, training=False)
+    t_fwd = timed(lambda: net.forward(feat, su, u1, u0), args.steps)
+    net.bind(g.N, training=True)
+    tgt = torch.randn((3, Nn), dtype=torch.float32, device="cuda")
+    lr = 1e-12                            # a step that leaves the weights as they are
+
+    def train():
+        net.train_step(feat, tgt)
+        net.adam(lr)
+
+    t_train = timed(train, args.steps)
+    f = nn_flops_per_node()
+    tf_fwd = f * Nn / (t_fwd * 1e-3) / 1e12
+    tf_train = 3 * f * Nn / (t_train * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": Nn / (t_fwd * 1e-3), "unit": "nodes/s (network inference)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_fwd,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"learned-start network (width 32, 6 modes, 4 blocks) on a held-out case, "
+                               f"{'x'.join(str(v) for v in g.N)} nodes", "precision": "bf16 MFMA, fp32 accumulation"},
+        "roofline": {"bound": "mfma", "achieved": round(tf_fwd, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tf_fwd / 2500.0, 4), "traffic": None, "kernel": "network forward (all kernels)",
+                     "alg_flops_per_node": f},
+        "ms": {"input_channels": round(t_feat, 4), "inference": round(t_fwd, 4), "training_step": round(t_train, 4)},
+        "training_tflops": round(tf_train, 1),
+    }
+    print(json.dumps(out))
+
+
 def bench_batch(args):
     """64 two-phase cells of uneven size, FP32 form, solved together to 1e-6 as one batch.
 
@@ -191,9 +263,10 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=5)
-    ap.add_argument("--workload", default="m256", choices=["m256", "c4", "c5"],
+    ap.add_argument("--workload", default="m256", choices=["m256", "c4", "c5", "nn"],
                     help="m256: 256^3 iteration throughput; c4: 64 uneven cells solved as one batch; "
-                         "c5: time to 1e-6 with the learned start vs the plain start on held-out cases")
+                         "c5: time to 1e-6 with the learned start vs the plain start on held-out cases; "
+                         "nn: the learned-start network alone (inference and a training step)")
     ap.add_argument("--cells", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -203,6 +276,8 @@ def main():
         return bench_batch(args)
     if args.workload == "c5":
         return bench_warmstart(args)
+    if args.workload == "nn":
+        return bench_nn(args)
 
     import torch
     import paper_2607_26082_amd as F

@@ -13,7 +13,7 @@
 //            GELU derivative of a stored pre-activation);
 //   k_reduce R[row][col] = sum_node L(node, row) X(node, col)
 //            (K = nodes; L the basis or an activation), written as per-wave
-//            partials that k_sum adds in a fixed order.
+//            partials that k_sum_groups and k_sum add in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -36,6 +36,9 @@ constexpr int kMaxM = 6;
 constexpr int kKPMax = 224;                 // 6^3 = 216 modes padded to 16
 constexpr int kTabMax = 3 * kMaxN * kMaxM;  // cosine tables, floats
 constexpr int kRedGrid = 256;               // workgroups of a reduction
+constexpr int kSumGroup = 32;               // per-wave partials summed per group (first pass)
+constexpr int kRedSplit = 2;                // basis rows split over grid.y (register budget)
+constexpr int kSumGroupsMax = (4 * kRedGrid + kSumGroup - 1) / kSumGroup;
 constexpr int kPartCols = kKPMax * kW;      // largest partial (rows x cols) per wave
 constexpr int kGemmGrid = 1024;
 constexpr int kHeadBlock = 256;
@@ -75,6 +78,14 @@ struct Dims {
 
 enum { EPI_STORE = 0, EPI_GELU = 1, EPI_GELU_Z = 2, EPI_DGELU = 3 };
 
+// Mode k of the m^3 cosine basis as packed per-axis indices kx | ky << 8 | kz << 16, or -1
+// for the padding modes k >= m^3 (built once per block; the basis loops then need no
+// division by the runtime m).
+__device__ __forceinline__ void mode_table(int* sK, int KP, int m, int M3) {
+  for (int k = threadIdx.x; k < KP; k += blockDim.x)
+    sK[k] = k < M3 ? ((k % m) | (((k / m) % m) << 8) | ((k / (m * m)) << 16)) : -1;
+}
+
 struct GemmArgs {
   Dims d;
   const uint16_t* x;     // [Nn][KX]
@@ -93,6 +104,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   __shared__ __align__(16) uint16_t sP[BASIS ? NO * kKPMax : 4];
   __shared__ float sBias[NO];
   __shared__ float sT[BASIS ? kTabMax : 1];
+  __shared__ int sK[BASIS ? kKPMax : 1];
   const int tid = threadIdx.x;
   for (int i = tid; i < NO * KX; i += 256) {
     const int o = i / KX, c = i % KX;
@@ -105,6 +117,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     for (int i = tid; i < NO * KP; i += 256) sP[i] = a.p[i];
     const int nt = (a.d.N[0] + a.d.N[1] + a.d.N[2]) * m;
     for (int i = tid; i < nt; i += 256) sT[i] = a.tab[i];
+    mode_table(sK, KP, m, M3);
   }
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6;
@@ -124,12 +137,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         s4 av;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int k = ks * 16 + q * 4 + e;
+          const int kk = sK[ks * 16 + q * 4 + e];
           float v = 0.0f;
-          if (valid && k < M3) {
-            const int kx = k % m, ky = (k / m) % m, kz = k / (m * m);
-            v = sT[tz + kz] * sT[ty + ky] * sT[tx + kx];
-          }
+          if (valid && kk >= 0) v = sT[tz + (kk >> 16)] * sT[ty + ((kk >> 8) & 255)] * sT[tx + (kk & 255)];
           av[e] = (short)f2bf(v);
         }
 #pragma unroll
@@ -187,14 +197,19 @@ struct RedArgs {
 template <bool BASIS, int RL, int C, bool ONES>
 __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   constexpr int CT = C / 16 + (ONES ? 1 : 0);
-  constexpr int RTM = BASIS ? kKPMax / 16 : RL / 16;
+  // basis reductions: each block row (grid.y) accumulates its share of the 16-row tiles
+  constexpr int RTM = BASIS ? kKPMax / 16 / kRedSplit : RL / 16;
+  static_assert(!BASIS || (kKPMax / 16) % kRedSplit == 0, "basis row tiles split evenly");
+  const int rt0 = BASIS ? (int)blockIdx.y * RTM : 0;
   __shared__ float sT[BASIS ? kTabMax : 1];
+  __shared__ int sK[BASIS ? kKPMax : 1];
   const int tid = threadIdx.x;
   const int m = a.d.m, M3 = a.d.M3;
   const int Nx = a.d.N[0], Ny = a.d.N[1];
   if (BASIS) {
     const int nt = (a.d.N[0] + a.d.N[1] + a.d.N[2]) * m;
     for (int i = tid; i < nt; i += 256) sT[i] = a.tab[i];
+    mode_table(sK, a.d.KP, m, M3);
     __syncthreads();
   }
   const int lane = tid & 63, w = tid >> 6;
@@ -236,12 +251,12 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
     }
 #pragma unroll
     for (int rt = 0; rt < RTM; ++rt) {
-      if (rt < RT) {
+      if (rt0 + rt < RT) {
       s4 av;
       if (BASIS) {
-        const int k = rt * 16 + r;
-        const bool km = k < M3;
-        const int kx = k % m, ky = (k / m) % m, kz = k / (m * m);
+        const int kk = sK[(rt0 + rt) * 16 + r];
+        const bool km = kk >= 0;
+        const int kx = kk & 255, ky = (kk >> 8) & 255, kz = kk >> 16;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float v = (ok[e] && km) ? sT[tz[e] + kz] * sT[ty[e] + ky] * sT[tx[e] + kx] : 0.0f;
@@ -261,14 +276,14 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   const size_t wg = (size_t)blockIdx.x * 4 + w;
 #pragma unroll
   for (int rt = 0; rt < RTM; ++rt) {
-    if (rt < RT) {
+    if (rt0 + rt < RT) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int col = ct * 16 + r;
         if (col < CP) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int row = rt * 16 + q * 4 + e;
+            const int row = (rt0 + rt) * 16 + q * 4 + e;
             a.part[(wg * R + row) * CP + col] = acc[rt][ct][e];
           }
         }
@@ -277,16 +292,28 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   }
 }
 
-// Fixed-order sum of the per-wave partials; col < ncols goes to dst[row][col]
-// (leading dimension ldd), col == bias_col to dst_bias[row].
-__global__ void k_sum(const float* part, int waves, int R, int CP, int rows, float scale, float* dst, int ldd,
+// Fixed-order sum of the per-wave partials, in two passes so that many waves share the
+// work: k_sum_groups adds each run of kSumGroup consecutive waves (grid.y = group, one
+// thread per output), k_sum adds the group sums in order; col < ncols goes to
+// dst[row][col] (leading dimension ldd), col == bias_col to dst_bias[row].
+__global__ void k_sum_groups(const float* part, int waves, int RCP, double* grp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= RCP) return;
+  const int w0 = (int)blockIdx.y * kSumGroup;
+  const int w1 = min(waves, w0 + kSumGroup);
+  double s = 0.0;
+  for (int w = w0; w < w1; ++w) s += part[(size_t)w * RCP + i];
+  grp[(size_t)blockIdx.y * RCP + i] = s;
+}
+
+__global__ void k_sum(const double* grp, int groups, int R, int CP, int rows, float scale, float* dst, int ldd,
                       int ncols, float* dst_bias, int bias_col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * CP) return;
   const int row = i / CP, col = i % CP;
   if (row >= rows) return;
   double s = 0.0;
-  for (int w = 0; w < waves; ++w) s += part[(size_t)w * R * CP + i];
+  for (int g = 0; g < groups; ++g) s += grp[(size_t)g * R * CP + i];
   const float v = (float)(s * scale);
   if (col < ncols) dst[row * ldd + col] = v;
   else if (col == bias_col && dst_bias) dst_bias[row] = v;
@@ -669,6 +696,7 @@ struct fftc_nn {
   float *xh = nullptr, *dyh = nullptr, *part = nullptr;
   uint16_t* P16 = nullptr;
   double *dsc = nullptr;      // small FP64 scratch: partials, tsum, loss
+  double* grp = nullptr;      // group sums of the reduction partials
   float* tinv = nullptr;
   std::string err;
 };
@@ -727,6 +755,7 @@ size_t ws_layout(const fftc_nn* nn, const int N[3], int training, size_t* off /*
   const size_t nhead = (Nn + kHeadBlock - 1) / kHeadBlock;
   off[q++] = o; o += al(8 * (std::max<size_t>(nhead, 1024) + 16));              // dsc
   off[q++] = o; o += al(16);                                                     // tinv
+  off[q++] = o; o += al(8 * (size_t)kSumGroupsMax * std::max(nn->KP * kW, kH * (kW + 1)));  // grp
   return o;
 }
 
@@ -763,10 +792,13 @@ void reduce(fftc_nn* nn, const uint16_t* l, const uint16_t* x, int rows, float s
             int ncols, float* dst_bias) {
   RedArgs a{dims_of(nn), l, x, nn->tab, nn->part};
   const int G = red_grid(nn);
-  hipLaunchKernelGGL((k_reduce<BASIS, RL, C, ONES>), dim3(G), dim3(256), 0, nn->stream, a);
+  hipLaunchKernelGGL((k_reduce<BASIS, RL, C, ONES>), dim3(G, BASIS ? kRedSplit : 1), dim3(256), 0, nn->stream, a);
   const int R = BASIS ? nn->KP : RL;
   const int CP = C + (ONES ? 1 : 0);
-  hipLaunchKernelGGL(k_sum, dim3((R * CP + 255) / 256), dim3(256), 0, nn->stream, (const float*)nn->part, 4 * G, R,
+  const int waves = 4 * G, groups = (waves + kSumGroup - 1) / kSumGroup;
+  hipLaunchKernelGGL(k_sum_groups, dim3((R * CP + 255) / 256, groups), dim3(256), 0, nn->stream,
+                     (const float*)nn->part, waves, R * CP, nn->grp);
+  hipLaunchKernelGGL(k_sum, dim3((R * CP + 255) / 256), dim3(256), 0, nn->stream, (const double*)nn->grp, groups, R,
                      CP, rows, scale, dst, ldd, ncols, dst_bias, ONES ? C : -1);
 }
 
@@ -900,6 +932,7 @@ int fftc_nn_bind(fftc_nn_h nn, const int32_t N[3], int32_t training, void* ws_de
   nn->P16 = (uint16_t*)(b + off[q++]);
   nn->dsc = (double*)(b + off[q++]);
   nn->tinv = (float*)(b + off[q++]);
+  nn->grp = (double*)(b + off[q++]);
   nn->training = training ? 1 : 0;
   nn->stream = (hipStream_t)stream;
   nn->d.N[0] = N[0];
