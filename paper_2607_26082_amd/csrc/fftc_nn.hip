@@ -6,14 +6,16 @@
 //   A (16 x 16, row i, column k):  i = r, k = 4 q + e
 //   B (16 x 16, row k, column j):  k = 4 q + e, j = r
 //   D (16 x 16 FP32, row i, col j): i = 4 q + e, j = r
-// Two kernel shapes cover every contraction of the network:
+// The contractions of the network:
 //   k_gemm   out[node][o] = sum_k phi(node, k) P[o][k] + sum_c X[node][c] Q[o][c] + bias[o]
 //            (rows = 16 nodes per tile; the cosine basis phi is formed on the fly
 //            from per-axis tables in LDS), with a fused epilogue (GELU, or the
 //            GELU derivative of a stored pre-activation);
-//   k_reduce R[row][col] = sum_node L(node, row) X(node, col)
-//            (K = nodes; L the basis or an activation), written as per-wave
-//            partials that k_sum_groups and k_sum add in a fixed order.
+//   k_reduce R[row][col] = sum_node L(node, row) X(node, col) (K = nodes, L an
+//            activation), written as per-wave partials that k_sum_groups and k_sum
+//            add in a fixed order;
+//   k_ana_*  the analysis onto the cosine modes, sum_node phi_k(node) X(node, c),
+//            separably: one axis at a time (x, then y, then z) in FP32.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -37,7 +39,6 @@ constexpr int kKPMax = 224;                 // 6^3 = 216 modes padded to 16
 constexpr int kTabMax = 3 * kMaxN * kMaxM;  // cosine tables, floats
 constexpr int kRedGrid = 256;               // workgroups of a reduction
 constexpr int kSumGroup = 32;               // per-wave partials summed per group (first pass)
-constexpr int kRedSplit = 2;                // basis rows split over grid.y (register budget)
 constexpr int kSumGroupsMax = (4 * kRedGrid + kSumGroup - 1) / kSumGroup;
 constexpr int kPartCols = kKPMax * kW;      // largest partial (rows x cols) per wave
 constexpr int kGemmGrid = 1024;
@@ -189,36 +190,21 @@ struct RedArgs {
   Dims d;
   const uint16_t* l;   // [Nn][RL] row source (activation rows)
   const uint16_t* x;   // [Nn][C]
-  const float* tab;
-  float* part;         // [waves][R][CP]
+  float* part;         // [waves][RL][CP]
 };
 
-// R = rows (KP for the basis, RL otherwise); CP = C + ONES (the ones column sums the rows).
-template <bool BASIS, int RL, int C, bool ONES>
+// R[row][col] = sum_node l[node][row] x[node][col], CP = C + ONES (the ones column sums the rows).
+template <int RL, int C, bool ONES>
 __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   constexpr int CT = C / 16 + (ONES ? 1 : 0);
-  // basis reductions: each block row (grid.y) accumulates its share of the 16-row tiles
-  constexpr int RTM = BASIS ? kKPMax / 16 / kRedSplit : RL / 16;
-  static_assert(!BASIS || (kKPMax / 16) % kRedSplit == 0, "basis row tiles split evenly");
-  const int rt0 = BASIS ? (int)blockIdx.y * RTM : 0;
-  __shared__ float sT[BASIS ? kTabMax : 1];
-  __shared__ int sK[BASIS ? kKPMax : 1];
+  constexpr int RT = RL / 16;
   const int tid = threadIdx.x;
-  const int m = a.d.m, M3 = a.d.M3;
-  const int Nx = a.d.N[0], Ny = a.d.N[1];
-  if (BASIS) {
-    const int nt = (a.d.N[0] + a.d.N[1] + a.d.N[2]) * m;
-    for (int i = tid; i < nt; i += 256) sT[i] = a.tab[i];
-    mode_table(sK, a.d.KP, m, M3);
-    __syncthreads();
-  }
   const int lane = tid & 63, w = tid >> 6;
   const int r = lane & 15, q = lane >> 4;
   const int Nn = a.d.Nn;
-  const int RT = BASIS ? a.d.ksteps : RL / 16;
-  f4 acc[RTM][CT];
+  f4 acc[RT][CT];
 #pragma unroll
-  for (int i = 0; i < RTM; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int nchunks = (Nn + 15) >> 4;
@@ -239,53 +225,27 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) bv[CT - 1][e] = (ok[e] && r == 0) ? (short)0x3f80 : (short)0;
     }
-    int tx[4], ty[4], tz[4];
-    if (BASIS) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int n0 = ok[e] ? nd[e] : 0;
-        tx[e] = (n0 % Nx) * m;
-        ty[e] = (Nx + (n0 / Nx) % Ny) * m;
-        tz[e] = (Nx + Ny + n0 / (Nx * Ny)) * m;
-      }
-    }
-#pragma unroll
-    for (int rt = 0; rt < RTM; ++rt) {
-      if (rt0 + rt < RT) {
+    for (int rt = 0; rt < RT; ++rt) {
       s4 av;
-      if (BASIS) {
-        const int kk = sK[(rt0 + rt) * 16 + r];
-        const bool km = kk >= 0;
-        const int kx = kk & 255, ky = (kk >> 8) & 255, kz = kk >> 16;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float v = (ok[e] && km) ? sT[tz[e] + kz] * sT[ty[e] + ky] * sT[tx[e] + kx] : 0.0f;
-          av[e] = (short)f2bf(v);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) av[e] = ok[e] ? (short)a.l[(size_t)nd[e] * RL + rt * 16 + r] : (short)0;
-      }
+      for (int e = 0; e < 4; ++e) av[e] = ok[e] ? (short)a.l[(size_t)nd[e] * RL + rt * 16 + r] : (short)0;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma16(av, bv[ct], acc[rt][ct]);
-      }
     }
   }
-  const int R = BASIS ? a.d.KP : RL;
   constexpr int CP = C + (ONES ? 1 : 0);
   const size_t wg = (size_t)blockIdx.x * 4 + w;
 #pragma unroll
-  for (int rt = 0; rt < RTM; ++rt) {
-    if (rt0 + rt < RT) {
+  for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + r;
-        if (col < CP) {
+    for (int ct = 0; ct < CT; ++ct) {
+      const int col = ct * 16 + r;
+      if (col < CP) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int row = (rt0 + rt) * 16 + q * 4 + e;
-            a.part[(wg * R + row) * CP + col] = acc[rt][ct][e];
-          }
+        for (int e = 0; e < 4; ++e) {
+          const int row = rt * 16 + q * 4 + e;
+          a.part[(wg * RL + row) * CP + col] = acc[rt][ct][e];
         }
       }
     }
@@ -317,6 +277,56 @@ __global__ void k_sum(const double* grp, int groups, int R, int CP, int rows, fl
   const float v = (float)(s * scale);
   if (col < ncols) dst[row * ldd + col] = v;
   else if (col == bias_col && dst_bias) dst_bias[row] = v;
+}
+
+// --------------------------------------------------------------------------
+// separable analysis onto the cosine modes
+// --------------------------------------------------------------------------
+// dst[k][c] = scale sum_node phi_k(node) X[node][c] with phi_k(x, y, z) = cx(x, kx) cy(y, ky)
+// cz(z, kz), k = kx + m (ky + m kz): one axis at a time, each sum in a fixed order, FP32.
+// Rows KP > k >= m^3 of dst are zero.
+
+// x: one block per (y, z) line: A1[line][kx][c] = sum_x cx(x, kx) X[(x, y, z)][c]
+__global__ __launch_bounds__(256) void k_ana_x(Dims d, const float* tab, const uint16_t* X, float* A1) {
+  __shared__ uint16_t sX[kMaxN * kW];
+  __shared__ float sC[kMaxN * kMaxM];
+  const int Nx = d.N[0], m = d.m, line = blockIdx.x;
+  const uint16_t* row = X + (size_t)line * Nx * kW;
+  for (int i = threadIdx.x; i < Nx * kW; i += blockDim.x) sX[i] = row[i];
+  for (int i = threadIdx.x; i < Nx * m; i += blockDim.x) sC[i] = tab[i];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= m * kW) return;
+  const int kx = t / kW, c = t % kW;
+  float s = 0.0f;
+  for (int x = 0; x < Nx; ++x) s += sC[x * m + kx] * bf2f(sX[x * kW + c]);
+  A1[(size_t)line * m * kW + t] = s;
+}
+
+// y: one block per (z, ky): A2[z][ky][kx][c] = sum_y cy(y, ky) A1[(y, z)][kx][c]
+__global__ __launch_bounds__(256) void k_ana_y(Dims d, const float* tab, const float* A1, float* A2) {
+  const int Nx = d.N[0], Ny = d.N[1], m = d.m;
+  const int z = blockIdx.x / m, ky = blockIdx.x % m, t = threadIdx.x;
+  if (t >= m * kW) return;
+  const float* cy = tab + Nx * m;
+  float s = 0.0f;
+  for (int y = 0; y < Ny; ++y) s += cy[y * m + ky] * A1[((size_t)z * Ny + y) * m * kW + t];
+  A2[((size_t)z * m + ky) * m * kW + t] = s;
+}
+
+// z: one block per (kz, ky): dst[k][c] = scale sum_z cz(z, kz) A2[z][ky][kx][c]
+__global__ __launch_bounds__(256) void k_ana_z(Dims d, const float* tab, const float* A2, float scale, float* dst,
+                                               int ldd) {
+  const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2], m = d.m;
+  const int kz = blockIdx.x / m, ky = blockIdx.x % m, t = threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int i = t; i < (d.KP - d.M3) * kW; i += blockDim.x) dst[(d.M3 + i / kW) * ldd + i % kW] = 0.0f;
+  if (t >= m * kW) return;
+  const float* cz = tab + (Nx + Ny) * m;
+  float s = 0.0f;
+  for (int z = 0; z < Nz; ++z) s += cz[z * m + kz] * A2[((size_t)z * m + ky) * m * kW + t];
+  const int kx = t / kW, c = t % kW;
+  dst[(kx + m * (ky + m * kz)) * ldd + c] = s * scale;
 }
 
 // --------------------------------------------------------------------------
@@ -697,6 +707,7 @@ struct fftc_nn {
   uint16_t* P16 = nullptr;
   double *dsc = nullptr;      // small FP64 scratch: partials, tsum, loss
   double* grp = nullptr;      // group sums of the reduction partials
+  float *ana1 = nullptr, *ana2 = nullptr;   // separable analysis: after x, after y
   float* tinv = nullptr;
   std::string err;
 };
@@ -735,7 +746,7 @@ int nfail(fftc_nn* nn, int code, const std::string& msg) {
     if (e_ != hipSuccess) return nfail(nn, FFTC_E_HIP, std::string("HIP: ") + hipGetErrorString(e_)); \
   } while (0)
 
-size_t ws_layout(const fftc_nn* nn, const int N[3], int training, size_t* off /* >= 16 */) {
+size_t ws_layout(const fftc_nn* nn, const int N[3], int training, size_t* off /* >= 20 */) {
   const size_t Nn = (size_t)N[0] * N[1] * N[2];
   const size_t act = al(2 * Nn * kW);
   size_t o = 0;
@@ -756,6 +767,8 @@ size_t ws_layout(const fftc_nn* nn, const int N[3], int training, size_t* off /*
   off[q++] = o; o += al(8 * (std::max<size_t>(nhead, 1024) + 16));              // dsc
   off[q++] = o; o += al(16);                                                     // tinv
   off[q++] = o; o += al(8 * (size_t)kSumGroupsMax * std::max(nn->KP * kW, kH * (kW + 1)));  // grp
+  off[q++] = o; o += al(4 * (size_t)N[1] * N[2] * nn->m * kW);                   // ana1
+  off[q++] = o; o += al(4 * (size_t)N[2] * nn->m * nn->m * kW);                  // ana2
   return o;
 }
 
@@ -786,14 +799,24 @@ void gemm(fftc_nn* nn, const uint16_t* x, const uint16_t* q, const uint16_t* p, 
   hipLaunchKernelGGL((k_gemm<NO, KX, BASIS, EPI, QT>), dim3(gemm_grid(nn)), dim3(256), 0, nn->stream, a);
 }
 
+// separable analysis of X [Nn][kW] onto the modes: dst [KP][ldd], scaled
+void analysis(fftc_nn* nn, const uint16_t* X, float scale, float* dst, int ldd) {
+  const Dims d = dims_of(nn);
+  hipLaunchKernelGGL(k_ana_x, dim3(d.N[1] * d.N[2]), dim3(256), 0, nn->stream, d, (const float*)nn->tab, X, nn->ana1);
+  hipLaunchKernelGGL(k_ana_y, dim3(d.N[2] * d.m), dim3(256), 0, nn->stream, d, (const float*)nn->tab,
+                     (const float*)nn->ana1, nn->ana2);
+  hipLaunchKernelGGL(k_ana_z, dim3(d.m * d.m), dim3(256), 0, nn->stream, d, (const float*)nn->tab,
+                     (const float*)nn->ana2, scale, dst, ldd);
+}
+
 // reduce then sum: rows valid `rows`, scale, destination mapping as k_sum
-template <bool BASIS, int RL, int C, bool ONES>
+template <int RL, int C, bool ONES>
 void reduce(fftc_nn* nn, const uint16_t* l, const uint16_t* x, int rows, float scale, float* dst, int ldd,
             int ncols, float* dst_bias) {
-  RedArgs a{dims_of(nn), l, x, nn->tab, nn->part};
+  RedArgs a{dims_of(nn), l, x, nn->part};
   const int G = red_grid(nn);
-  hipLaunchKernelGGL((k_reduce<BASIS, RL, C, ONES>), dim3(G, BASIS ? kRedSplit : 1), dim3(256), 0, nn->stream, a);
-  const int R = BASIS ? nn->KP : RL;
+  hipLaunchKernelGGL((k_reduce<RL, C, ONES>), dim3(G), dim3(256), 0, nn->stream, a);
+  const int R = RL;
   const int CP = C + (ONES ? 1 : 0);
   const int waves = 4 * G, groups = (waves + kSumGroup - 1) / kSumGroup;
   hipLaunchKernelGGL(k_sum_groups, dim3((R * CP + 255) / 256, groups), dim3(256), 0, nn->stream,
@@ -814,7 +837,7 @@ void forward(fftc_nn* nn, const uint16_t* feat) {
     const float* blk = p + o.blk0 + b * o.blk_stride;
     const int nxt = tr ? b + 1 : (cur ^ 1);
     float* xh = nn->xh + (size_t)(tr ? b : 0) * KPW;
-    reduce<true, 16, kW, false>(nn, nullptr, xbuf(nn, cur), nn->KP, 1.0f / (float)nn->d.Nn, xh, kW, kW, nullptr);
+    analysis(nn, xbuf(nn, cur), 1.0f / (float)nn->d.Nn, xh, kW);
     hipLaunchKernelGGL(k_mix_fwd, dim3((KPW + 255) / 256), dim3(256), 0, nn->stream, blk + o.Ws, (const float*)xh,
                        nn->M3, nn->KP, nn->P16);
     if (tr)
@@ -901,7 +924,7 @@ int fftc_nn_bind_state(fftc_nn_h nn, void* state_dev, size_t bytes, void* stream
 int fftc_nn_workspace_bytes(fftc_nn_h nn, const int32_t N[3], int32_t training, size_t* bytes) {
   if (!nn || !N || !bytes) return FFTC_E_ARG;
   if (!check_grid(N)) return FFTC_E_UNSUPPORTED;
-  size_t off[16];
+  size_t off[20];
   const int Nc[3] = {N[0], N[1], N[2]};
   *bytes = ws_layout(nn, Nc, training, off);
   return FFTC_OK;
@@ -912,7 +935,7 @@ int fftc_nn_bind(fftc_nn_h nn, const int32_t N[3], int32_t training, void* ws_de
   if (!check_grid(N)) return nfail(nn, FFTC_E_UNSUPPORTED, "node grid must have 2..257 nodes per axis");
   if ((long long)N[0] * N[1] * N[2] >= (1ll << 31) / kH) return nfail(nn, FFTC_E_UNSUPPORTED, "grid too large");
   if ((uintptr_t)ws_dev % kAlign) return nfail(nn, FFTC_E_ARG, "workspace must be 256-byte aligned");
-  size_t off[16];
+  size_t off[20];
   const int Nc[3] = {N[0], N[1], N[2]};
   const size_t need = ws_layout(nn, Nc, training, off);
   if (bytes < need) return nfail(nn, FFTC_E_WORKSPACE, "workspace too small");
@@ -933,6 +956,8 @@ int fftc_nn_bind(fftc_nn_h nn, const int32_t N[3], int32_t training, void* ws_de
   nn->dsc = (double*)(b + off[q++]);
   nn->tinv = (float*)(b + off[q++]);
   nn->grp = (double*)(b + off[q++]);
+  nn->ana1 = (float*)(b + off[q++]);
+  nn->ana2 = (float*)(b + off[q++]);
   nn->training = training ? 1 : 0;
   nn->stream = (hipStream_t)stream;
   nn->d.N[0] = N[0];
@@ -1040,9 +1065,9 @@ int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* targ
                      loss_dev ? loss_dev : lossd);
   float* g = nn->g;
   // Wp2, bp2 from dy (rows 0..2 of the 16-wide dy) and h
-  reduce<false, kCh, kH, true>(nn, nn->dy16, nn->h, kCout, 1.0f, g + o.Wp2, kH, kH, g + o.bp2);
+  reduce<kCh, kH, true>(nn, nn->dy16, nn->h, kCout, 1.0f, g + o.Wp2, kH, kH, g + o.bp2);
   // Wp1, bp1 from dhpre and x_B
-  reduce<false, kH, kW, true>(nn, nn->dhpre, xbuf(nn, B), kH, 1.0f, g + o.Wp1, kW, kW, g + o.bp1);
+  reduce<kH, kW, true>(nn, nn->dhpre, xbuf(nn, B), kH, 1.0f, g + o.Wp1, kW, kW, g + o.bp1);
   // dx_B = dhpre Wp1, then through GELU of block B (or into the lift when B = 0)
   uint16_t* dcur = dzbuf(nn, 0);
   if (B > 0)
@@ -1056,9 +1081,9 @@ int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* targ
     const float* pb = nn->p + o.blk0 + b * o.blk_stride;
     const float* xh = nn->xh + (size_t)b * KPW;
     // dyh = sum_i phi(i) dz(i)
-    reduce<true, 16, kW, false>(nn, nullptr, dcur, nn->KP, 1.0f, nn->dyh, kW, kW, nullptr);
+    analysis(nn, dcur, 1.0f, nn->dyh, kW);
     // W_b, c_b
-    reduce<false, kW, kW, true>(nn, dcur, xbuf(nn, b), kW, 1.0f, gb + o.Wb, kW, kW, gb + o.cb);
+    reduce<kW, kW, true>(nn, dcur, xbuf(nn, b), kW, 1.0f, gb + o.Wb, kW, kW, gb + o.cb);
     hipLaunchKernelGGL(k_mix_bwd_dw, dim3((nn->M3 * kW * kW + 255) / 256), dim3(256), 0, s, (const float*)nn->dyh,
                        xh, nn->M3, gb + o.Ws);
     hipLaunchKernelGGL(k_mix_bwd_dx, dim3((KPW + 255) / 256), dim3(256), 0, s, pb + o.Ws, (const float*)nn->dyh,
@@ -1073,7 +1098,7 @@ int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* targ
     dcur = dnext;
   }
   // lift: Wl (9 of the 16 input columns), bl
-  reduce<false, kW, kCh, true>(nn, dcur, feat_dev, kW, 1.0f, g + o.Wl, kCin, kCin, g + o.bl);
+  reduce<kW, kCh, true>(nn, dcur, feat_dev, kW, 1.0f, g + o.Wl, kCin, kCin, g + o.bl);
   NNCHK(nn, hipGetLastError());
   return FFTC_OK;
 }
