@@ -1597,13 +1597,14 @@ constexpr int kVX = kTX + 1, kVY = kTY + 1;   // voxels x0-1 .. x0+kTX-1
 constexpr int kPlane = 3 * kHY * kHX;         // values of one staged node plane
 constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
 
-__device__ __forceinline__ int ring3(int p) { return ((p % 3) + 3) % 3; }
+// slot of node plane p in the four-plane ring of delta planes (p may be -1)
+__device__ __forceinline__ int ring4(int p) { return p & 3; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, TileGrid tg) {
   __shared__ double su[2][3][kHY][kHX];
-  __shared__ T sdl[3][3][kHY][kHX];
+  __shared__ T sdl[4][3][kHY][kHX];
   __shared__ T ss[2][12][kVY][kVX];   // stress component q of the voxels of a layer
   __shared__ double sh[kPartStrideD * 16];
   if (st->done) return;
@@ -1637,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
 
   // Node planes are fetched into registers one step ahead and committed to LDS the next
   // step.  u: su[pz & 1], nodes outside the grid read as 0 (no voxel uses them); delta:
-  // sdl[pz mod 3] with the stencil's halo (mirror or periodic image).
+  // sdl[pz mod 4] with the stencil's halo (mirror or periodic image).
   double ru[kPR];
   T rd[kPR];
   auto fetch = [&](int pz) {
@@ -1671,7 +1672,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   };
   auto commit = [&](int pz) {
     double* du = &su[pz & 1][0][0][0];
-    T* dd = &sdl[ring3(pz)][0][0][0];
+    T* dd = &sdl[ring4(pz)][0][0][0];
 #pragma unroll
     for (int r = 0; r < kPR; ++r) {
       const int e = tid + 256 * r;
@@ -1805,7 +1806,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) {
-      const int zm = ring3(z - 1), z0 = ring3(z), zp = ring3(z + 1);
+      const int zm = ring4(z - 1), z0 = ring4(z), zp = ring4(z + 1);
       const int hx = lx + 1, hy = ly + 1;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1834,8 +1835,12 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   fetch_lm(zb, lnext, mnext, oknext);
   __syncthreads();
   layer(zb - 1, false, lcur, mcur, okcur);
+  __syncthreads();
+  // Per step, plane z + 1 is committed with no barrier before it: its u slot was last read
+  // by layer(z - 1), and its delta slot (four-plane ring) by nodes(z - 2), both before the
+  // barrier that follows layer(z - 1).  The stress slot written by layer(z) was last read by
+  // nodes(z - 1), which precedes the barrier before layer(z).
   for (int z = zb; z < ze; ++z) {
-    __syncthreads();
     commit(z + 1);
     if (z + 2 <= ze) fetch(z + 2);
     lcur = lnext;
