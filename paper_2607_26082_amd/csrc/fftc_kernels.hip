@@ -2192,20 +2192,50 @@ void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const Con
   hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, w.m, ct, kPartStrideD);
 }
 
+// Blocks of the tiled residual pass resident on the current device at once (blocks per CU
+// at the kernel's register and LDS use, times the CU count), queried once per device.
+static int residual_resident() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
+  if (!cache[dev]) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    cache[dev] = per_cu * cus;
+  }
+  return cache[dev];
+}
+
 // Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
-// segments so that the block count stays within the 2048 partial-sum rows; tx = 0 when
-// the node plane alone needs more tiles than that.
+// segments, at most 2048 blocks (the partial-sum rows); tx = 0 when the node plane alone
+// needs more tiles than that.  A block marches its segment's planes plus two planes of
+// prologue, and the blocks run in rounds of the resident count, so the split taken is the
+// one with the fewest (rounds x planes per block); ties go to fewer segments.
 TileGrid residual_tiles(const Geo& g) {
   TileGrid t{0, 0, 0, 0};
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
   if ((long long)tx * ty > 2048) return t;
-  int nseg = std::max(1, std::min(g.N[2], 2048 / (tx * ty)));
-  const int seg = (g.N[2] + nseg - 1) / nseg;
-  nseg = (g.N[2] + seg - 1) / seg;
+  const int Nz = g.N[2];
+  const int maxseg = std::max(1, std::min(Nz, 2048 / (tx * ty)));
+  const long long resident = residual_resident();
+  long long best = -1;
+  int bseg = Nz;
+  for (int ns = 1; ns <= maxseg; ++ns) {
+    const int seg = (Nz + ns - 1) / ns;
+    const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
+    const long long cost = (blocks + resident - 1) / resident * (seg + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      bseg = seg;
+    }
+  }
   t.tx = tx;
   t.ty = ty;
-  t.nseg = nseg;
-  t.seg = seg;
+  t.seg = bseg;
+  t.nseg = (Nz + bseg - 1) / bseg;
   return t;
 }
 
