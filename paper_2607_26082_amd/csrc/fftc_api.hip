@@ -1037,6 +1037,7 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
   }
+  (void)residual_tiles(h->g);   // occupancy query of the residual pass, outside any capture
   if (h->nblk_res >= 8) h->nblk_res -= h->nblk_res % 8;   // whole slabs per XCD
   if (h->nblk_res < 1) h->nblk_res = 1;
   for (int q = 0; q < 10; ++q)

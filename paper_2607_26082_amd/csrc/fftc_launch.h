@@ -14,6 +14,10 @@ void launch_control(DevState* st, const double* part, int nblk, const double* wp
 template <typename T>
 void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
                                   DevState* st, double* part, double* wpart, int nblk, hipStream_t s);
+// Tile grid of the tiled residual pass on the current device.  Its first call on a device
+// queries the kernel's occupancy, which must not happen under stream capture: call it once
+// outside capture (the workspace binding does) before capturing iterations.
+TileGrid residual_tiles(const Geo& g);
 template <typename T>
 void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
 template <typename T>
