@@ -270,7 +270,7 @@ def main():
     ap.add_argument("--cells", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU per process; multi-GPU runs are not supported, --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "c4":
         return bench_batch(args)
