@@ -16,6 +16,8 @@
 
 #include <math.h>
 #include <type_traits>
+#include <algorithm>
+#include <atomic>
 
 namespace fftc {
 
@@ -2195,18 +2197,20 @@ void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const Con
 // Blocks of the tiled residual pass resident on the current device at once (blocks per CU
 // at the kernel's register and LDS use, times the CU count), queried once per device.
 static int residual_resident() {
-  static int cache[64] = {};
+  static std::atomic<int> cache[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
-  if (!cache[dev]) {
+  int r = cache[dev].load(std::memory_order_relaxed);
+  if (!r) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    cache[dev] = per_cu * cus;
+    r = per_cu * cus;
+    cache[dev].store(r, std::memory_order_relaxed);   // every thread computes the same value
   }
-  return cache[dev];
+  return r;
 }
 
 // Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
