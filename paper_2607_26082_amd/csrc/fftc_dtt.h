@@ -222,7 +222,8 @@ __device__ __forceinline__ T post_ct(int type, int inv, const cplx<T>* Zb, int m
 
 // Complex FFT of LB lines of length NF held in LDS (cb, line stride CS); the first pass
 // reads its inputs through `load(l, k)` (pre-processing) instead of from cb.  On return
-// the result is in cb in natural order.  Must be called by all NT threads.
+// the result is in cb in natural order.  tw: e^{-2 pi i s / 4NF} for s = 0 .. 2 NF.  Must be
+// called by all NT threads.
 template <typename T, int NF, int SGN, int NT, typename Loader>
 __device__ __forceinline__ void fft_ct(cplx<T>* cb, int CS, const cplx<T>* __restrict__ tw, Loader load) {
   constexpr int R1 = FftPlan<NF>::R1, R2 = FftPlan<NF>::R2;
@@ -252,8 +253,12 @@ __device__ __forceinline__ void fft_ct(cplx<T>* cb, int CS, const cplx<T>* __res
       for (int q = 0; q < R2; ++q) {
         cplx<T> v = cb[l * CS + cpad<NF>(j + q * B2)];
         if (q > 0 && kk > 0) {
-          // W_{R1 R2}^{q kk} = e^{SGN 2 pi i q kk / NF}; table holds e^{-2 pi i s / 4NF}
-          cplx<T> f = tw[4 * q * kk];
+          // W_{R1 R2}^{q kk} = e^{SGN 2 pi i q kk / NF}; the table holds e^{-2 pi i s / 4NF}
+          // for s <= 2 NF only, and q kk < NF: past NF / 2 use e^{-i pi} = -1
+          const int jj = q * kk;
+          const bool hi = jj > NF / 2;
+          cplx<T> f = tw[4 * (hi ? jj - NF / 2 : jj)];
+          if (hi) f = {-f.re, -f.im};
           if (SGN > 0) f.im = -f.im;
           v = cmul(v, f);
         }

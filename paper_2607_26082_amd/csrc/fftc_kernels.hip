@@ -892,11 +892,12 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   base += (long long)c * a.g.Nn;
   T* rb = (T*)smem;
   cplx<T>* cb = (cplx<T>*)smem;
-  // twiddle table e^{-2 pi i s / 4NF}, s < 4NF, staged in LDS after the line buffer
+  // twiddles e^{-2 pi i s / 4NF} staged in LDS after the line buffer: s <= 2 NF covers the
+  // pre- and post-processing, and the FFT folds its larger indices onto that range
   cplx<T>* tws = (cplx<T>*)smem + LB * CS;
   {
     const cplx<T>* twg = (const cplx<T>*)a.ap.tw;
-    for (int s = threadIdx.x; s < 4 * NF; s += NT) tws[s] = twg[s];
+    for (int s = threadIdx.x; s <= 2 * NF; s += NT) tws[s] = twg[s];
   }
   const cplx<T>* tw = tws;
   // TY >= 0: every component of this pass has transform type TY (fixed at compile time)
@@ -2097,7 +2098,7 @@ static void launch_dtt2(const DttArgs<T>& a, hipStream_t s) {
   if (a.axis == 0) grid = dim3((Ny + S::LB - 1) / S::LB, Nz, 3);
   else if (a.axis == 1) grid = dim3((Nx + S::LB - 1) / S::LB, Nz, 3);
   else grid = dim3((Nx + S::LB - 1) / S::LB, Ny, 3);
-  const size_t sm = sizeof(cplx<T>) * ((size_t)S::LB * S::CS + 4 * NF);
+  const size_t sm = sizeof(cplx<T>) * ((size_t)S::LB * S::CS + 2 * NF + 1);
   hipLaunchKernelGGL((k_dtt2<T, NF, NTH, TY>), grid, dim3(S::NT), sm, s, a);
 }
 
