@@ -378,8 +378,9 @@ void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
   const long long n3 = 3 * h->Nn;
   hipStream_t s = h->stream;
   if (tm) tm->mark(s);
-  launch_delta_iteration_front<float>(h->g, D, ct, w, h->st, h->part, h->wpart, h->nblk_res, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, s);
   if (tm) tm->mark(s);
+  launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
   if (tm) tm->mark(s);
   if (h->cfg.acv == FFTC_ACV_P) launch_delta_anderson<float>(D, n3, h->st, h->gpart, h->nblk_res, s);
   if (tm) tm->mark(s);

@@ -2182,8 +2182,8 @@ void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double
 TileGrid residual_tiles(const Geo& g);
 
 template <typename T>
-void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
-                                  DevState* st, double* part, double* wpart, int nblk, hipStream_t s) {
+int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
+                          int nblk, hipStream_t s) {
   const TileGrid tg = residual_tiles(g);
   if (tg.tx > 0) {
     nblk = tg.tx * tg.ty * tg.nseg;
@@ -2191,6 +2191,12 @@ void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const Con
   } else {
     hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
   }
+  return nblk;
+}
+
+template <typename T>
+void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w, DevState* st,
+                          const double* part, const double* wpart, int nblk, hipStream_t s) {
   if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(grid_for(w.m, 1 << 30)), dim3(kBlock), 0, s, g, D, w, st);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, st, part, nblk, wpart, w.m, ct, kPartStrideD);
 }
@@ -2319,8 +2325,10 @@ FFTC_INST(float)
 template void launch_convert<double, double>(const double*, double*, long long, hipStream_t);
 template void launch_convert<double, float>(const double*, float*, long long, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, long long, hipStream_t);
-template void launch_delta_iteration_front<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
-                                                  DevState*, double*, double*, int, hipStream_t);
+template int launch_delta_residual<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, DevState*, double*,
+                                          int, hipStream_t);
+template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
+                                          DevState*, const double*, const double*, int, hipStream_t);
 template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
 template void launch_delta_proj<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, const WeakDev&,
                                        const ContactDev&, DevState*, int, int, hipStream_t);

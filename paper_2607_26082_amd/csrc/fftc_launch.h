@@ -11,9 +11,14 @@ template <typename T>
 void launch_weak(const Geo& g, const Bufs<T>& B, const WeakDev& w, DevState* st, int force, hipStream_t s);
 void launch_control(DevState* st, const double* part, int nblk, const double* wpart, long long nweak,
                     const ContactDev& ct, int pstride, hipStream_t s);
+// Residual-form iteration, first half: the residual pass (returns the number of block
+// partial rows it wrote), then the average relations and the control step over those rows.
 template <typename T>
-void launch_delta_iteration_front(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w,
-                                  DevState* st, double* part, double* wpart, int nblk, hipStream_t s);
+int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
+                          int nblk, hipStream_t s);
+template <typename T>
+void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w, DevState* st,
+                          const double* part, const double* wpart, int nblk, hipStream_t s);
 // Tile grid of the tiled residual pass on the current device.  Its first call on a device
 // queries the kernel's occupancy, which must not happen under stream capture: call it once
 // outside capture (the workspace binding does) before capturing iterations.
