@@ -117,11 +117,26 @@ int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node_host, const int8
                        const double* value_host, int32_t set_id);
 
 /* Kinematic relations: mean of u[comp[r]] over the k nodes of support r equals value[r]
- * (Section 4.2.1, eq 10-14; k = 8 voxel corners or k = 4 face corners; calls of either
- * size may be combined in one problem).  support_host: m*k triples.  Errors: FFTC_E_ARG, FFTC_E_BC (support node eliminated for comp),
- * FFTC_E_OVERLAP (a DOF in two supports or also strongly constrained). */
+ * (Section 4.2.1, eq 10-14: k = 8 voxel corners or k = 4 face corners; Section 4.2.3: the 44
+ * nodes of a line of ten voxels; any 2 <= k <= 64; calls of different k may be combined).
+ * proj_U moves the support by the same amount (eq 11), proj_P removes the mean of the
+ * boundary-weighted residual 2^-b p from it (eq 14).  support_host: m*k triples.
+ * Errors: FFTC_E_ARG (k or index out of range), FFTC_E_BC (support node eliminated for comp),
+ * FFTC_E_OVERLAP (a DOF in two supports or also constrained otherwise). */
 int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support_host,
                      const int8_t* comp_host, const double* value_host, int32_t set_id);
+
+/* Smoothly applied conditions (Section 4.2.2, eq 15-17, Table 2): u[comp[r]] at node r equals
+ * value[r] (proj_U, eq 15), and the node's reaction is spread over its neighbours (proj_P,
+ * eq 17): a node on no non-periodic face spreads over the 26 nodes of the 2x2x2-voxel cell
+ * around it (weights 1/2 middle of faces, 1/4 middle of edges, 1/8 corners, total 8 times
+ * the node's multiplier); a node on one face over the 8 nodes of the 2x2 face cell around it
+ * in the face plane (1/2, 1/4, total 4).  node_host: m triples (i, j, k).  The reaction
+ * reported per condition is the total force.  Errors: FFTC_E_ARG (index out of range),
+ * FFTC_E_UNSUPPORTED (node on an edge or corner of the cell), FFTC_E_BC (support reaches a
+ * DOF held at 0 by a Dirichlet face), FFTC_E_OVERLAP (support shares a constrained DOF). */
+int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node_host, const int8_t* comp_host,
+                    const double* value_host, int32_t set_id);
 
 /* Rigid sphere obstacle (Section 5): every node of face (axis*2 + side) is a potential
  * contact node.  Errors: FFTC_E_ARG (radius <= 0, face out of range, periodic axis). */
@@ -154,7 +169,9 @@ int fftc_move_sphere(fftc_h h, const double center_host[3]);
 
 /* Reactions of the last solve (Section 4.1.3: physical nodal force 2^-b p, sign of eq 8):
  * per_dof_host[m_strong] in the order the strong DOFs were added (dropped zero DOFs
- * excluded), per_relation_host[m_average], totals_host[nsets*3].  Any pointer may be NULL. */
+ * excluded), per_relation_host[m_relations] (averages and smooth conditions in the order
+ * they were added: the total force each applies), totals_host[nsets*3].  Any pointer may
+ * be NULL. */
 int fftc_get_reactions(fftc_h h, double* per_dof_host, double* per_relation_host,
                        double* totals_host, int32_t nsets);
 int fftc_num_constraints(fftc_h h, int64_t* n_strong, int64_t* n_average);

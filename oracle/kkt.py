@@ -1,15 +1,17 @@
 """Direct solves of the constrained minimisation problems (plain definitions).
 
-Paper, Section 4.3, eq (18)-(22): the converged fixed point solves
+Paper, Section 4.3, eq (18)-(23): the converged fixed point solves
 min 1/2 u^T K u subject to A u = U, i.e. the saddle-point system
 [K A^T; A 0][u; f] = [0; U], where K is assembled over the voxels of the
 cell, u holds every DOF not eliminated by an antisymmetric extension, A holds
 unit rows for strong constraints (eq 21) and 1/k rows for average relations
-(eq 22).  Section 5.5, eq (31)-(33) adds unilateral contact.
+(eq 22).  Smoothly applied conditions (eq 23) replace A^T by a distribution
+matrix B: the system [K B; A 0] is no longer symmetric.  Section 5.5, eq
+(31)-(33) adds unilateral contact.
 
 Sign convention: `reaction` returned here is the force the constraint applies
-to the body, K u = A^T reaction (the paper's eq 8 convention, f = -lambda of
-eq 19).  Remaining free modes of [K; A] (rigid sub-lattice motions left free
+to the body, K u = B f (the paper's eq 8 convention, f = -lambda of eq 19),
+reported per constraint as the total force sum(B column) f.  Remaining free modes of [K; A] (rigid sub-lattice motions left free
 by the boundary conditions) are reported as an orthonormal basis Z so that a
 caller can compare displacements modulo that span.
 """
@@ -18,6 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 from .plan import Plan
+from .relations import relations_from
 from .tetra2 import assemble_dense, element_tensor_iso
 
 
@@ -25,7 +28,7 @@ def assemble_physical(plan, lam, mu):
     return assemble_dense(plan, lambda vx, vy, vz: element_tensor_iso(lam[vz, vy, vx], mu[vz, vy, vx]))
 
 
-def dense_kkt(n, lam, mu, bc, strong=(), average=()):
+def dense_kkt(n, lam, mu, bc, strong=(), average=(), smooth=()):
     plan = Plan(n, bc)
     Nx, Ny, Nz = plan.N
     Nn = Nx * Ny * Nz
@@ -35,7 +38,7 @@ def dense_kkt(n, lam, mu, bc, strong=(), average=()):
     pos = -np.ones(3 * Nn, np.int64)
     pos[fidx] = np.arange(len(fidx))
     Kr = K[np.ix_(fidx, fidx)]
-    rows, rhs = [], []
+    rows, cols, rhs = [], [], []
     for s in strong:
         node = np.asarray(s.node, np.int64).reshape(-1, 3)
         for (i, j, k), c, v in zip(node, s.comp, s.value):
@@ -43,22 +46,22 @@ def dense_kkt(n, lam, mu, bc, strong=(), average=()):
             if pos[dof] < 0:
                 continue                           # eliminated DOF with value 0
             r = np.zeros(len(fidx)); r[pos[dof]] = 1.0
-            rows.append(r); rhs.append(float(v))
-    for a in average:
-        sup = np.asarray(a.support, np.int64).reshape(len(a.comp), -1, 3)
-        for r_i in range(sup.shape[0]):
-            r = np.zeros(len(fidx))
-            kk = sup.shape[1]
-            for (i, j, k) in sup[r_i]:
-                r[pos[int(a.comp[r_i]) * Nn + i + Nx * (j + Ny * k)]] += 1.0 / kk
-            rows.append(r); rhs.append(float(a.value[r_i]))
+            rows.append(r); cols.append(r); rhs.append(float(v))
+    for rel in relations_from(plan, average, smooth):
+        r = np.zeros(len(fidx)); bcol = np.zeros(len(fidx))
+        for node, wa, wb in zip(rel.nodes, rel.a, rel.b):
+            r[pos[rel.comp * Nn + int(node)]] += wa
+            bcol[pos[rel.comp * Nn + int(node)]] += wb
+        rows.append(r); cols.append(bcol); rhs.append(rel.value)
     A = np.array(rows).reshape(-1, len(fidx))
+    B = np.array(cols).reshape(-1, len(fidx)).T
     U = np.array(rhs)
     m = A.shape[0]
-    KKT = np.block([[Kr, A.T], [A, np.zeros((m, m))]])
+    KKT = np.block([[Kr, B], [A, np.zeros((m, m))]])
     b = np.concatenate([np.zeros(len(fidx)), U])
     sol, *_ = np.linalg.lstsq(KKT, b, rcond=1e-13)
     ur, lam_mult = sol[:len(fidx)], sol[len(fidx):]
+    total = B.sum(axis=0) if m else np.zeros(0)
     # free modes: null space of [Kr; A]
     M = np.vstack([Kr, A]) if m else Kr
     _, sv, Vt = np.linalg.svd(M)
@@ -68,7 +71,7 @@ def dense_kkt(n, lam, mu, bc, strong=(), average=()):
     u[fidx] = ur
     Z = np.zeros((3 * Nn, Zr.shape[1]))
     Z[fidx] = Zr
-    return dict(u=u.reshape(3, Nz, Ny, Nx), reaction=-lam_mult, Z=Z, K=K, plan=plan,
+    return dict(u=u.reshape(3, Nz, Ny, Nx), reaction=-lam_mult * total, Z=Z, K=K, plan=plan,
                 residual=np.abs(KKT @ sol - b).max())
 
 

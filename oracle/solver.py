@@ -1,16 +1,17 @@
 """Algorithm 1: displacement-based fixed point with local kinematic constraints.
 
-Paper, Section 4.1.1, eq (9) and Algorithm 1, with the weak (voxel/face
-average) relations of Section 4.2.1 (eq 10-14).  One iteration:
+Paper, Section 4.1.1, eq (9) and Algorithm 1, with the relations on several nodes of
+Section 4.2 (averages, eq 10-14; smoothly applied conditions, eq 15-17; see relations.py).
+One iteration:
 
   sigma = C : grad^s_D(u)
   p = div_D(sigma)
-  proj_P: strong DOFs p = 0, weak supports p -= mean
+  proj_P: strong DOFs p = 0, relation supports per eq 14 / eq 17
   exit if h ||p|| / ||sigma|| < tol                        (eq 5)
   p~ = p - div_D(R0 : grad_D u)
   Anderson on p~ (ACV_P) or on u (ACV_U)
   u = DT^-1( G_hat DT(p~) )                                (eq 3, right)
-  proj_U: strong DOFs u = U, weak supports u += U - mean
+  proj_U: strong DOFs u = U, relation supports per eq 11 / eq 15
 
 Readings (the paper defers these details to other work):
  * Anderson: type II with mixing 1 over the last four pairs
@@ -23,15 +24,15 @@ Readings (the paper defers these details to other work):
    boundary-weighted p after proj_P; ||sigma||^2 = sum over voxels and both
    IPs of (1/2) sigma:sigma; h = 1.
  * Reactions (Section 4.1.3): the physical nodal force is 2^-b p; the
-   reaction of a strong DOF is f = -2^-b p before proj_P, that of a weak
-   relation f = -sum_support 2^-b p.
- * Weak relations act on the physical (2^-b weighted) residual.
+   reaction of a strong DOF is f = -2^-b p before proj_P, that of a relation the total
+   force it applies (relations.py).
+ * Relations act on the physical (2^-b weighted) residual.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import tetra2
+from . import relations, tetra2
 from .green import Green, reference_from_factor
 from .plan import Plan
 
@@ -77,9 +78,9 @@ class Anderson:
 
 
 class Constraints:
-    """Strong nodal DOFs and weak average relations on the node grid of a plan."""
+    """Strong nodal DOFs and relations on several nodes (averages, smooth conditions)."""
 
-    def __init__(self, plan, strong=(), average=()):
+    def __init__(self, plan, strong=(), average=(), smooth=()):
         self.plan = plan
         Nx, Ny, Nz = plan.N
         sc, sn, sv, ss = [], [], [], []
@@ -97,43 +98,35 @@ class Constraints:
         self.s_node = np.concatenate(sn) if sn else np.zeros(0, np.int64)
         self.s_val = np.concatenate(sv) if sv else np.zeros(0)
         self.s_set = np.concatenate(ss) if ss else np.zeros(0, np.int64)
-        self.weak = []     # (comp, flat nodes [k], value, set_id)
-        for a in average:
-            sup = np.asarray(a.support, np.int64).reshape(len(a.comp), -1, 3)
-            for r in range(sup.shape[0]):
-                flat = sup[r, :, 0] + Nx * (sup[r, :, 1] + Ny * sup[r, :, 2])
-                self.weak.append((int(a.comp[r]), flat, float(a.value[r]), a.set_id))
+        self.rel = relations.relations_from(plan, average, smooth)
+        Nn = Nx * Ny * Nz
+        relations.check_relations(plan, self.rel, self.s_comp * Nn + self.s_node)
         self.w2b = plan.w2b.ravel()
 
     def proj_U(self, u):
         uf = u.reshape(3, -1)
         uf[self.s_comp, self.s_node] = self.s_val
-        for c, nodes, val, _ in self.weak:
-            uf[c, nodes] += val - uf[c, nodes].mean()
+        relations.proj_U(u, self.rel)
         return u
 
     def proj_P(self, p):
-        """Projects p in place and returns (strong reactions [m], weak reactions [r])."""
+        """Projects p in place and returns (strong reactions [m], relation reactions [r])."""
         pf = p.reshape(3, -1)
         f_strong = -pf[self.s_comp, self.s_node] / self.w2b[self.s_node]
         pf[self.s_comp, self.s_node] = 0.0
-        f_weak = np.zeros(len(self.weak))
-        for r, (c, nodes, val, _) in enumerate(self.weak):
-            phys = pf[c, nodes] / self.w2b[nodes]
-            f_weak[r] = -phys.sum()
-            pf[c, nodes] = (phys - phys.mean()) * self.w2b[nodes]
-        return f_strong, f_weak
+        f_rel = relations.proj_P(p, self.rel, self.w2b)
+        return f_strong, f_rel
 
-    def totals(self, f_strong, f_weak, nsets):
+    def totals(self, f_strong, f_rel, nsets):
         out = np.zeros((nsets, 3))
         np.add.at(out, (self.s_set, self.s_comp), f_strong)
-        for r, (c, _, _, sid) in enumerate(self.weak):
-            out[sid, c] += f_weak[r]
+        for r, rel in enumerate(self.rel):
+            out[rel.set_id, rel.comp] += f_rel[r]
         return out
 
 
 class Solver:
-    def __init__(self, n, lam, mu, bc, strong=(), average=(), r0_factor=1.0, lam0=None, mu0=None):
+    def __init__(self, n, lam, mu, bc, strong=(), average=(), r0_factor=1.0, lam0=None, mu0=None, smooth=()):
         self.plan = Plan(n, bc)
         self.lam = np.asarray(lam, np.float64)
         self.mu = np.asarray(mu, np.float64)
@@ -141,12 +134,14 @@ class Solver:
             lam0, mu0 = reference_from_factor(self.lam, self.mu, r0_factor)
         self.lam0, self.mu0 = lam0, mu0
         self.green = Green(self.plan, lam0, mu0)
-        self.cons = Constraints(self.plan, strong, average)
-        self.nsets = 1 + max([s.set_id for s in strong] + [a.set_id for a in average] + [0])
+        self.cons = Constraints(self.plan, strong, average, smooth)
+        self.nsets = 1 + max([s.set_id for s in strong] + [a.set_id for a in average] +
+                             [m.set_id for m in smooth] + [0])
 
     @classmethod
     def from_problem(cls, prob):
-        return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.r0_factor)
+        return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.r0_factor,
+                   smooth=prob.smooth)
 
     def zeros(self):
         return np.zeros((3,) + tuple(self.plan.N[J] for J in (2, 1, 0)))

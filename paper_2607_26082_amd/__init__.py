@@ -52,6 +52,8 @@ _SIGS = {
                                      C.POINTER(C.c_double), C.c_int32]),
     "fftc_add_average": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
                                    C.POINTER(C.c_double), C.c_int32]),
+    "fftc_add_smooth": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
+                                  C.POINTER(C.c_double), C.c_int32]),
     "fftc_set_sphere": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, C.c_int32]),
     "fftc_move_sphere": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "fftc_set_solver": (C.c_int, [_P, C.POINTER(fftc_solver_cfg)]),
@@ -183,6 +185,14 @@ def fftc_add_average(h, support, comp, value, set_id=0):
     return _check(h, load().fftc_add_average(h, len(comp), sup.shape[1], _ptr(sup, C.c_int64),
                                              _ptr(comp, C.c_int8), _ptr(value, C.c_double), int(set_id)),
                   "fftc_add_average")
+
+
+def fftc_add_smooth(h, node, comp, value, set_id=0):
+    node = np.ascontiguousarray(np.asarray(node, np.int64).reshape(-1, 3))
+    comp = np.ascontiguousarray(np.asarray(comp, np.int8).ravel())
+    value = np.ascontiguousarray(np.asarray(value, np.float64).ravel())
+    return _check(h, load().fftc_add_smooth(h, len(comp), _ptr(node, C.c_int64), _ptr(comp, C.c_int8),
+                                            _ptr(value, C.c_double), int(set_id)), "fftc_add_smooth")
 
 
 def fftc_set_sphere(h, center, radius, face):
@@ -476,7 +486,8 @@ class Solver:
     """One problem on the current CUDA (HIP) device: handle + torch-owned workspace."""
 
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
-                 precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda"):
+                 precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
+                 smooth=()):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -493,6 +504,9 @@ class Solver:
         for a in average:
             fftc_add_average(self.h, a.support, a.comp, a.value, a.set_id)
             self.nsets = max(self.nsets, a.set_id + 1)
+        for m in smooth:
+            fftc_add_smooth(self.h, m.node, m.comp, m.value, m.set_id)
+            self.nsets = max(self.nsets, m.set_id + 1)
         if sphere is not None:
             fftc_set_sphere(self.h, sphere.center, sphere.radius, sphere.face)
         fftc_set_reference_factor(self.h, r0_factor)
@@ -519,7 +533,7 @@ class Solver:
         kw.setdefault("acv", prob.acv)
         kw.setdefault("period", prob.acv_period)
         return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.sphere,
-                   prob.r0_factor, precision=precision, **kw)
+                   prob.r0_factor, precision=precision, smooth=prob.smooth, **kw)
 
     def solve(self, zero_start=True):
         rc, rep = fftc_solve(self.h, self.u, zero_start)

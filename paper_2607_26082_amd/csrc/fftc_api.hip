@@ -30,7 +30,10 @@ struct fftc_problem {
   std::vector<int8_t> s_comp;
   std::vector<double> s_val;
   std::vector<int> s_set;
-  std::vector<long long> w_nodes;   // kWeakSlots per relation, unused slots -1
+  // relations on several nodes: support of relation r = slots w_off[r] .. w_off[r+1]
+  std::vector<long long> w_off{0};
+  std::vector<long long> w_nodes;
+  std::vector<double> w_a, w_b, w_d;
   std::vector<int8_t> w_comp;
   std::vector<double> w_val;
   std::vector<int> w_set;
@@ -61,6 +64,8 @@ struct fftc_problem {
   int8_t* d_scomp = nullptr;
   double* d_sval = nullptr;
   long long* d_wnodes = nullptr;
+  long long* d_woff = nullptr;
+  double *d_wa = nullptr, *d_wb = nullptr, *d_wd = nullptr;
   int8_t* d_wcomp = nullptr;
   double* d_wval = nullptr;
   uint8_t *C = nullptr, *V0 = nullptr, *V1 = nullptr;
@@ -202,9 +207,12 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(8 * (ms + 1));
   off[q++] = L.take(ms + 1);
   off[q++] = L.take(8 * (ms + 1));
-  off[q++] = L.take(8 * (h->w_nodes.size() + 1));
+  const size_t nslot = h->w_nodes.size();
+  off[q++] = L.take(8 * (nslot + 1));
   off[q++] = L.take(mw + 1);
   off[q++] = L.take(8 * (mw + 1));
+  off[q++] = L.take(8 * (mw + 1));
+  for (int i = 0; i < 3; ++i) off[q++] = L.take(8 * (nslot + 1));
   long long nface = 1;
   if (h->has_sphere) {
     const int a = h->face / 2;
@@ -242,6 +250,10 @@ size_t carve(fftc_problem* h, char* base) {
     h->d_wnodes = (long long*)(base + off[q++]);
     h->d_wcomp = (int8_t*)(base + off[q++]);
     h->d_wval = (double*)(base + off[q++]);
+    h->d_woff = (long long*)(base + off[q++]);
+    h->d_wa = (double*)(base + off[q++]);
+    h->d_wb = (double*)(base + off[q++]);
+    h->d_wd = (double*)(base + off[q++]);
     h->C = (uint8_t*)(base + off[q++]);
     h->V0 = (uint8_t*)(base + off[q++]);
     h->V1 = (uint8_t*)(base + off[q++]);
@@ -328,7 +340,8 @@ StrongDev strong_dev(fftc_problem* h) {
 }
 
 WeakDev weak_dev(fftc_problem* h) {
-  WeakDev w{(long long)h->w_comp.size(), kWeakSlots, h->d_wnodes, h->d_wcomp, h->d_wval, h->wpart, h->wreact};
+  WeakDev w{(long long)h->w_comp.size(), h->d_woff, h->d_wnodes, h->d_wa, h->d_wb, h->d_wd,
+            h->d_wcomp, h->d_wval, h->wpart, h->wreact};
   return w;
 }
 
@@ -819,7 +832,7 @@ int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, con
                      int32_t set_id) {
   if (!h || m < 0 || (m > 0 && (!support || !comp || !value))) return FFTC_E_ARG;
   if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
-  if (k != 4 && k != 8) return fail(h, FFTC_E_ARG, "support size must be 4 or 8");
+  if (k < 2 || k > kMaxRelSlots) return fail(h, FFTC_E_ARG, "support size must be 2..64 nodes");
   if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
   std::unordered_set<long long> mine;
   for (int64_t r = 0; r < m; ++r) {
@@ -836,10 +849,88 @@ int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, con
     }
   }
   for (int64_t r = 0; r < m; ++r) {
-    for (int q = 0; q < kWeakSlots; ++q) {
+    for (int q = 0; q < k; ++q) {
       const int64_t* p = support + (r * k + q) * 3;
-      h->w_nodes.push_back(q < k ? node_flat(h, p[0], p[1], p[2]) : -1);
+      h->w_nodes.push_back(node_flat(h, p[0], p[1], p[2]));
+      h->w_a.push_back(1.0 / k);
+      h->w_b.push_back(1.0);
+      h->w_d.push_back(1.0);
     }
+    h->w_off.push_back((long long)h->w_nodes.size());
+    h->w_comp.push_back(comp[r]);
+    h->w_val.push_back(value[r]);
+    h->w_set.push_back(set_id);
+  }
+  for (long long key : mine) h->dof_used.insert(key);
+  return FFTC_OK;
+}
+
+int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value, int32_t set_id) {
+  if (!h || m < 0 || (m > 0 && (!node || !comp || !value))) return FFTC_E_ARG;
+  if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
+  if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
+  // Table 2 weights by the number of non-zero offsets from the node
+  static const double wvol[4] = {1.0, 0.5, 0.25, 0.125};   // centre, middle of faces, of edges, corners
+  static const double wsurf[3] = {1.0, 0.5, 0.25};         // centre, middle of edges, corners
+  struct Rel {
+    std::vector<long long> nodes;
+    std::vector<double> b;
+  };
+  std::vector<Rel> rels((size_t)m);
+  std::unordered_set<long long> mine;
+  for (int64_t r = 0; r < m; ++r) {
+    const long long c0[3] = {node[3 * r], node[3 * r + 1], node[3 * r + 2]};
+    for (int J = 0; J < 3; ++J)
+      if (c0[J] < 0 || c0[J] >= h->N[J]) return fail(h, FFTC_E_ARG, "constraint node out of range");
+    if (comp[r] < 0 || comp[r] > 2) return fail(h, FFTC_E_ARG, "component out of range");
+    if (!isfinite(value[r])) return fail(h, FFTC_E_ARG, "non-finite prescribed value");
+    int nface = 0, fax = -1;
+    for (int J = 0; J < 3; ++J)
+      if (!h->periodic[J] && (c0[J] == 0 || c0[J] == h->n[J])) {
+        ++nface;
+        fax = J;
+      }
+    if (nface > 1) return fail(h, FFTC_E_UNSUPPORTED, "smooth condition on an edge or corner node of the cell");
+    Rel& R = rels[(size_t)r];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int d[3] = {dx, dy, dz};
+          if (fax >= 0 && d[fax] != 0) continue;       // surface node: neighbours in the face plane
+          long long xyz[3];
+          int nz = 0;
+          for (int J = 0; J < 3; ++J) {
+            long long x = c0[J] + d[J];
+            nz += d[J] != 0;
+            if (h->periodic[J]) x = (x + h->N[J]) % h->N[J];
+            else if (x < 0 || x > h->n[J]) return fail(h, FFTC_E_ARG, "smooth support leaves the cell");
+            xyz[J] = x;
+          }
+          if (node_antisym(h, comp[r], xyz))
+            return fail(h, FFTC_E_BC, "smooth support holds a DOF held at 0 by a Dirichlet face");
+          const long long flat = node_flat(h, xyz[0], xyz[1], xyz[2]);
+          const long long key = comp[r] * h->Nn + flat;
+          if (h->dof_used.count(key) || mine.count(key)) return fail(h, FFTC_E_OVERLAP, "overlapping constraint supports");
+          mine.insert(key);
+          const double w = fax >= 0 ? wsurf[nz] : wvol[nz];
+          if (nz == 0) {        // the node itself leads its support
+            R.nodes.insert(R.nodes.begin(), flat);
+            R.b.insert(R.b.begin(), w);
+          } else {
+            R.nodes.push_back(flat);
+            R.b.push_back(w);
+          }
+        }
+  }
+  for (int64_t r = 0; r < m; ++r) {
+    const Rel& R = rels[(size_t)r];
+    for (size_t q = 0; q < R.nodes.size(); ++q) {
+      h->w_nodes.push_back(R.nodes[q]);
+      h->w_a.push_back(q == 0 ? 1.0 : 0.0);
+      h->w_b.push_back(R.b[q]);
+      h->w_d.push_back(q == 0 ? 1.0 : 0.0);
+    }
+    h->w_off.push_back((long long)h->w_nodes.size());
     h->w_comp.push_back(comp[r]);
     h->w_val.push_back(value[r]);
     h->w_set.push_back(set_id);
@@ -902,7 +993,6 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     }
     for (size_t e = 0; e < h->w_nodes.size(); ++e) {
       long long nd = h->w_nodes[e];
-      if (nd < 0) continue;
       const long long xyz[3] = {nd % h->N[0], (nd / h->N[0]) % h->N[1], nd / ((long long)h->N[0] * h->N[1])};
       if (xyz[a] == fc) return fail(h, FFTC_E_OVERLAP, "average relation on a potential contact node");
     }
@@ -985,8 +1075,7 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
   std::vector<uint8_t> mask(h->Nn, 0);
   for (size_t e = 0; e < h->s_node.size(); ++e) mask[h->s_node[e]] |= (uint8_t)(M_STRONG << h->s_comp[e]);
   for (size_t r = 0; r < h->w_comp.size(); ++r)
-    for (int q = 0; q < kWeakSlots; ++q)
-      if (h->w_nodes[r * kWeakSlots + q] >= 0) mask[h->w_nodes[r * kWeakSlots + q]] |= (uint8_t)(M_WEAK << h->w_comp[r]);
+    for (long long q = h->w_off[r]; q < h->w_off[r + 1]; ++q) mask[h->w_nodes[q]] |= (uint8_t)(M_WEAK << h->w_comp[r]);
   if (h->has_sphere) {
     const int a = h->face / 2;
     const long long fc = (h->face % 2) ? h->n[a] : 0;
@@ -1006,6 +1095,10 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_wnodes, h->w_nodes.data(), 8 * h->w_nodes.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->d_wcomp, h->w_comp.data(), mw, hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->d_wval, h->w_val.data(), 8 * mw, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_woff, h->w_off.data(), 8 * (mw + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_wa, h->w_a.data(), 8 * h->w_a.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_wb, h->w_b.data(), 8 * h->w_b.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->d_wd, h->w_d.data(), 8 * h->w_d.size(), hipMemcpyHostToDevice, s));
   }
   h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
   // autotune the block size of each axis pass: time both variants on the bound buffers

@@ -1,0 +1,82 @@
+// Device helpers shared by the kernel translation units of libfftc.
+#pragma once
+
+#include "fftc_internal.h"
+
+namespace fftc {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of NV doubles; result valid in thread 0.  Fixed reduction order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*16 */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q * 16 + wid] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[q * 16 + w];
+      v[q] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Contiguous node range of this block, with blocks of one XCD (workgroups are dealt
+// round-robin to the 8 XCDs) owning one contiguous slab, so that the y/z neighbours a
+// block reads are produced by blocks on the same XCD and hit its L2.
+__device__ __forceinline__ void xcd_chunk(long long total, long long& lo, long long& hi) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const long long chunk = (total + G - 1) / G;
+  lo = (long long)lb * chunk;
+  hi = lo + chunk < total ? lo + chunk : total;
+}
+
+__device__ __forceinline__ int mirror_coord(const Geo& g, int x, int J) {
+  if (g.periodic[J]) return x < 0 ? x + g.N[J] : (x >= g.N[J] ? x - g.N[J] : x);
+  return x < 0 ? -x : (x > g.n[J] ? 2 * g.n[J] - x : x);
+}
+
+__device__ __forceinline__ bool is_antisym(const Geo& g, int c, const int xyz[3]) {
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    if (g.periodic[J]) continue;
+    if (xyz[J] == 0 && ((g.aface >> (c * 6 + J * 2 + 0)) & 1)) return true;
+    if (xyz[J] == g.n[J] && ((g.aface >> (c * 6 + J * 2 + 1)) & 1)) return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ int bcount(const Geo& g, const int xyz[3]) {
+  int b = 0;
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    if (!g.periodic[J] && (xyz[J] == 0 || xyz[J] == g.n[J])) ++b;
+  return b;
+}
+
+static inline int grid_for(long long n, int cap) {
+  long long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (int)(b < cap ? b : cap);
+}
+
+// blocks of kBlock threads for one wavefront per relation
+static inline int rel_grid(long long m) { return (int)((m + (kBlock / 64) - 1) / (kBlock / 64)); }
+
+}  // namespace fftc

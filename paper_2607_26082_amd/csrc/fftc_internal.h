@@ -118,22 +118,25 @@ struct StrongDev {
   const double* val;
 };
 
-// Average relations: every relation's support (4 or 8 nodes) is stored in kWeakSlots
-// node slots; the unused slots of a 4-node support hold -1.
-constexpr int kWeakSlots = 8;
+// Relations on several nodes (averages, eq 10-14; smoothly applied conditions, eq 15-17):
+// relation r on component comp[r] has the support nodes[off[r] .. off[r+1]) (at most
+// kMaxRelSlots, one wavefront lane per node) with per-node weights: wa its kinematic row
+// (wa . u = val), wb the distribution of its multiplier onto nodal forces (a column of B in
+// eq 23), wd the direction along which proj_U moves the support.
+constexpr int kMaxRelSlots = 64;
 
 struct WeakDev {
   long long m;
-  int k;                    // slots per relation (kWeakSlots)
-  const long long* nodes;   // m*k, unused slots -1
+  const long long* off;     // m + 1 slot offsets
+  const long long* nodes;   // flat node per slot
+  const double* wa;
+  const double* wb;
+  const double* wd;
   const int8_t* comp;
   const double* val;
   double* part;             // per relation partial ||p||^2 after projection
-  double* react;            // per relation reaction
+  double* react;            // per relation total reaction
 };
-
-// support size of relation r (4 or 8)
-__host__ __device__ inline int weak_size(const WeakDev& w, long long r) { return w.nodes[r * w.k + 4] < 0 ? 4 : 8; }
 
 template <typename T>
 struct DttArgs {

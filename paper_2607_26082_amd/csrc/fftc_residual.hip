@@ -1,0 +1,864 @@
+// Residual-form iteration kernels of libfftc (FP32 fields, FP64 displacement) for CDNA4.
+#include "fftc_internal.h"
+#include "fftc_launch.h"
+#include "fftc_common.h"
+
+#include <math.h>
+#include <algorithm>
+#include <atomic>
+
+namespace fftc {
+
+// ===========================================================================
+// Residual-form iteration (FP32 fields, FP64 displacement).  The same fixed point as
+// above with ACV_P, rearranged exactly: with y_i = p_i + K0 u_i the Green input of the
+// paper's iteration, e_i = x_i - K0 u_i is residual-sized, u_{i+1} = Pi u_i + K0^+ e_i,
+// and Anderson runs in difference form on
+//   R_i = p_i + K0 delta_i - e_{i-1},  dR = R_i - R_{i-1},  dY = p_i - p_{i-1} + K0 delta_i,
+//   e_i = p_i - sum_j gamma_j dY_j,  gamma = argmin |R_i - sum_j gamma_j dR_j|.
+// Only residual-sized quantities pass through FP32 transforms.
+// ===========================================================================
+
+// K0 f at a node for the three components (Paux stencil, mirrored neighbours)
+template <typename T>
+__device__ __forceinline__ void stencil_k0(const Geo& g, const T* __restrict__ f, int i, int j, int k, T out[3]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int xs[3] = {mirror_coord(g, i - 1, 0), i, mirror_coord(g, i + 1, 0)};
+  const int ys[3] = {mirror_coord(g, j - 1, 1), j, mirror_coord(g, j + 1, 1)};
+  const int zs[3] = {mirror_coord(g, k - 1, 2), k, mirror_coord(g, k + 1, 2)};
+  auto at = [&](int c, int dx, int dy, int dz) {
+    return f[c * Nn + (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1])];
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T sxy = at(c, -1, -1, 0) + at(c, 1, -1, 0) + at(c, -1, 1, 0) + at(c, 1, 1, 0);
+    const T sxz = at(c, -1, 0, -1) + at(c, 1, 0, -1) + at(c, -1, 0, 1) + at(c, 1, 0, 1);
+    const T syz = at(c, 0, -1, -1) + at(c, 0, 1, -1) + at(c, 0, -1, 1) + at(c, 0, 1, 1);
+    out[c] = T(g.st[c][0]) * at(c, 0, 0, 0) + T(g.st[c][1]) * sxy + T(g.st[c][2]) * sxz + T(g.st[c][3]) * syz;
+  }
+}
+
+// p = 2^b div_D(sigma) from an FP64 displacement: neighbour differences are formed in
+// FP64 and rounded once, the stress and divergence arithmetic is in T.
+template <typename T, bool SIG>
+__device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restrict__ u, const T* __restrict__ lam,
+                                            const T* __restrict__ mu, int i, int j, int k, T p[3], double& sn,
+                                            double ms[6]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int xs[3] = {mirror_coord(g, i - 1, 0), i, mirror_coord(g, i + 1, 0)};
+  const int ys[3] = {mirror_coord(g, j - 1, 1), j, mirror_coord(g, j + 1, 1)};
+  const int zs[3] = {mirror_coord(g, k - 1, 2), k, mirror_coord(g, k + 1, 2)};
+  const long long self = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * k);
+  double u0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u0[c] = u[c * Nn + self];
+  T nb[27][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nrm = (dx != 0) + (dy != 0) + (dz != 0);
+        if (nrm != 2) continue;
+        const long long idx = (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1]);
+        const int q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nb[q][c] = (T)(u[c * Nn + idx] - u0[c]);
+      }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) nb[13][c] = T(0);
+  T F[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    int vx = i - ax, vy = j - ay, vz = k - az;
+    bool inside = true;
+    if (g.periodic[0]) { if (vx < 0) vx += g.n[0]; } else inside &= (vx >= 0 && vx < g.n[0]);
+    if (g.periodic[1]) { if (vy < 0) vy += g.n[1]; } else inside &= (vy >= 0 && vy < g.n[1]);
+    if (g.periodic[2]) { if (vz < 0) vz += g.n[2]; } else inside &= (vz >= 0 && vz < g.n[2]);
+    if (!inside) continue;
+    const long long vid = (long long)vx + (long long)g.n[0] * ((long long)vy + (long long)g.n[1] * vz);
+    const T l = lam[vid], m = mu[vid];
+    T G[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) G[r][s] = T(0);
+    const int par = (ax + ay + az) & 1;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+      if (((cx + cy + cz) & 1) != par) continue;
+      const int q = (cx - ax + 1) + 3 * (cy - ay + 1) + 9 * (cz - az + 1);
+      const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        G[r][0] += sx * nb[q][r];
+        G[r][1] += sy * nb[q][r];
+        G[r][2] += sz * nb[q][r];
+      }
+    }
+    const T tr = G[0][0] + G[1][1] + G[2][2];
+    const T s00 = l * tr + T(2) * m * G[0][0];
+    const T s11 = l * tr + T(2) * m * G[1][1];
+    const T s22 = l * tr + T(2) * m * G[2][2];
+    const T s01 = m * (G[0][1] + G[1][0]);
+    const T s02 = m * (G[0][2] + G[2][0]);
+    const T s12 = m * (G[1][2] + G[2][1]);
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    F[0] += bx * s00 + by * s01 + bz * s02;
+    F[1] += bx * s01 + by * s11 + bz * s12;
+    F[2] += bx * s02 + by * s12 + bz * s22;
+    if (SIG && (a == 0 || a == 1)) {
+      const double d00 = s00, d11 = s11, d22 = s22, d01 = s01, d02 = s02, d12 = s12;
+      sn += 0.5 * (d00 * d00 + d11 * d11 + d22 * d22 + 2.0 * (d01 * d01 + d02 * d02 + d12 * d12));
+      ms[0] += 0.5 * d00; ms[1] += 0.5 * d11; ms[2] += 0.5 * d22;
+      ms[3] += 0.5 * d12; ms[4] += 0.5 * d02; ms[5] += 0.5 * d01;
+    }
+  }
+  const int xyz[3] = {i, j, k};
+  const T w2b = T(1 << bcount(g, xyz));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+}
+
+// forward-transform weight of a node in the singular coefficients (DCT1 ends 1, interior 2; DFT 1)
+__device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
+  double w = 1.0;
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    if (!g.periodic[J] && xyz[J] > 0 && xyz[J] < g.n[J]) w *= 2.0;
+  return w;
+}
+
+// Per-node part of the residual pass of the residual-form iteration, once p is known:
+// singular-mode coefficients of u, contact bookkeeping or constraint masking, the norm of
+// p, p itself, and (ACV_P, from the second iteration on) R_i = p_i + K0 delta_i - e_{i-1}
+// with its differences.  kd = K0 delta at the node (read only when kd_used).
+// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}, R_{i-1}.
+template <typename T>
+struct TailIn {
+  uint8_t m;
+  T e[3], pp[3], rp[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, const T* pp,
+                                          const T* Rp, long long node, TailIn<T>& t) {
+  t.m = D.mask[node];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    t.e[c] = T(0);
+    t.pp[c] = T(0);
+    t.rp[c] = T(0);
+    if (kd_used) {
+      t.e[c] = D.e[c * Nn + node];
+      if (il >= 2) {
+        t.pp[c] = pp[c * Nn + node];
+        t.rp[c] = Rp[c * Nn + node];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, int cur,
+                                           bool kd_used, int il, int slot, T* pc, T* Rc, int i, int j, int k,
+                                           long long node, T p[3], const T kd[3], const TailIn<T>& tin,
+                                           double* acc) {
+  const long long Nn = g.Nn;
+  const int xyz[3] = {i, j, k};
+  // singular-mode coefficients of u (projection Pi of the update)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!g.sing[c]) continue;
+    const double wu = sing_weight(g, xyz) * D.u[c * Nn + node];
+    acc[8 + 2 * c] += wu;
+    if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
+  }
+  const uint8_t m = tin.m;
+  if (ct.on && (m & M_FACE)) {
+    const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
+    const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
+    const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
+    const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double gap = rr - ct.radius;
+    const double n0 = -d0 / rr, n1 = -d1 / rr, n2 = -d2 / rr;
+    const double pn = (double)p[0] * n0 + (double)p[1] * n1 + (double)p[2] * n2;
+    const double fnc = -pn / (double)(1 << bcount(g, xyz));
+    const uint8_t inC = ct.C[f];
+    if (inC) {
+      p[0] = (T)((double)p[0] - pn * n0);
+      p[1] = (T)((double)p[1] - pn * n1);
+      p[2] = (T)((double)p[2] - pn * n2);
+    }
+    ct.V[cur][f] = (uint8_t)(((!inC) && gap < 0.0) ? 1 : 0) | (uint8_t)((inC && fnc > 0.0) ? 2 : 0);
+    ct.fnc[f] = fnc;
+    ct.gap[f] = gap;
+    acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (m & (M_STRONG << c)) p[c] = T(0);
+      else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pc[c * Nn + node] = p[c];
+  if (kd_used) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long e = c * Nn + node;
+      const T Ri = p[c] + kd[c] - tin.e[c];
+      Rc[e] = Ri;
+      if (il >= 2) {
+        D.dR[slot][e] = Ri - tin.rp[c];
+        D.dY[slot][e] = p[c] - tin.pp[c] + kd[c];
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[kPartStrideD * 16];
+  if (st->done) return;
+  double acc[kPartStrideD];
+#pragma unroll
+  for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int cur = ct.on ? st->vpar : 0;
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;   // (il - 2) mod 3
+  const bool kd_used = acvp && il >= 1;
+  T* pc = D.p[par];
+  const T* pp = D.p[par ^ 1];
+  T* Rc = D.R[par];
+  const T* Rp = D.R[par ^ 1];
+  long long lo, hi;
+  xcd_chunk(Nn, lo, hi);
+  for (long long node = lo + threadIdx.x; node < hi; node += blockDim.x) {
+    const int nd = (int)node;
+    const int r = nd / Nx;
+    const int i = nd - r * Nx;
+    const int k = r / Ny, j = r - k * Ny;
+    T p[3];
+    double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
+    node_eval_d<T, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    acc[1] += sn;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
+    T kd[3] = {T(0), T(0), T(0)};
+    if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
+    TailIn<T> tin;
+    tail_load<T>(D, Nn, kd_used, il, pp, Rp, node, tin);
+    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
+  }
+  block_sum<kPartStrideD>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// The same residual pass, tiled: a block owns a kTX x kTY column of nodes and marches
+// along z over a segment of node planes.  Node planes of u (FP64) and of delta (with the
+// stencil's mirrored / periodic halo) sit in LDS with a one-node halo; the stresses of the
+// two tetrahedra of every voxel of a layer are formed once per block (differences of u
+// taken in FP64 against the voxel's corner 000, then rounded) and serve the two node
+// planes that bound the layer.  Every voxel's stress-norm and mean-stress terms are
+// counted by the one block whose node column and segment contain its corner 000.
+// ---------------------------------------------------------------------------
+constexpr int kTX = 31, kTY = 7;                // 217 nodes; 32 x 8 = 256 voxels per layer
+constexpr int kHX = kTX + 2, kHY = kTY + 2;   // node tile with halo: x0-1 .. x0+kTX
+constexpr int kVX = kTX + 1, kVY = kTY + 1;   // voxels x0-1 .. x0+kTX-1
+constexpr int kPlane = 3 * kHY * kHX;         // values of one staged node plane
+constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
+
+// slot of node plane p in the four-plane ring of delta planes (p may be -1)
+__device__ __forceinline__ int ring4(int p) { return p & 3; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
+                                                     double* __restrict__ part, TileGrid tg) {
+  __shared__ double su[2][3][kHY][kHX];
+  __shared__ T sdl[4][3][kHY][kHX];
+  __shared__ T ss[2][12][kVY][kVX];   // stress component q of the voxels of a layer
+  __shared__ double sh[kPartStrideD * 16];
+  if (st->done) return;
+  const int tid = threadIdx.x;
+  // contiguous ranges of tiles per XCD (blocks go to the 8 XCDs round-robin), so that
+  // neighbouring tiles share their halo lines in one L2
+  int b;
+  {
+    const unsigned G = gridDim.x, p = blockIdx.x;
+    const unsigned q = G / 8, r = G % 8, xcd = p % 8, slot = p / 8;
+    b = (int)(xcd * q + (xcd < r ? xcd : r) + slot);
+  }
+  const int bx = b % tg.tx, by = (b / tg.tx) % tg.ty, bz = b / (tg.tx * tg.ty);
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int zb = bz * tg.seg;
+  const int ze = min(zb + tg.seg, Nz);
+  const int Nn = (int)g.Nn;
+  const int cur = ct.on ? st->vpar : 0;
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;
+  const bool kd_used = acvp && il >= 1;
+  T* pc = D.p[par];
+  const T* pp = D.p[par ^ 1];
+  T* Rc = D.R[par];
+  const T* Rp = D.R[par ^ 1];
+  double acc[kPartStrideD];
+#pragma unroll
+  for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
+
+  // Node planes are fetched into registers one step ahead and committed to LDS the next
+  // step.  u: su[pz & 1], nodes outside the grid read as 0 (no voxel uses them); delta:
+  // sdl[pz mod 4] with the stencil's halo (mirror or periodic image).
+  double ru[kPR];
+  T rd[kPR];
+  auto fetch = [&](int pz) {
+    int gz = pz;
+    bool okz = true;
+    if (g.periodic[2]) gz = (pz + Nz) % Nz;
+    else okz = pz >= 0 && pz < Nz;
+    const int mz = mirror_coord(g, pz, 2);
+    const bool okm = mz >= 0 && mz < Nz;
+#pragma unroll
+    for (int r = 0; r < kPR; ++r) {
+      const int e = tid + 256 * r;
+      ru[r] = 0.0;
+      rd[r] = T(0);
+      if (e < kPlane) {
+        const int c = e / (kHY * kHX), q = e - c * (kHY * kHX);
+        const int hy = q / kHX, hx = q - hy * kHX;
+        int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+        bool ok = okz;
+        if (g.periodic[0]) gx = (gx + Nx) % Nx;
+        else ok = ok && gx >= 0 && gx < Nx;
+        if (g.periodic[1]) gy = (gy + Ny) % Ny;
+        else ok = ok && gy >= 0 && gy < Ny;
+        if (ok) ru[r] = D.u[c * Nn + gx + Nx * (gy + Ny * gz)];
+        if (kd_used) {
+          const int mx = mirror_coord(g, x0 - 1 + hx, 0), my = mirror_coord(g, y0 - 1 + hy, 1);
+          if (okm && mx >= 0 && mx < Nx && my >= 0 && my < Ny) rd[r] = D.delta[c * Nn + mx + Nx * (my + Ny * mz)];
+        }
+      }
+    }
+  };
+  auto commit = [&](int pz) {
+    double* du = &su[pz & 1][0][0][0];
+    T* dd = &sdl[ring4(pz)][0][0][0];
+#pragma unroll
+    for (int r = 0; r < kPR; ++r) {
+      const int e = tid + 256 * r;
+      if (e < kPlane) {
+        du[e] = ru[r];
+        if (kd_used) dd[e] = rd[r];
+      }
+    }
+  };
+  // Every thread owns one voxel of a layer (kVX * kVY = 256): local (vlx, vly).
+  const int vly = tid / kVX, vlx = tid - (tid / kVX) * kVX;
+  const int vux = x0 - 1 + vlx, vuy = y0 - 1 + vly;   // unwrapped voxel coordinates
+  int vxw = vux, vyw = vuy;
+  bool vok = true;
+  if (g.periodic[0]) vxw = (vux + nx) % nx;
+  else vok = vux >= 0 && vux < nx;
+  if (g.periodic[1]) vyw = (vuy + ny) % ny;
+  else vok = vok && vuy >= 0 && vuy < ny;
+  // Lame values of this thread's voxel in layer lz (fetched one step ahead)
+  auto fetch_lm = [&](int lz, T& l, T& m, bool& ok) {
+    int vz = lz;
+    ok = vok;
+    if (g.periodic[2]) vz = (lz + nz) % nz;
+    else ok = ok && lz >= 0 && lz < nz;
+    l = T(0);
+    m = T(0);
+    if (ok) {
+      const int vid = vxw + nx * (vyw + ny * vz);
+      l = D.lam[vid];
+      m = D.mu[vid];
+    }
+  };
+  // voxel layer lz (between node planes lz and lz+1, held in su[lz & 1] and su[(lz+1) & 1])
+  auto layer = [&](int lz, bool own_z, T l, T m, bool ok) {
+    const int lo = lz & 1, hi = (lz + 1) & 1;
+    {
+      const int ly = vly, lx = vlx;
+      T (*out)[kVY][kVX] = ss[lz & 1];
+      const int ux = vux, uy = vuy;
+      if (!ok) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) out[q][ly][lx] = T(0);
+        return;
+      }
+      T d[8][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ref = su[lo][c][ly][lx];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+          d[cc][c] = cc == 0 ? T(0) : (T)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
+        }
+      }
+      const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
+      T vs[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        T G[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) G[r][q] = T(0);
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+          if (((cx + cy + cz) & 1) != t) continue;
+          const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            G[r][0] += sx * d[cc][r];
+            G[r][1] += sy * d[cc][r];
+            G[r][2] += sz * d[cc][r];
+          }
+        }
+        const T tr = G[0][0] + G[1][1] + G[2][2];
+        const T s00 = l * tr + T(2) * m * G[0][0];
+        const T s11 = l * tr + T(2) * m * G[1][1];
+        const T s22 = l * tr + T(2) * m * G[2][2];
+        const T s01 = m * (G[0][1] + G[1][0]);
+        const T s02 = m * (G[0][2] + G[2][0]);
+        const T s12 = m * (G[1][2] + G[2][1]);
+        out[t * 6 + 0][ly][lx] = s00;
+        out[t * 6 + 1][ly][lx] = s11;
+        out[t * 6 + 2][ly][lx] = s22;
+        out[t * 6 + 3][ly][lx] = s01;
+        out[t * 6 + 4][ly][lx] = s02;
+        out[t * 6 + 5][ly][lx] = s12;
+        if (own) {
+          // the voxel's two tetrahedra in T, added to the FP64 block sums once per voxel
+          vs[0] += s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
+          vs[1] += s00;
+          vs[2] += s11;
+          vs[3] += s22;
+          vs[4] += s12;
+          vs[5] += s02;
+          vs[6] += s01;
+        }
+      }
+      if (own)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) acc[1 + q] += 0.5 * (double)vs[q];
+    }
+  };
+  const int nlx = tid % kTX, nly = tid / kTX;
+  const bool nact = tid < kTX * kTY && x0 + nlx < Nx && y0 + nly < Ny;
+  TailIn<T> tin;
+  auto nodes = [&](int z) {
+    if (!nact) return;
+    const int lx = nlx, ly = nly;
+    const int i = x0 + lx, j = y0 + ly;
+    T F[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      // voxel (i - ax, j - ay, z - az): local voxel (lx + 1 - ax, ly + 1 - ay), layer z - az;
+      // the node is its corner (ax, ay, az), in tetrahedron T1 (even) or T2 (odd)
+      const int q0 = ((ax + ay + az) & 1) * 6, vy = ly + 1 - ay, vx = lx + 1 - ax;
+      T (*sv)[kVY][kVX] = ss[(z - az) & 1];
+      const T s00 = sv[q0 + 0][vy][vx], s11 = sv[q0 + 1][vy][vx], s22 = sv[q0 + 2][vy][vx];
+      const T s01 = sv[q0 + 3][vy][vx], s02 = sv[q0 + 4][vy][vx], s12 = sv[q0 + 5][vy][vx];
+      const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
+      F[0] += bxw * s00 + byw * s01 + bzw * s02;
+      F[1] += bxw * s01 + byw * s11 + bzw * s12;
+      F[2] += bxw * s02 + byw * s12 + bzw * s22;
+    }
+    const int xyz[3] = {i, j, z};
+    const T w2b = T(1 << bcount(g, xyz));
+    T p[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+    T kd[3] = {T(0), T(0), T(0)};
+    if (kd_used) {
+      const int zm = ring4(z - 1), z0 = ring4(z), zp = ring4(z + 1);
+      const int hx = lx + 1, hy = ly + 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T sxy = sdl[z0][c][hy - 1][hx - 1] + sdl[z0][c][hy - 1][hx + 1] + sdl[z0][c][hy + 1][hx - 1] +
+                      sdl[z0][c][hy + 1][hx + 1];
+        const T sxz = sdl[zm][c][hy][hx - 1] + sdl[zm][c][hy][hx + 1] + sdl[zp][c][hy][hx - 1] +
+                      sdl[zp][c][hy][hx + 1];
+        const T syz = sdl[zm][c][hy - 1][hx] + sdl[zm][c][hy + 1][hx] + sdl[zp][c][hy - 1][hx] +
+                      sdl[zp][c][hy + 1][hx];
+        kd[c] = T(g.st[c][0]) * sdl[z0][c][hy][hx] + T(g.st[c][1]) * sxy + T(g.st[c][2]) * sxz +
+                T(g.st[c][3]) * syz;
+      }
+    }
+    const long long node = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * z);
+    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
+  };
+
+  T lcur, mcur, lnext, mnext;
+  bool okcur, oknext;
+  fetch(zb - 1);
+  commit(zb - 1);
+  fetch(zb);
+  commit(zb);
+  fetch(zb + 1);
+  fetch_lm(zb - 1, lcur, mcur, okcur);
+  fetch_lm(zb, lnext, mnext, oknext);
+  __syncthreads();
+  layer(zb - 1, false, lcur, mcur, okcur);
+  __syncthreads();
+  // Per step, plane z + 1 is committed with no barrier before it: its u slot was last read
+  // by layer(z - 1), and its delta slot (four-plane ring) by nodes(z - 2), both before the
+  // barrier that follows layer(z - 1).  The stress slot written by layer(z) was last read by
+  // nodes(z - 1), which precedes the barrier before layer(z).
+  for (int z = zb; z < ze; ++z) {
+    commit(z + 1);
+    if (z + 2 <= ze) fetch(z + 2);
+    lcur = lnext;
+    mcur = mnext;
+    okcur = oknext;
+    if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
+    if (nact) {
+      const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
+      tail_load<T>(D, g.Nn, kd_used, il, pp, Rp, node, tin);
+    }
+    __syncthreads();
+    layer(z, true, lcur, mcur, okcur);
+    __syncthreads();
+    nodes(z);
+  }
+  block_sum<kPartStrideD>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+}
+
+// proj_P of the relations on several nodes (eq 14, eq 17) on p and on the quantities linear
+// in p (R, and the differences dR, dY): one wavefront per relation, one lane per support node.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st) {
+  if (st->done) return;
+  const long long r = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  if (r >= w.m) return;   // uniform over the wavefront
+  const int lane = threadIdx.x & 63;
+  const int c = w.comp[r];
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int slot = (il + 1) % 3;
+  const long long o0 = w.off[r];
+  const bool act = lane < w.off[r + 1] - o0;
+  long long node = 0;
+  double wa = 0.0, wb = 0.0, q = 0.0, scale = 1.0;
+  if (act) {
+    node = w.nodes[o0 + lane];
+    wa = w.wa[o0 + lane];
+    wb = w.wb[o0 + lane];
+    const int i = (int)(node % g.N[0]);
+    const long long t = node / g.N[0];
+    const int j = (int)(t % g.N[1]), k = (int)(t / g.N[1]);
+    T p[3];
+    double sn = 0.0, ms[6];
+    node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    const int xyz[3] = {i, j, k};
+    scale = (double)(1 << bcount(g, xyz));
+    q = (double)p[c] / scale;
+  }
+  const double num = wave_sum(wa * q), den = wave_sum(wa * wb), sb = wave_sum(wb);
+  const double f = num / den;
+  const double pnew = (q - wb * f) * scale;
+  const double pn = wave_sum(act ? pnew * pnew : 0.0);
+  if (act) {
+    const long long e = c * g.Nn + node;
+    const T sh = (T)(wb * f * scale);
+    D.p[par][e] = (T)pnew;
+    if (acvp && il >= 1) {
+      D.R[par][e] -= sh;
+      if (il >= 2) {
+        D.dR[slot][e] -= sh;
+        D.dY[slot][e] -= sh;
+      }
+    }
+  }
+  if (lane == 0) {
+    w.part[r] = pn;
+    w.react[r] = -f * sb;
+  }
+}
+
+// Gram matrix of the R differences and their products with R_i (accelerating iterations)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gram3(DeltaBufs<T> D, long long n3, DevState* st, double* __restrict__ gpart) {
+  __shared__ double sh[9 * 16];
+  if (st->done || !st->accel) return;
+  const T* Ri = D.R[st->it & 1];
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
+    const double a0 = D.dR[0][e], a1 = D.dR[1][e], a2 = D.dR[2][e], r = Ri[e];
+    acc[0] += a0 * a0; acc[1] += a0 * a1; acc[2] += a0 * a2;
+    acc[3] += a1 * a1; acc[4] += a1 * a2; acc[5] += a2 * a2;
+    acc[6] += a0 * r; acc[7] += a1 * r; acc[8] += a2 * r;
+  }
+  block_sum<9>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gpart[blockIdx.x * 9 + q] = acc[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* __restrict__ gpart, int nblk) {
+  __shared__ double sh[9 * 16];
+  if (st->done || !st->accel) return;
+  double acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] += gpart[b * 9 + q];
+  block_sum<9>(acc, sh);
+  if (threadIdx.x != 0) return;
+  double G[3][4] = {{acc[0], acc[1], acc[2], acc[6]}, {acc[1], acc[3], acc[4], acc[7]}, {acc[2], acc[4], acc[5], acc[8]}};
+  const double tr = G[0][0] + G[1][1] + G[2][2];
+  for (int a = 0; a < 3; ++a) G[a][a] += 1e-14 * tr / 3.0;
+  bool ok = true;
+  for (int col = 0; col < 3 && ok; ++col) {
+    int piv = col;
+    double best = fabs(G[col][col]);
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(G[r][col]) > best) {
+        best = fabs(G[r][col]);
+        piv = r;
+      }
+    if (!(best > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (piv != col)
+      for (int q = 0; q < 4; ++q) {
+        const double t = G[col][q];
+        G[col][q] = G[piv][q];
+        G[piv][q] = t;
+      }
+    for (int r = col + 1; r < 3; ++r) {
+      const double f = G[r][col] / G[col][col];
+      for (int q = col; q < 4; ++q) G[r][q] -= f * G[col][q];
+    }
+  }
+  double y[3] = {0, 0, 0};
+  if (ok) {
+    for (int r = 2; r >= 0; --r) {
+      double s = G[r][3];
+      for (int q = r + 1; q < 3; ++q) s -= G[r][q] * y[q];
+      y[r] = s / G[r][r];
+    }
+    ok = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  }
+  if (ok)
+    for (int a = 0; a < 3; ++a) st->gamma[a] = y[a];
+  st->accel_ok = ok ? 1 : 0;
+}
+
+// proj_U of the residual-form path on the FP64 displacement; the increment follows
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_d(Geo g, DeltaBufs<T> D, StrongDev s, WeakDev w, ContactDev ct,
+                                                   DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  // strong DOFs
+  if (e < s.m) {
+    const long long idx = s.comp[e] * g.Nn + s.node[e];
+    const double old = D.u[idx];
+    D.u[idx] = s.val[e];
+    D.delta[idx] = (T)((double)D.delta[idx] + (s.val[e] - old));
+  }
+  // contact nodes: radial projection onto the sphere
+  if (ct.on && e < ct.nface && ct.C[e]) {
+    int xyz[3];
+    xyz[ct.axis] = ct.side ? g.n[ct.axis] : 0;
+    xyz[ct.b1] = (int)(e % g.N[ct.b1]);
+    xyz[ct.b2] = (int)(e / g.N[ct.b1]);
+    const long long node = xyz[0] + (long long)g.N[0] * (xyz[1] + (long long)g.N[1] * xyz[2]);
+    double d[3], r2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      d[c] = xyz[c] + D.u[c * g.Nn + node] - ct.center[c];
+      r2 += d[c] * d[c];
+    }
+    const double rr = sqrt(r2);
+    for (int c = 0; c < 3; ++c) {
+      const long long idx = c * g.Nn + node;
+      const double nw = ct.center[c] + ct.radius * d[c] / rr - xyz[c];
+      D.delta[idx] = (T)((double)D.delta[idx] + (nw - D.u[idx]));
+      D.u[idx] = nw;
+    }
+  }
+}
+
+// proj_U of the relations (eq 11, eq 15) on the FP64 displacement, the increment follows
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_rel_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long r = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  if (r >= w.m) return;
+  const int lane = threadIdx.x & 63;
+  const long long o0 = w.off[r];
+  const bool act = lane < w.off[r + 1] - o0;
+  long long e = 0;
+  double wa = 0.0, wd = 0.0, v = 0.0;
+  if (act) {
+    e = w.comp[r] * g.Nn + w.nodes[o0 + lane];
+    wa = w.wa[o0 + lane];
+    wd = w.wd[o0 + lane];
+    v = D.u[e];
+  }
+  const double num = wave_sum(wa * v), den = wave_sum(wa * wd);
+  const double corr = (w.val[r] - num) / den;
+  if (act) {
+    D.u[e] = v + wd * corr;
+    D.delta[e] = (T)((double)D.delta[e] + wd * corr);
+  }
+}
+
+template <typename T>
+__global__ void k_advance(DevState* st) {
+  if (st->done) return;
+  st->it += 1;
+  st->i_local += 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, StrongDev s, double* out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= s.m) return;
+  const long long node = s.node[e];
+  const int i = (int)(node % g.N[0]);
+  const long long q = node / g.N[0];
+  const int j = (int)(q % g.N[1]), k = (int)(q / g.N[1]);
+  T p[3];
+  double sn = 0.0, ms[6];
+  node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  const int xyz[3] = {i, j, k};
+  out[e] = -(double)p[s.comp[e]] / (double)(1 << bcount(g, xyz));
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+TileGrid residual_tiles(const Geo& g);
+
+template <typename T>
+int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
+                          int nblk, hipStream_t s) {
+  const TileGrid tg = residual_tiles(g);
+  if (tg.tx > 0) {
+    nblk = tg.tx * tg.ty * tg.nseg;
+    hipLaunchKernelGGL(k_residual_dt<T>, dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+  } else {
+    hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+  }
+  return nblk;
+}
+
+template <typename T>
+void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w, DevState* st,
+                          const double* part, const double* wpart, int nblk, hipStream_t s) {
+  if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(rel_grid(w.m)), dim3(kBlock), 0, s, g, D, w, st);
+  launch_control(st, part, nblk, wpart, w.m, ct, kPartStrideD, s);
+}
+
+// Blocks of the tiled residual pass resident on the current device at once (blocks per CU
+// at the kernel's register and LDS use, times the CU count), queried once per device.
+static int residual_resident() {
+  static std::atomic<int> cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 512;
+  int r = cache[dev].load(std::memory_order_relaxed);
+  if (!r) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    r = per_cu * cus;
+    cache[dev].store(r, std::memory_order_relaxed);   // every thread computes the same value
+  }
+  return r;
+}
+
+// Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
+// segments, at most 2048 blocks (the partial-sum rows); tx = 0 when the node plane alone
+// needs more tiles than that.  A block marches its segment's planes plus two planes of
+// prologue, and the blocks run in rounds of the resident count, so the split taken is the
+// one with the fewest (rounds x planes per block); ties go to fewer segments.
+TileGrid residual_tiles(const Geo& g) {
+  TileGrid t{0, 0, 0, 0};
+  const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
+  if ((long long)tx * ty > 2048) return t;
+  const int Nz = g.N[2];
+  const int maxseg = std::max(1, std::min(Nz, 2048 / (tx * ty)));
+  const long long resident = residual_resident();
+  long long best = -1;
+  int bseg = Nz;
+  for (int ns = 1; ns <= maxseg; ++ns) {
+    const int seg = (Nz + ns - 1) / ns;
+    const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
+    const long long cost = (blocks + resident - 1) / resident * (seg + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      bseg = seg;
+    }
+  }
+  t.tx = tx;
+  t.ty = ty;
+  t.seg = bseg;
+  t.nseg = (Nz + bseg - 1) / bseg;
+  return t;
+}
+
+template <typename T>
+void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram3<T>, dim3(nblk), dim3(kBlock), 0, s, D, n3, st, gpart);
+  hipLaunchKernelGGL(k_alpha3, dim3(1), dim3(kBlock), 0, s, st, gpart, nblk);
+}
+
+template <typename T>
+void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, const WeakDev& w,
+                       const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s) {
+  long long m = sd.m;
+  if (ct.on && ct.nface > m) m = ct.nface;
+  if (m > 0) hipLaunchKernelGGL(k_proj_d<T>, dim3(grid_for(m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, w, ct, st, force);
+  if (w.m > 0) hipLaunchKernelGGL(k_proj_rel_d<T>, dim3(rel_grid(w.m)), dim3(kBlock), 0, s, g, D, w, st, force);
+  if (advance) hipLaunchKernelGGL(k_advance<T>, dim3(1), dim3(1), 0, s, st);
+}
+
+template <typename T>
+void launch_reactions_d(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, double* out, hipStream_t s) {
+  if (sd.m == 0) return;
+  hipLaunchKernelGGL(k_reactions_d<T>, dim3(grid_for(sd.m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, out);
+}
+
+template <typename T>
+void launch_weak_d_stage(const Geo& g, const DeltaBufs<T>& D, const WeakDev& w, DevState* st, hipStream_t s) {
+  if (w.m > 0) hipLaunchKernelGGL(k_weak_d<T>, dim3(rel_grid(w.m)), dim3(kBlock), 0, s, g, D, w, st);
+}
+
+template int launch_delta_residual<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, DevState*, double*,
+                                          int, hipStream_t);
+template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
+                                          DevState*, const double*, const double*, int, hipStream_t);
+template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
+template void launch_delta_proj<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, const WeakDev&,
+                                       const ContactDev&, DevState*, int, int, hipStream_t);
+template void launch_reactions_d<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, double*, hipStream_t);
+
+}  // namespace fftc

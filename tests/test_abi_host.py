@@ -78,7 +78,9 @@ def test_dirichlet_validation_and_bookkeeping():
 def test_average_sphere_solver_reference_validation():
     h = F.fftc_create((8, 8, 8))
     sup = np.stack(np.meshgrid([2, 3], [2, 3], [2, 3], indexing="ij"), -1).reshape(1, 8, 3)
-    assert _code(F.fftc_add_average, h, sup[:, :6], [0], [0.0]) == F.FFTC_E_ARG   # support of 6
+    assert _code(F.fftc_add_average, h, sup[:, :1], [0], [0.0]) == F.FFTC_E_ARG   # support of 1
+    big = np.stack(np.meshgrid(range(5), range(13), [0], indexing="ij"), -1).reshape(1, 65, 3)
+    assert _code(F.fftc_add_average, h, big, [0], [0.0]) == F.FFTC_E_ARG         # support of 65
     F.fftc_add_average(h, sup, [0], [0.01])
     assert _code(F.fftc_add_average, h, sup, [0], [0.02]) == F.FFTC_E_OVERLAP
     face = np.stack(np.meshgrid([5, 6], [5, 6], [8], indexing="ij"), -1).reshape(1, 4, 3)
@@ -92,6 +94,28 @@ def test_average_sphere_solver_reference_validation():
     assert _code(F.fftc_set_solver, h, 1e-6, 100, F.FFTC_ACV_P, 3) == F.FFTC_E_UNSUPPORTED
     assert _code(F.fftc_set_reference_factor, h, 0.0) == F.FFTC_E_ARG
     assert _code(F.fftc_set_reference, h, 1.0, -1.0) == F.FFTC_E_ARG
+    F.fftc_destroy(h)
+
+
+def test_smooth_condition_validation():
+    """Section 4.2.2: volume and surface nodes only; supports may not reach DOFs held at 0 or
+    other constraints."""
+    h = F.fftc_create((8, 8, 8))
+    bc = np.zeros((3, 3, 2), np.int8); bc[:, 2, 0] = 1          # bottom face fixed
+    F.fftc_set_bc(h, bc)
+    assert _code(F.fftc_add_smooth, h, [[0, 4, 8]], [2], [0.1]) == F.FFTC_E_UNSUPPORTED   # edge node
+    assert _code(F.fftc_add_smooth, h, [[4, 4, 1]], [0], [0.1]) == F.FFTC_E_BC            # reaches z = 0
+    assert _code(F.fftc_add_smooth, h, [[4, 4, 9]], [0], [0.1]) == F.FFTC_E_ARG           # out of range
+    F.fftc_add_smooth(h, [[4, 4, 4]], [2], [0.1])                 # volume node, 27 support nodes
+    F.fftc_add_smooth(h, [[4, 4, 8]], [2], [0.1])                 # surface node, 9 support nodes
+    assert _code(F.fftc_add_smooth, h, [[5, 5, 5]], [2], [0.1]) == F.FFTC_E_OVERLAP
+    F.fftc_add_smooth(h, [[5, 5, 5]], [1], [0.1])                 # other component: no overlap
+    assert _code(F.fftc_add_dirichlet, h, [[5, 4, 8]], [2], [0.0]) == F.FFTC_E_ARG        # DOF in a support
+    ns, nw = C.c_int64(), C.c_int64()
+    F.load().fftc_num_constraints(h, C.byref(ns), C.byref(nw))
+    assert nw.value == 3 and ns.value == 0
+    sz = C.c_size_t()
+    assert F.load().fftc_workspace_bytes(h, C.byref(sz)) == 0
     F.fftc_destroy(h)
 
 

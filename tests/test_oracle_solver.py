@@ -54,8 +54,8 @@ def test_fixed_point_equals_dense_kkt(case):
     uf = out["u"].reshape(3, -1)
     cons = s.cons
     assert np.abs(uf[cons.s_comp, cons.s_node] - cons.s_val).max() < 1e-15
-    for c, nodes, val, _ in cons.weak:
-        assert abs(uf[c, nodes].mean() - val) < 1e-15
+    for rel in cons.rel:
+        assert abs(uf[rel.comp, rel.nodes].mean() - rel.value) < 1e-15
 
 
 def test_uniaxial_strain_exact_linear_field():

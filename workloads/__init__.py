@@ -45,8 +45,19 @@ class Strong:
 
 @dataclass
 class Average:
-    """Kinematic relation: mean of u[comp] over a 4- or 8-node support = value (eq 10)."""
-    support: np.ndarray       # int64 node triples, shape [m, k, 3], k in {4, 8}
+    """Kinematic relation: mean of u[comp] over a k-node support = value (eq 10: the 8 corners
+    of a voxel or the 4 of a face; Section 4.2.3: the 44 nodes of a line of ten voxels)."""
+    support: np.ndarray       # int64 node triples, shape [m, k, 3], 2 <= k <= 64
+    comp: np.ndarray          # int8, shape [m]
+    value: np.ndarray         # float64, shape [m]
+    set_id: int = 0
+
+
+@dataclass
+class Smooth:
+    """Smoothly applied condition: u[comp] at node = value, reaction spread over the
+    neighbouring nodes with the weights of Table 2 (Section 4.2.2, eq 15-17)."""
+    node: np.ndarray          # int64 (i, j, k) triples, shape [m, 3]
     comp: np.ndarray          # int8, shape [m]
     value: np.ndarray         # float64, shape [m]
     set_id: int = 0
@@ -69,6 +80,7 @@ class Problem:
     bc: np.ndarray            # int8 [3, 3, 2]
     strong: List[Strong] = field(default_factory=list)
     average: List[Average] = field(default_factory=list)
+    smooth: List[Smooth] = field(default_factory=list)
     sphere: Optional[Sphere] = None
     r0_factor: float = 1.0    # reference medium = factor * (max lambda, max mu)
     tol: float = 1e-6
