@@ -152,6 +152,18 @@ int fftc_workspace_bytes(fftc_h h, size_t* bytes);
  * NULL = default stream).  Uploads tables and constraints.  FFTC_E_WORKSPACE if small. */
 int fftc_bind_workspace(fftc_h h, void* ws_dev, size_t bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fftc_bind_workspace on a workspace the
+ * library holds itself, one array of FFTC_STATIC_WORKSPACE_BYTES per device, kept until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and times no block sizes: every transform pass takes its larger block.  All
+ * handles bound this way on one device share that device's array: a new binding replaces
+ * the previous one, whose later calls return FFTC_E_STATE, and calls on two such handles
+ * that overlap in time race.  Errors: FFTC_E_WORKSPACE (the problem needs more than
+ * FFTC_STATIC_WORKSPACE_BYTES, see fftc_workspace_bytes), FFTC_E_HIP. */
+#define FFTC_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+int fftc_bind_workspace_static(fftc_h h, void* stream);
+
 /* Per-voxel isotropic stiffness, FP64 device arrays [nz][ny][nx] (paper eq 1: sigma =
  * C : eps).  lam = mu = 0 marks void voxels.  Errors: FFTC_E_NAN (non-finite),
  * FFTC_E_ARG (mu < 0 or 3 lam + 2 mu < 0), FFTC_E_STATE (no workspace). */

@@ -59,6 +59,7 @@ _SIGS = {
     "fftc_set_solver": (C.c_int, [_P, C.POINTER(fftc_solver_cfg)]),
     "fftc_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "fftc_bind_workspace": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "fftc_bind_workspace_static": (C.c_int, [_P, _P]),
     "fftc_set_stiffness": (C.c_int, [_P, _P, _P]),
     "fftc_solve": (C.c_int, [_P, _P, C.c_int32, C.POINTER(fftc_report)]),
     "fftc_get_reactions": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -219,6 +220,13 @@ def fftc_workspace_bytes(h):
 def fftc_bind_workspace(h, ws, nbytes, stream):
     return _check(h, load().fftc_bind_workspace(h, _dev(ws), int(nbytes), C.c_void_p(stream)),
                   "fftc_bind_workspace")
+
+
+def fftc_bind_workspace_static(h, stream):
+    return _check(h, load().fftc_bind_workspace_static(h, C.c_void_p(stream)), "fftc_bind_workspace_static")
+
+
+FFTC_STATIC_WORKSPACE_BYTES = 128 << 20
 
 
 def fftc_set_stiffness(h, lam_dev, mu_dev):
@@ -487,7 +495,7 @@ class Solver:
 
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
                  precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
-                 smooth=()):
+                 smooth=(), static_workspace=False):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -515,11 +523,15 @@ class Solver:
                         period=period, update_gate=gate)
         nbytes = fftc_workspace_bytes(self.h)
         self.device = torch.device(device)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.ws.data_ptr()) % 256
-        self.ws_view = self.ws[off:off + nbytes]
         self.stream = torch.cuda.current_stream(self.device)
-        fftc_bind_workspace(self.h, self.ws_view, nbytes, self.stream.cuda_stream)
+        if static_workspace:            # the library's own per-device workspace, no allocation
+            self.ws = self.ws_view = None
+            fftc_bind_workspace_static(self.h, self.stream.cuda_stream)
+        else:
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self.ws_view = self.ws[off:off + nbytes]
+            fftc_bind_workspace(self.h, self.ws_view, nbytes, self.stream.cuda_stream)
         lam_t = torch.as_tensor(np.ascontiguousarray(lam, np.float64), device=self.device)
         mu_t = torch.as_tensor(np.ascontiguousarray(mu, np.float64), device=self.device)
         self.stream.synchronize()

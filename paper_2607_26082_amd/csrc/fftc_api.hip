@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -15,6 +16,12 @@
 #include "fftc_nn_internal.h"
 
 using namespace fftc;
+
+// Device workspace of fftc_bind_workspace_static: one array per device, for callers that
+// cannot allocate device memory.
+constexpr size_t kStaticWsBytes = FFTC_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
 
 struct fftc_problem {
   int n[3] = {0, 0, 0}, N[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
@@ -48,7 +55,9 @@ struct fftc_problem {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   int bound = 0, stiff_set = 0;
-  void* fld[10];  // u, X, S0..3, R0..3
+  void* fld[10] = {};  // u, X, S0..3, R0..3 (FP32 carves S, R only for ACV_U)
+  int nlit = 10;       // literal fields carved at binding
+  int static_dev = -1; // device whose static workspace is bound, else -1
   // residual-form (FP32) fields: delta, e, p0, p1, R0, R1, dR0..2, dY0..2, t; FP64 u
   void* dfld[13] = {};
   double* u64 = nullptr;
@@ -191,7 +200,10 @@ size_t carve(fftc_problem* h, char* base) {
   const size_t f3 = ts * 3 * (size_t)h->Nn;
   size_t off[64];
   int q = 0;
-  for (int i = 0; i < 10; ++i) off[q++] = L.take(f3);
+  // the FP32 residual-form iteration keeps its own fields; its literal form (ACV_U) and the
+  // stage entry points need u and p~, the Anderson rings only for ACV_U
+  const int nlit = (h->precision == FFTC_FP64 || h->cfg.acv == FFTC_ACV_U) ? 10 : 2;
+  for (int i = 0; i < nlit; ++i) off[q++] = L.take(f3);
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take((size_t)h->Nn);
@@ -233,7 +245,8 @@ size_t carve(fftc_problem* h, char* base) {
   if (nd) off[q++] = L.take(8 * 3 * (size_t)h->Nn);
   if (base) {
     q = 0;
-    for (int i = 0; i < 10; ++i) h->fld[i] = base + off[q++];
+    h->nlit = nlit;
+    for (int i = 0; i < 10; ++i) h->fld[i] = i < nlit ? base + off[q++] : nullptr;
     h->lam = base + off[q++];
     h->mu = base + off[q++];
     h->mask = (uint8_t*)(base + off[q++]);
@@ -568,6 +581,8 @@ int init_delta(fftc_problem* h, const double* u_dev, int zero_start) {
 }
 
 int solve_init(fftc_problem* h, const double* u_dev, int zero_start) {
+  if (h->precision == FFTC_FP32 && h->cfg.acv == FFTC_ACV_U && h->nlit < 10)
+    return fail(h, FFTC_E_STATE, "ACV_U in FP32 needs its Anderson fields: set it before binding the workspace");
   // FP32: residual-form iteration (FP64 displacement), except for ACV_U
   h->delta_mode = (h->precision == FFTC_FP32 && h->cfg.acv != FFTC_ACV_U) ? 1 : 0;
   if (h->delta_mode) return init_delta(h, u_dev, zero_start);
@@ -719,6 +734,21 @@ int stage_green_t(fftc_problem* h, const double* ptil_dev, double* u_dev) {
   return FFTC_OK;
 }
 
+// ---- static workspace (fftc_bind_workspace_static) ----
+// One array per device, in this file: its device address comes from hipGetSymbolAddress
+// (the array's name is only a host-side stand-in), looked up on the first static binding
+// on each device with that device current.  Handles bound to it on one device share it: a
+// new binding unbinds the previous one, whose later calls then report FFTC_E_STATE.
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+fftc_problem* g_static_owner[kMaxDevices] = {};
+
+void release_static(fftc_problem* h) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (h->static_dev >= 0 && g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
+  h->static_dev = -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -755,7 +785,11 @@ int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision) {
   return FFTC_OK;
 }
 
-void fftc_destroy(fftc_h h) { delete h; }
+void fftc_destroy(fftc_h h) {
+  if (!h) return;
+  release_static(h);
+  delete h;
+}
 
 int fftc_set_bc(fftc_h h, const int8_t* bc) {
   if (!h || !bc) return FFTC_E_ARG;
@@ -967,6 +1001,8 @@ int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg) {
   if (cfg->depth != 4) return fail(h, FFTC_E_UNSUPPORTED, "Anderson depth must be 4");
   if (cfg->period < 1 || cfg->max_iter < 0 || !(cfg->tol >= 0.0) || cfg->acv < 0 || cfg->acv > 2)
     return fail(h, FFTC_E_ARG, "invalid solver settings");
+  if (h->bound && cfg->acv == FFTC_ACV_U && h->nlit < 10)
+    return fail(h, FFTC_E_STATE, "ACV_U in FP32 needs its Anderson fields: set it before binding the workspace");
   h->cfg = *cfg;
   return FFTC_OK;
 }
@@ -977,7 +1013,10 @@ int fftc_workspace_bytes(fftc_h h, size_t* bytes) {
   return FFTC_OK;
 }
 
-int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
+namespace {
+// Binds ws to h: carves the fields, uploads tables and constraints, and (tune) times the two
+// block sizes of every transform pass; without tuning every pass takes the larger block.
+int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   if (!h || !ws) return FFTC_E_ARG;
   if (((uintptr_t)ws) % kAlign) return fail(h, FFTC_E_WORKSPACE, "workspace must be 256-byte aligned");
   const size_t need = carve(h, nullptr);
@@ -1102,7 +1141,9 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
   }
   h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
   // autotune the block size of each axis pass: time both variants on the bound buffers
-  {
+  if (!tune) {
+    for (int J = 0; J < 3; ++J) h->dtt_nt[J] = h->precision == FFTC_FP64 ? 256 : 512;
+  } else {
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
@@ -1134,13 +1175,54 @@ int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
   (void)residual_tiles(h->g);   // occupancy query of the residual pass, outside any capture
   if (h->nblk_res >= 8) h->nblk_res -= h->nblk_res % 8;   // whole slabs per XCD
   if (h->nblk_res < 1) h->nblk_res = 1;
-  for (int q = 0; q < 10; ++q)
+  for (int q = 0; q < h->nlit; ++q)
     HIPCHK(h, hipMemsetAsync(h->fld[q], 0, (h->precision == FFTC_FP64 ? 8 : 4) * 3 * (size_t)h->Nn, s));
   HIPCHK(h, hipStreamSynchronize(s));
   h->bound = 1;
   h->stiff_set = 0;
   if (h->ref_mode == 1) set_stencil(h);
   return FFTC_OK;
+}
+
+}  // namespace
+
+int fftc_bind_workspace(fftc_h h, void* ws, size_t bytes, void* stream) {
+  if (!h) return FFTC_E_ARG;
+  release_static(h);
+  return bind_impl(h, ws, bytes, stream, true);
+}
+
+int fftc_bind_workspace_static(fftc_h h, void* stream) {
+  if (!h) return FFTC_E_ARG;
+  const size_t need = carve(h, nullptr);
+  if (need > kStaticWsBytes)
+    return fail(h, FFTC_E_WORKSPACE, "problem needs " + std::to_string(need) + " bytes of workspace, the static "
+                                     "workspace holds " + std::to_string(kStaticWsBytes));
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, FFTC_E_UNSUPPORTED, "device index beyond the static table");
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) return fail(h, FFTC_E_HIP, std::string("HIP: ") + hipGetErrorString(e));
+      g_static_ptr[dev] = ptr;
+    }
+    ptr = g_static_ptr[dev];
+    fftc_problem* prev = g_static_owner[dev];
+    if (prev && prev != h) {   // its fields are about to be overwritten
+      prev->bound = 0;
+      prev->stiff_set = 0;
+      prev->static_dev = -1;
+      prev->err = "the static workspace was bound to another problem";
+    }
+    g_static_owner[dev] = h;
+  }
+  h->static_dev = dev;
+  const int rc = bind_impl(h, ptr, kStaticWsBytes, stream, false);
+  if (rc != FFTC_OK) release_static(h);
+  return rc;
 }
 
 int fftc_set_stiffness(fftc_h h, const double* lam, const double* mu) {
