@@ -142,6 +142,16 @@ int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node_host, const int8_t*
  * contact node.  Errors: FFTC_E_ARG (radius <= 0, face out of range, periodic axis). */
 int fftc_set_sphere(fftc_h h, const double center_host[3], double radius, int32_t face);
 
+/* Kinematics of the behaviour law (Section 5.2, eq 29, Algorithm 3).  FFTC_SMALL_STRAIN (the
+ * default): sigma = C : eps.  FFTC_FINITE_STRAIN: the first Piola-Kirchhoff stress
+ * P = F S of the Saint-Venant-Kirchhoff law (Section 5.4: S = lam tr(E) I + 2 mu E,
+ * E = (F^T F - I)/2, F = I + grad u) replaces sigma in the residual, in the equilibrium
+ * measure (eq 5: ||P||), in the contact reactions and in mean_stress (<P>: xx, yy, zz, yz, xz,
+ * xy); the reference medium and the projections are unchanged.  Any time before a solve. */
+#define FFTC_SMALL_STRAIN 0
+#define FFTC_FINITE_STRAIN 1
+int fftc_set_kinematics(fftc_h h, int32_t kind);
+
 /* Solver settings; defaults {1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2}. */
 int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg);
 
@@ -202,6 +212,18 @@ int fftc_num_face_nodes(fftc_h h, int64_t* count);
 int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* ptil_dev,
                         double* sums_host);
 int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev);
+
+/* Stage entry of the FP32 iteration as it runs (the residual form of Algorithm 1: FP64
+ * displacement u, FP32 residual-sized fields): one residual pass plus the relation projections
+ * and the control step, on caller state.  In: u (FP64), delta = u_i - u_{i-1}, e = the last
+ * Green input minus K0 u_{i-1}, p_prev, R_prev (FP64 device node fields converted to FP32;
+ * NULL = zero), i_local = the Anderson index of the iteration (R is formed from 1 on, its
+ * differences from 2 on).  Out (FP64 device node fields, NULL to skip): p after proj_P,
+ * R = p + K0 delta - e, dR = R - R_prev, dY = p - p_prev + K0 delta (all 0 at DOFs held at 0),
+ * sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.  FP32 handles only (FFTC_E_UNSUPPORTED). */
+int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_dev, const double* e_dev,
+                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, double* p_dev,
+                             double* r_dev, double* dr_dev, double* dy_dev, double* sums_host);
 
 /* Batched form: many independent cells (each a fully set-up, bound handle, possibly of
  * different sizes, boundary tables and precisions) iterated together.  A few iterations

@@ -1,4 +1,5 @@
-"""Algorithm 2: small-strain frictionless contact with a rigid sphere (active set).
+"""Algorithm 2: small-strain frictionless contact with a rigid sphere (active set), and
+Algorithm 3: the same with the finite-strain stress (finite_strain=True).
 
 Paper, Section 5.1, eq (24)-(28) and Algorithm 2.  For one load increment:
 start from the previous displacement, move the sphere, set the active zone C
@@ -21,6 +22,9 @@ Readings:
    inequalities g < 0 and f_nc > 0.
  * The residual is tested after the contact projection; the loop ends when
    it is below tol and V_gap and V_react are both empty.
+ * Finite strain (Section 5.2, eq 29, Algorithm 3): PK1 of the Saint-Venant-Kirchhoff law
+   replaces sigma in the residual, in f_nc = -2^-b div(PK1).n_c and in the force
+   F = -A0 <PK1_aa> (Section 5.4); contact geometry and projections are unchanged.
 Parity against the paper's iteration counts: unpinned.
 """
 from __future__ import annotations
@@ -33,8 +37,8 @@ from .solver import Anderson, Solver
 
 class ContactSolver(Solver):
     def __init__(self, n, lam, mu, bc, face, radius, strong=(), average=(), r0_factor=5.0,
-                 lam0=None, mu0=None):
-        super().__init__(n, lam, mu, bc, strong, average, r0_factor, lam0, mu0)
+                 lam0=None, mu0=None, finite_strain=False):
+        super().__init__(n, lam, mu, bc, strong, average, r0_factor, lam0, mu0, finite_strain=finite_strain)
         self.radius = float(radius)
         axis, side = divmod(int(face), 2)
         Nx, Ny, Nz = self.plan.N

@@ -126,7 +126,8 @@ class Constraints:
 
 
 class Solver:
-    def __init__(self, n, lam, mu, bc, strong=(), average=(), r0_factor=1.0, lam0=None, mu0=None, smooth=()):
+    def __init__(self, n, lam, mu, bc, strong=(), average=(), r0_factor=1.0, lam0=None, mu0=None, smooth=(),
+                 finite_strain=False):
         self.plan = Plan(n, bc)
         self.lam = np.asarray(lam, np.float64)
         self.mu = np.asarray(mu, np.float64)
@@ -135,22 +136,27 @@ class Solver:
         self.lam0, self.mu0 = lam0, mu0
         self.green = Green(self.plan, lam0, mu0)
         self.cons = Constraints(self.plan, strong, average, smooth)
+        self.finite_strain = bool(finite_strain)
         self.nsets = 1 + max([s.set_id for s in strong] + [a.set_id for a in average] +
                              [m.set_id for m in smooth] + [0])
 
     @classmethod
     def from_problem(cls, prob):
         return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.r0_factor,
-                   smooth=prob.smooth)
+                   smooth=prob.smooth, finite_strain=prob.finite_strain)
 
     def zeros(self):
         return np.zeros((3,) + tuple(self.plan.N[J] for J in (2, 1, 0)))
 
     # -- stages -----------------------------------------------------------
     def stress_residual(self, u):
-        """Stress and divergence: boundary-weighted p = 2^b div_D(sigma) (A-DOFs 0), sigma, ||sigma||^2."""
+        """Stress and divergence: boundary-weighted p = 2^b div_D(sigma) (A-DOFs 0), sigma, ||sigma||^2.
+        Finite strain (Algorithm 3, lines 10-11): sigma is PK1 of the Saint-Venant-Kirchhoff law."""
         G = tetra2.tet_gradients(u, self.plan)
-        sig = tetra2.stress(G, self.lam, self.mu)
+        if self.finite_strain:
+            sig = tetra2.stress_svk(G, self.lam, self.mu)
+        else:
+            sig = tetra2.stress(G, self.lam, self.mu)
         p = self.plan.w2b[None] * tetra2.divergence(sig, self.plan)
         p[self.plan.amask] = 0.0
         return p, sig, tetra2.stress_norm2(sig), G

@@ -125,6 +125,34 @@ def stress(G, lam, mu):
     return sig
 
 
+def stress_svk(G, lam, mu):
+    """Finite strain (Section 5.2, eq 29; the example law of Section 5.4): first Piola-Kirchhoff
+    stress PK1 = F S of the Saint-Venant-Kirchhoff law at each IP, with F = I + grad u,
+    Green-Lagrange strain E = (F^T F - I) / 2 and S = lam tr(E) I + 2 mu E.
+    Returns the non-symmetric PK1[t][i][J] (row i: component, column J: material direction),
+    the layout `divergence` takes."""
+    I = np.eye(3)[None, :, :, None, None, None]
+    F = I + G
+    E = 0.5 * (np.einsum("tkaxyz,tkbxyz->tabxyz", F, F) - I)
+    tr = E[:, 0, 0] + E[:, 1, 1] + E[:, 2, 2]
+    S = 2.0 * mu[None, None, None] * E
+    for i in range(3):
+        S[:, i, i] += lam[None] * tr
+    return np.einsum("tikxyz,tkjxyz->tijxyz", F, S)
+
+
+def svk_energy(G, lam, mu):
+    """Stored energy of the Saint-Venant-Kirchhoff law summed over voxels and both IPs with
+    weight 1/2: W = sum (1/2) (lam/2 tr(E)^2 + mu E:E).  Its derivative with respect to the
+    nodal displacements is minus the nodal force of PK1 (used to pin stress_svk)."""
+    I = np.eye(3)[None, :, :, None, None, None]
+    F = I + G
+    E = 0.5 * (np.einsum("tkaxyz,tkbxyz->tabxyz", F, F) - I)
+    tr = E[:, 0, 0] + E[:, 1, 1] + E[:, 2, 2]
+    w = 0.5 * lam[None] * tr ** 2 + mu[None] * np.sum(E * E, axis=(1, 2))
+    return float(IP_WEIGHT * np.sum(w))
+
+
 def paux(G, lam0, mu0):
     """Reference-medium flux of Paux et al. (Section 3.2.3): R0:grad u = lam0 (grad u o I) + 2 mu0 grad u,
     with o the entrywise product, on the full (non-symmetric) gradient."""
@@ -135,7 +163,8 @@ def paux(G, lam0, mu0):
 
 
 def stress_norm2(sig):
-    """sum over voxels and IPs of (1/2) sigma:sigma (h = 1)."""
+    """sum over voxels and IPs of (1/2) sigma:sigma (h = 1); the same measure of PK1 in the
+    finite-strain form (all nine components)."""
     return float(IP_WEIGHT * np.sum(sig * sig))
 
 

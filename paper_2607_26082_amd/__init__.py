@@ -57,6 +57,9 @@ _SIGS = {
     "fftc_set_sphere": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, C.c_int32]),
     "fftc_move_sphere": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "fftc_set_solver": (C.c_int, [_P, C.POINTER(fftc_solver_cfg)]),
+    "fftc_set_kinematics": (C.c_int, [_P, C.c_int32]),
+    "fftc_stage_residual_form": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P,
+                                           C.POINTER(C.c_double)]),
     "fftc_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "fftc_bind_workspace": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "fftc_bind_workspace_static": (C.c_int, [_P, _P]),
@@ -206,6 +209,14 @@ def fftc_move_sphere(h, center):
     return _check(h, load().fftc_move_sphere(h, _ptr(c, C.c_double)), "fftc_move_sphere")
 
 
+FFTC_SMALL_STRAIN = 0
+FFTC_FINITE_STRAIN = 1
+
+
+def fftc_set_kinematics(h, kind):
+    return _check(h, load().fftc_set_kinematics(h, int(kind)), "fftc_set_kinematics")
+
+
 def fftc_set_solver(h, tol=1e-6, max_iter=2000, acv=FFTC_ACV_P, depth=4, period=2, update_gate=1e-2):
     cfg = fftc_solver_cfg(float(tol), int(max_iter), int(acv), int(depth), int(period), float(update_gate))
     return _check(h, load().fftc_set_solver(h, C.byref(cfg)), "fftc_set_solver")
@@ -264,6 +275,16 @@ def fftc_stage_residual(h, u_dev, p_dev=None, ptil_dev=None):
     sums = np.zeros(2)
     _check(h, load().fftc_stage_residual(h, _dev(u_dev), _dev(p_dev), _dev(ptil_dev), _ptr(sums, C.c_double)),
            "fftc_stage_residual")
+    return sums
+
+
+def fftc_stage_residual_form(h, u_dev, delta_dev, e_dev, pprev_dev, rprev_dev, i_local, p_dev=None, r_dev=None,
+                             dr_dev=None, dy_dev=None):
+    sums = np.zeros(2)
+    _check(h, load().fftc_stage_residual_form(h, _dev(u_dev), _dev(delta_dev), _dev(e_dev), _dev(pprev_dev),
+                                              _dev(rprev_dev), int(i_local), _dev(p_dev), _dev(r_dev),
+                                              _dev(dr_dev), _dev(dy_dev), _ptr(sums, C.c_double)),
+           "fftc_stage_residual_form")
     return sums
 
 
@@ -495,7 +516,7 @@ class Solver:
 
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
                  precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
-                 smooth=(), static_workspace=False):
+                 smooth=(), static_workspace=False, finite_strain=False):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -518,6 +539,8 @@ class Solver:
         if sphere is not None:
             fftc_set_sphere(self.h, sphere.center, sphere.radius, sphere.face)
         fftc_set_reference_factor(self.h, r0_factor)
+        if finite_strain:
+            fftc_set_kinematics(self.h, FFTC_FINITE_STRAIN)
         fftc_set_solver(self.h, tol=tol, max_iter=max_iter,
                         acv={"NONE": FFTC_ACV_NONE, "U": FFTC_ACV_U, "P": FFTC_ACV_P}[acv],
                         period=period, update_gate=gate)
@@ -545,7 +568,7 @@ class Solver:
         kw.setdefault("acv", prob.acv)
         kw.setdefault("period", prob.acv_period)
         return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.sphere,
-                   prob.r0_factor, precision=precision, smooth=prob.smooth, **kw)
+                   prob.r0_factor, precision=precision, smooth=prob.smooth, finite_strain=prob.finite_strain, **kw)
 
     def solve(self, zero_start=True):
         rc, rep = fftc_solve(self.h, self.u, zero_start)
@@ -578,6 +601,15 @@ class Solver:
         p = t.empty_like(u_t); pt = t.empty_like(u_t)
         sums = fftc_stage_residual(self.h, u_t, p, pt)
         return p.cpu().numpy(), pt.cpu().numpy(), sums
+
+    def stage_residual_form(self, u, delta, e, p_prev, R_prev, i_local):
+        """The FP32 iteration's residual pass on given state: (p, R, dR, dY, sums) as numpy."""
+        t = self.torch
+        dev = [t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+               for a in (u, delta, e, p_prev, R_prev)]
+        outs = [t.empty_like(dev[0]) for _ in range(4)]
+        sums = fftc_stage_residual_form(self.h, *dev, i_local, *outs)
+        return tuple(o.cpu().numpy() for o in outs) + (sums,)
 
     def stage_green(self, ptil):
         t = self.torch

@@ -26,6 +26,7 @@ static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
 struct fftc_problem {
   int n[3] = {0, 0, 0}, N[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
   int precision = FFTC_FP64;
+  int fs = 0;   // FFTC_FINITE_STRAIN
   long long Nn = 0, Nv = 0;
   int8_t bc[18];
   int type[3][3];
@@ -722,6 +723,60 @@ int stage_residual_t(fftc_problem* h, const double* u_dev, double* p_dev, double
   return FFTC_OK;
 }
 
+// One residual pass of the FP32 residual-form iteration on caller state (iteration 0 of the
+// ping-pong, local Anderson index il): u (FP64), delta, e, p_prev, R_prev in, p, R, dR, dY
+// out (FP64 copies), sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.
+int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, double* const* out, double* sums) {
+  DeltaBufs<float> D = dbufs(h);
+  hipStream_t s = h->stream;
+  const long long n3 = 3 * h->Nn;
+  const int slot = (il + 1) % 3;
+  HIPCHK(h, hipMemcpyAsync(D.u, in[0], 8 * n3, hipMemcpyDeviceToDevice, s));
+  float* dst[4] = {D.delta, D.e, D.p[1], D.R[1]};
+  for (int q = 0; q < 4; ++q) {
+    if (in[q + 1]) launch_convert<double, float>(in[q + 1], dst[q], n3, s);
+    else HIPCHK(h, hipMemsetAsync(dst[q], 0, 4 * n3, s));
+  }
+  for (int q = 0; q < 3; ++q) {
+    HIPCHK(h, hipMemsetAsync(D.dR[q], 0, 4 * n3, s));
+    HIPCHK(h, hipMemsetAsync(D.dY[q], 0, 4 * n3, s));
+  }
+  DevState hs{};
+  hs.acv = FFTC_ACV_P;
+  hs.i_local = il;
+  hs.it = 0;
+  hs.tol = 0.0;
+  hs.max_iter = 1 << 30;
+  hs.period = h->cfg.period;
+  hs.gate = h->cfg.update_gate;
+  hs.contact = h->has_sphere;
+  HIPCHK(h, hipMemcpyAsync(h->st, &hs, sizeof(DevState), hipMemcpyHostToDevice, s));
+  const ContactDev ct = contact_dev(h);
+  const WeakDev w = weak_dev(h);
+  if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, s);
+  launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
+  const float* src[4] = {D.p[0], D.R[0], D.dR[slot], D.dY[slot]};
+  for (int q = 0; q < 4; ++q)
+    if (out[q]) launch_convert<float, double>(src[q], out[q], n3, s);
+  if (sums) {
+    std::vector<double> part((size_t)nres * kPartStrideD), wp(w.m + 1);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->part, 8 * part.size(), hipMemcpyDeviceToHost, s));
+    if (w.m) HIPCHK(h, hipMemcpyAsync(wp.data(), h->wpart, 8 * w.m, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    double a0 = 0, a1 = 0;
+    for (int b = 0; b < nres; ++b) {
+      a0 += part[(size_t)b * kPartStrideD + 0];
+      a1 += part[(size_t)b * kPartStrideD + 1];
+    }
+    for (long long r = 0; r < w.m; ++r) a0 += wp[r];
+    sums[0] = a0;
+    sums[1] = a1;
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  return FFTC_OK;
+}
+
 template <typename T>
 int stage_green_t(fftc_problem* h, const double* ptil_dev, double* u_dev) {
   Bufs<T> B = bufs<T>(h);
@@ -996,6 +1051,14 @@ int fftc_move_sphere(fftc_h h, const double center[3]) {
   return FFTC_OK;
 }
 
+int fftc_set_kinematics(fftc_h h, int32_t kind) {
+  if (!h) return FFTC_E_ARG;
+  if (kind != FFTC_SMALL_STRAIN && kind != FFTC_FINITE_STRAIN) return fail(h, FFTC_E_ARG, "unknown kinematics");
+  h->fs = kind == FFTC_FINITE_STRAIN;
+  h->g.fs = h->fs;
+  return FFTC_OK;
+}
+
 int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg) {
   if (!h || !cfg) return FFTC_E_ARG;
   if (cfg->depth != 4) return fail(h, FFTC_E_UNSUPPORTED, "Anderson depth must be 4");
@@ -1051,6 +1114,7 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   g.Nn = h->Nn;
   g.Nv = h->Nv;
   g.aface = h->aface;
+  g.fs = h->fs;
   // singular modes of each component: theta = 0 needs DCT1 or DFT on all axes; theta = pi
   // additionally needs an even length on DFT axes
   for (int c = 0; c < 3; ++c) {
@@ -1561,6 +1625,17 @@ int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* pt
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
   return h->precision == FFTC_FP64 ? stage_residual_t<double>(h, u_dev, p_dev, ptil_dev, sums)
                                    : stage_residual_t<float>(h, u_dev, p_dev, ptil_dev, sums);
+}
+
+int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_dev, const double* e_dev,
+                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, double* p_dev,
+                             double* r_dev, double* dr_dev, double* dy_dev, double* sums_host) {
+  if (!h || !u_dev || i_local < 0) return FFTC_E_ARG;
+  if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
+  if (h->precision != FFTC_FP32) return fail(h, FFTC_E_UNSUPPORTED, "the residual form is the FP32 iteration");
+  const double* in[5] = {u_dev, delta_dev, e_dev, pprev_dev, rprev_dev};
+  double* out[4] = {p_dev, r_dev, dr_dev, dy_dev};
+  return stage_residual_form_t(h, in, i_local, out, sums_host);
 }
 
 int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev) {

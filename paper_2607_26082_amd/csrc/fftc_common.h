@@ -76,6 +76,31 @@ static inline int grid_for(long long n, int cap) {
   return (int)(b < cap ? b : cap);
 }
 
+// First Piola-Kirchhoff stress of the Saint-Venant-Kirchhoff law (finite strain, Section 5.2,
+// eq 29; the law of Section 5.4) from the displacement gradient G (G[r][s] = d u_r / d x_s):
+// F = I + G, Green-Lagrange E = (G + G^T + G^T G) / 2, S = l tr(E) I + 2 m E, P = F S.
+template <typename T>
+__device__ __forceinline__ void svk_pk1(const T (&G)[3][3], T l, T m, T (&P)[3][3]) {
+  T E[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b) {
+      E[a][b] = T(0.5) * (G[a][b] + G[b][a] + G[0][a] * G[0][b] + G[1][a] * G[1][b] + G[2][a] * G[2][b]);
+      E[b][a] = E[a][b];
+    }
+  const T lt = l * (E[0][0] + E[1][1] + E[2][2]);
+  T S[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) S[a][b] = T(2) * m * E[a][b] + (a == b ? lt : T(0));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[i][j] = S[i][j] + G[i][0] * S[0][j] + G[i][1] * S[1][j] + G[i][2] * S[2][j];
+}
+
 // blocks of kBlock threads for one wavefront per relation
 static inline int rel_grid(long long m) { return (int)((m + (kBlock / 64) - 1) / (kBlock / 64)); }
 

@@ -41,6 +41,7 @@ struct Geo {
   // singular modes (symbol zero) per component: bit 0 theta = 0, bit 1 theta = (pi, pi, pi)
   int sing[3];
   double sing_scale[3];   // inverse-transform factor of one singular coefficient (prod 1/2n or 1/n)
+  int fs;                 // finite strain: Saint-Venant-Kirchhoff PK1 in place of the linear stress
 };
 
 // Device-resident iteration state (one per handle, in the workspace).

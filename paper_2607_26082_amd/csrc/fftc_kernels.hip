@@ -26,7 +26,7 @@ namespace fftc {
 // the symmetric extension of u.  Optionally the stress norm and mean-stress sums of
 // the tetrahedra owned by this node (T1 of voxel n, T2 of voxel n - e_x).
 // ---------------------------------------------------------------------------
-template <typename T, bool SIG>
+template <typename T, bool SIG, bool FS = false>
 __device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u, const T* __restrict__ lam,
                                           const T* __restrict__ mu, int i, int j, int k, T p[3], T k0[3],
                                           double& sn, double ms[6]) {
@@ -84,6 +84,26 @@ __device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u,
         G[r][2] += sz * nb[q][r];
       }
     }
+    // nodal force: (1/2 IP weight) * B_node^T sigma with B_node = (2a - 1)/2
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    if constexpr (FS) {
+      // finite strain: the non-symmetric PK1 stress, nodal force row r = B . P[r][:]
+      T P[3][3];
+      svk_pk1<T>(G, l, m, P);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) F[r] += bx * P[r][0] + by * P[r][1] + bz * P[r][2];
+      if (SIG && (a == 0 || a == 1)) {
+        double q = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q += (double)P[r][c] * (double)P[r][c];
+        sn += 0.5 * q;
+        ms[0] += 0.5 * (double)P[0][0]; ms[1] += 0.5 * (double)P[1][1]; ms[2] += 0.5 * (double)P[2][2];
+        ms[3] += 0.5 * (double)P[1][2]; ms[4] += 0.5 * (double)P[0][2]; ms[5] += 0.5 * (double)P[0][1];
+      }
+      continue;
+    }
     const T tr = G[0][0] + G[1][1] + G[2][2];
     const T s00 = l * tr + T(2) * m * G[0][0];
     const T s11 = l * tr + T(2) * m * G[1][1];
@@ -91,8 +111,6 @@ __device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u,
     const T s01 = m * (G[0][1] + G[1][0]);
     const T s02 = m * (G[0][2] + G[2][0]);
     const T s12 = m * (G[1][2] + G[2][1]);
-    // nodal force: (1/2 IP weight) * B_node^T sigma with B_node = (2a - 1)/2
-    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
     F[0] += bx * s00 + by * s01 + bz * s02;
     F[1] += bx * s01 + by * s11 + bz * s12;
     F[2] += bx * s02 + by * s12 + bz * s22;
@@ -122,7 +140,7 @@ __device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u,
 // ---------------------------------------------------------------------------
 // Residual pass
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool FS>
 __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, int force, int write_p) {
   __shared__ double sh[kPartStride * 16];
@@ -142,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDe
     const int k = r / Ny, j = r - k * Ny;
     T p[3], k0[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
-    node_eval<T, true>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+    node_eval<T, true, FS>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
     acc[1] += sn;
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
@@ -193,7 +211,8 @@ __device__ __forceinline__ void node_p(const Geo& g, const Bufs<T>& B, long long
   const int j = (int)(r % Ny), k = (int)(r / Ny);
   T k0[3];
   double sn = 0.0, ms[6];
-  node_eval<T, false>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+  if (g.fs) node_eval<T, false, true>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+  else node_eval<T, false, false>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
   const int xyz[3] = {i, j, k};
   b = bcount(g, xyz);
 }
@@ -667,7 +686,8 @@ __global__ void k_extend(DevState* st, int iters, double tol) {
 template <typename T>
 void launch_residual(const Geo& g, const Bufs<T>& B, const ContactDev& ct, DevState* st, double* part, int nblk,
                      int force, int write_p, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual<T>, dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+  if (g.fs) hipLaunchKernelGGL((k_residual<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+  else hipLaunchKernelGGL((k_residual<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
 }
 
 template <typename T>

@@ -41,7 +41,7 @@ __device__ __forceinline__ void stencil_k0(const Geo& g, const T* __restrict__ f
 
 // p = 2^b div_D(sigma) from an FP64 displacement: neighbour differences are formed in
 // FP64 and rounded once, the stress and divergence arithmetic is in T.
-template <typename T, bool SIG>
+template <typename T, bool SIG, bool FS = false>
 __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restrict__ u, const T* __restrict__ lam,
                                             const T* __restrict__ mu, int i, int j, int k, T p[3], double& sn,
                                             double ms[6]) {
@@ -101,6 +101,24 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
         G[r][2] += sz * nb[q][r];
       }
     }
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    if constexpr (FS) {
+      T P[3][3];
+      svk_pk1<T>(G, l, m, P);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) F[r] += bx * P[r][0] + by * P[r][1] + bz * P[r][2];
+      if (SIG && (a == 0 || a == 1)) {
+        double q = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) q += (double)P[r][c] * (double)P[r][c];
+        sn += 0.5 * q;
+        ms[0] += 0.5 * (double)P[0][0]; ms[1] += 0.5 * (double)P[1][1]; ms[2] += 0.5 * (double)P[2][2];
+        ms[3] += 0.5 * (double)P[1][2]; ms[4] += 0.5 * (double)P[0][2]; ms[5] += 0.5 * (double)P[0][1];
+      }
+      continue;
+    }
     const T tr = G[0][0] + G[1][1] + G[2][2];
     const T s00 = l * tr + T(2) * m * G[0][0];
     const T s11 = l * tr + T(2) * m * G[1][1];
@@ -108,7 +126,6 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
     const T s01 = m * (G[0][1] + G[1][0]);
     const T s02 = m * (G[0][2] + G[2][0]);
     const T s12 = m * (G[1][2] + G[2][1]);
-    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
     F[0] += bx * s00 + by * s01 + bz * s02;
     F[1] += bx * s01 + by * s11 + bz * s12;
     F[2] += bx * s02 + by * s12 + bz * s22;
@@ -212,6 +229,9 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long e = c * Nn + node;
+      // At a DOF held at 0 by a Dirichlet face p is 0 and K0 delta is taken from the
+      // symmetric image; the transforms drop these entries, but they stay in the Gram matrix
+      // of the differences (measured: zeroing them makes the FP32 least squares less robust).
       const T Ri = p[c] + kd[c] - tin.e[c];
       Rc[e] = Ri;
       if (il >= 2) {
@@ -222,7 +242,7 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
   }
 }
 
-template <typename T>
+template <typename T, bool FS>
 __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                        double* __restrict__ part) {
   __shared__ double sh[kPartStrideD * 16];
@@ -249,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     const int k = r / Ny, j = r - k * Ny;
     T p[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
-    node_eval_d<T, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    node_eval_d<T, true, FS>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
     acc[1] += sn;
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
@@ -283,12 +303,13 @@ constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
 // slot of node plane p in the four-plane ring of delta planes (p may be -1)
 __device__ __forceinline__ int ring4(int p) { return p & 3; }
 
-template <typename T>
+template <typename T, bool FS>
 __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, TileGrid tg) {
+  constexpr int NQ = FS ? 9 : 6;      // stored stress components per tetrahedron (PK1: all nine)
   __shared__ double su[2][3][kHY][kHX];
   __shared__ T sdl[4][3][kHY][kHX];
-  __shared__ T ss[2][12][kVY][kVX];   // stress component q of the voxels of a layer
+  __shared__ T ss[2][2 * NQ][kVY][kVX];   // stress component q of the voxels of a layer
   __shared__ double sh[kPartStrideD * 16];
   if (st->done) return;
   const int tid = threadIdx.x;
@@ -397,7 +418,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       const int ux = vux, uy = vuy;
       if (!ok) {
 #pragma unroll
-        for (int q = 0; q < 12; ++q) out[q][ly][lx] = T(0);
+        for (int q = 0; q < 2 * NQ; ++q) out[q][ly][lx] = T(0);
         return;
       }
       T d[8][3];
@@ -430,6 +451,27 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
             G[r][1] += sy * d[cc][r];
             G[r][2] += sz * d[cc][r];
           }
+        }
+        if constexpr (FS) {
+          T P[3][3];
+          svk_pk1<T>(G, l, m, P);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[t * 9 + r * 3 + c][ly][lx] = P[r][c];
+          if (own) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) vs[0] += P[r][c] * P[r][c];
+            vs[1] += P[0][0];
+            vs[2] += P[1][1];
+            vs[3] += P[2][2];
+            vs[4] += P[1][2];
+            vs[5] += P[0][2];
+            vs[6] += P[0][1];
+          }
+          continue;
         }
         const T tr = G[0][0] + G[1][1] + G[2][2];
         const T s00 = l * tr + T(2) * m * G[0][0];
@@ -473,11 +515,17 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       // voxel (i - ax, j - ay, z - az): local voxel (lx + 1 - ax, ly + 1 - ay), layer z - az;
       // the node is its corner (ax, ay, az), in tetrahedron T1 (even) or T2 (odd)
-      const int q0 = ((ax + ay + az) & 1) * 6, vy = ly + 1 - ay, vx = lx + 1 - ax;
+      const int q0 = ((ax + ay + az) & 1) * NQ, vy = ly + 1 - ay, vx = lx + 1 - ax;
       T (*sv)[kVY][kVX] = ss[(z - az) & 1];
+      const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
+      if constexpr (FS) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          F[r] += bxw * sv[q0 + 3 * r][vy][vx] + byw * sv[q0 + 3 * r + 1][vy][vx] + bzw * sv[q0 + 3 * r + 2][vy][vx];
+        continue;
+      }
       const T s00 = sv[q0 + 0][vy][vx], s11 = sv[q0 + 1][vy][vx], s22 = sv[q0 + 2][vy][vx];
       const T s01 = sv[q0 + 3][vy][vx], s02 = sv[q0 + 4][vy][vx], s12 = sv[q0 + 5][vy][vx];
-      const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
       F[0] += bxw * s00 + byw * s01 + bzw * s02;
       F[1] += bxw * s01 + byw * s11 + bzw * s12;
       F[2] += bxw * s02 + byw * s12 + bzw * s22;
@@ -569,7 +617,8 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
     const int j = (int)(t % g.N[1]), k = (int)(t / g.N[1]);
     T p[3];
     double sn = 0.0, ms[6];
-    node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    if (g.fs) node_eval_d<T, false, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    else node_eval_d<T, false, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
     const int xyz[3] = {i, j, k};
     scale = (double)(1 << bcount(g, xyz));
     q = (double)p[c] / scale;
@@ -746,7 +795,8 @@ __global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, S
   const int j = (int)(q % g.N[1]), k = (int)(q / g.N[1]);
   T p[3];
   double sn = 0.0, ms[6];
-  node_eval_d<T, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  if (g.fs) node_eval_d<T, false, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  else node_eval_d<T, false, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
   const int xyz[3] = {i, j, k};
   out[e] = -(double)p[s.comp[e]] / (double)(1 << bcount(g, xyz));
 }
@@ -762,9 +812,11 @@ int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
   const TileGrid tg = residual_tiles(g);
   if (tg.tx > 0) {
     nblk = tg.tx * tg.ty * tg.nseg;
-    hipLaunchKernelGGL(k_residual_dt<T>, dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    if (g.fs) hipLaunchKernelGGL((k_residual_dt<T, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else hipLaunchKernelGGL((k_residual_dt<T, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
   } else {
-    hipLaunchKernelGGL(k_residual_d<T>, dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+    if (g.fs) hipLaunchKernelGGL((k_residual_d<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+    else hipLaunchKernelGGL((k_residual_d<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
   }
   return nblk;
 }
@@ -785,7 +837,7 @@ static int residual_resident() {
   int r = cache[dev].load(std::memory_order_relaxed);
   if (!r) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;

@@ -1,0 +1,89 @@
+"""Node-by-node parity of the FP32 iteration's residual pass as it runs (the residual form: FP64
+displacement, FP32 residual-sized fields; tiled kernel, and its fallback for node planes wider
+than 2048 tiles) through fftc_stage_residual_form, against quantities formed from the oracle:
+p after proj_P (Algorithm 1), K0 delta = -2^b div_D(R0 : grad_D delta) (eq 3), R = p + K0 delta - e,
+dR = R - R_prev, dY = p - p_prev + K0 delta.  At DOFs held at 0 by a Dirichlet face p is 0 and the
+transforms drop the entries; R, dR, dY there are compared with K0 delta from the symmetric image,
+the stencil the pass applies (the oracle's reference term has no equation there)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import tetra2
+from oracle.solver import Solver as OSolver
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2607_26082_amd as F
+    F.load()
+    return F
+
+
+def _box(xs, ys, zs):
+    g = np.stack(np.meshgrid(np.asarray(xs), np.asarray(ys), np.asarray(zs), indexing="ij"), -1)
+    return g.reshape(-1, 3)
+
+
+# grids straddling the 31 x 7 node tiles of the tiled pass (ragged last tiles in x and y),
+# periodic axes, and a thin wide grid whose node plane needs more than 2048 tiles (fallback)
+SHAPES = [((40, 15, 9), None, False), ((30, 15, 6), 0, False), ((45, 20, 8), 1, False), ((32, 12, 10), 2, False),
+          ((40, 15, 9), None, True), ((30, 15, 6), 0, True), ((720, 720, 3), None, False)]
+
+
+def _case(seed, n, per):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    lam = rng.uniform(0.4, 2.5, (nz, ny, nx)); mu = rng.uniform(0.3, 1.8, (nz, ny, nx))
+    lam[0, 0, :3] = 0.0; mu[0, 0, :3] = 0.0
+    bc = rng.integers(0, 2, (3, 3, 2)).astype(np.int8)
+    bc[:, 2, 0] = W.BC_D
+    bc[0, 2, 1] = W.BC_N          # the strong DOF below sits on the top face
+    if per is not None:
+        bc[:, per, :] = W.BC_P
+    strong = [W.Strong(np.array([[2, 2, nz if per != 2 else nz - 1]]), np.array([0], np.int8), np.array([0.01]))]
+    avg = [W.Average(_box([4, 5], [3, 4], [1, 2])[None], np.array([1], np.int8), np.array([0.01]), set_id=1)]
+    return lam, mu, bc, strong, avg
+
+
+@pytest.mark.parametrize("idx", range(len(SHAPES)))
+@pytest.mark.parametrize("il", [0, 1, 3])
+def test_stage_residual_form(idx, il):
+    F = _lib()
+    n, per, fs = SHAPES[idx]
+    if n[0] == 720 and il != 3:
+        pytest.skip("the wide grid runs once (every output formed at il = 3)")
+    print(f"[residual form] n={n} periodic={per} finite_strain={fs} il={il}", flush=True)
+    lam, mu, bc, strong, avg = _case(70 + idx, n, per)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.3, finite_strain=fs)
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=1.3, precision="fp32", finite_strain=fs)
+    rng = np.random.default_rng(idx + 10 * il)
+    shape = o.zeros().shape
+    A = o.plan.amask
+    u = rng.standard_normal(shape) * (5e-2 if fs else 1e-2)
+    u[A] = 0.0
+    o.cons.proj_U(u)
+    fields = []
+    for sc in (1e-3, 2e-2, 2e-2, 2e-2):
+        f = rng.standard_normal(shape) * sc
+        f[A] = 0.0
+        fields.append(f)
+    delta, e, p_prev, R_prev = fields
+    p, R, dR, dY, sums = g.stage_residual_form(u, delta, e, p_prev, R_prev, il)
+    parts = o.iterate_parts(u)
+    k0d = -o.reference_term(tetra2.tet_gradients(delta, o.plan))
+    tol = 2e-5
+    pe = parts["p"]
+    assert np.abs(p - pe).max() <= tol * np.abs(pe).max()
+    assert abs(sums[0] - parts["pnorm2"]) <= 10 * tol * parts["pnorm2"]
+    assert abs(sums[1] - parts["sig2"]) <= 10 * tol * parts["sig2"]
+    if il >= 1:
+        Re = pe + k0d - e
+        free = ~A
+        assert np.abs(R - Re)[free].max() <= tol * np.abs(Re).max()
+        if il >= 2:
+            dRe = Re - R_prev
+            dYe = pe - p_prev + k0d
+            assert np.abs(dR - dRe)[free].max() <= tol * np.abs(dRe).max()
+            assert np.abs(dY - dYe)[free].max() <= tol * np.abs(dYe).max()

@@ -83,6 +83,7 @@ class Problem:
     smooth: List[Smooth] = field(default_factory=list)
     sphere: Optional[Sphere] = None
     r0_factor: float = 1.0    # reference medium = factor * (max lambda, max mu)
+    finite_strain: bool = False   # Saint-Venant-Kirchhoff PK1 instead of linear stress (Section 5.2)
     tol: float = 1e-6
     acv: str = "P"            # "NONE", "U" or "P"
     acv_period: int = 2
@@ -234,16 +235,18 @@ def c2_compact_tension(n=(256, 256, 16), notch_len=64, notch_h=4, radius=8.0, of
     return Problem("C2", n, lam, mu, bc, strong=sets, r0_factor=2.0, tol=1e-6)
 
 
-def c3_indentation(n=(256, 256, 128), R=96.0, d_over_R=0.002, E=1.0, nu=0.3):
-    """Block fixed at the bottom, traction-free elsewhere, rigid sphere on the top face."""
+def c3_indentation(n=(256, 256, 128), R=96.0, d_over_R=0.002, E=1.0, nu=0.3, finite_strain=False):
+    """Block fixed at the bottom, traction-free elsewhere, rigid sphere on the top face.
+    finite_strain: the Saint-Venant-Kirchhoff form of Algorithm 3 with the reference factor 10
+    that Section 5.4 uses for it (5 for small strain)."""
     nx, ny, nz = n
     lam, mu = lame(np.full((nz, ny, nx), E), nu)
     bc = bc_table(BC_N)
     bc[:, 2, 0] = BC_D
     d = d_over_R * R
     sph = Sphere(np.array([nx / 2.0, ny / 2.0, nz + R - d]), R, face=5)
-    return Problem("C3", n, lam, mu, bc, sphere=sph, r0_factor=5.0, tol=1e-6,
-                   meta={"E": E, "nu": nu, "d": d})
+    return Problem("C3", n, lam, mu, bc, sphere=sph, r0_factor=10.0 if finite_strain else 5.0, tol=1e-6,
+                   finite_strain=finite_strain, meta={"E": E, "nu": nu, "d": d})
 
 
 def random_cell(seed, n=None, edges=(32, 48, 64, 96, 128), with_patches=True):
