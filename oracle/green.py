@@ -20,9 +20,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import dtt
+from . import dtt, hex1, tetra2
 from .plan import Plan
-from .tetra2 import assemble_dense, element_tensor_paux
+from .tetra2 import element_tensor_paux
 
 
 def reference_from_factor(lam, mu, factor):
@@ -30,10 +30,11 @@ def reference_from_factor(lam, mu, factor):
     return factor * float(np.max(lam)), factor * float(np.max(mu))
 
 
-def stencil(lam0, mu0):
-    """Stencil {delta: coefficient} of each component of the assembled Paux K0."""
+def stencil(lam0, mu0, scheme="tetra2"):
+    """Stencil {delta: coefficient} of each component of the assembled Paux K0 of a scheme."""
     plan = Plan((4, 4, 4), np.full((3, 3, 2), 2, np.int8))       # 4^3 periodic
-    K = assemble_dense(plan, lambda *_: element_tensor_paux(lam0, mu0))
+    assemble = tetra2.assemble_dense if scheme == "tetra2" else hex1.assemble_dense
+    K = assemble(plan, lambda *_: element_tensor_paux(lam0, mu0))
     Nn = 64
     out = []
     for c in range(3):
@@ -89,9 +90,9 @@ def inverse_dt(coef, plan, c):
 
 
 class Green:
-    def __init__(self, plan, lam0, mu0):
+    def __init__(self, plan, lam0, mu0, scheme="tetra2"):
         self.plan = plan
-        st = stencil(lam0, mu0)
+        st = stencil(lam0, mu0, scheme)
         self.Minv = []
         for c in range(3):
             th = [dtt.thetas(plan.types[c][J], plan.n[J]) for J in range(3)]

@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import relations, tetra2
+from . import hex1, relations, tetra2
 from .green import Green, reference_from_factor
 from .plan import Plan
 
@@ -127,14 +127,20 @@ class Constraints:
 
 class Solver:
     def __init__(self, n, lam, mu, bc, strong=(), average=(), r0_factor=1.0, lam0=None, mu0=None, smooth=(),
-                 finite_strain=False):
+                 finite_strain=False, scheme="tetra2", reference="paux"):
         self.plan = Plan(n, bc)
         self.lam = np.asarray(lam, np.float64)
         self.mu = np.asarray(mu, np.float64)
         if lam0 is None:
             lam0, mu0 = reference_from_factor(self.lam, self.mu, r0_factor)
         self.lam0, self.mu0 = lam0, mu0
-        self.green = Green(self.plan, lam0, mu0)
+        self.scheme, self.reference = scheme, reference
+        if reference == "iso":
+            self.green = hex1.IsoGreenPeriodic(self.plan, lam0, mu0)
+            if scheme != "hex1":
+                raise ValueError("the isotropic reference medium is built for the HEX1 scheme")
+        else:
+            self.green = Green(self.plan, lam0, mu0, scheme)
         self.cons = Constraints(self.plan, strong, average, smooth)
         self.finite_strain = bool(finite_strain)
         self.nsets = 1 + max([s.set_id for s in strong] + [a.set_id for a in average] +
@@ -143,7 +149,8 @@ class Solver:
     @classmethod
     def from_problem(cls, prob):
         return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.r0_factor,
-                   smooth=prob.smooth, finite_strain=prob.finite_strain)
+                   smooth=prob.smooth, finite_strain=prob.finite_strain, scheme=prob.scheme,
+                   reference=prob.reference)
 
     def zeros(self):
         return np.zeros((3,) + tuple(self.plan.N[J] for J in (2, 1, 0)))
@@ -152,17 +159,30 @@ class Solver:
     def stress_residual(self, u):
         """Stress and divergence: boundary-weighted p = 2^b div_D(sigma) (A-DOFs 0), sigma, ||sigma||^2.
         Finite strain (Algorithm 3, lines 10-11): sigma is PK1 of the Saint-Venant-Kirchhoff law."""
-        G = tetra2.tet_gradients(u, self.plan)
+        if self.scheme == "hex1":
+            G = hex1.gradients(u, self.plan)
+        else:
+            G = tetra2.tet_gradients(u, self.plan)
         if self.finite_strain:
             sig = tetra2.stress_svk(G, self.lam, self.mu)
         else:
             sig = tetra2.stress(G, self.lam, self.mu)
-        p = self.plan.w2b[None] * tetra2.divergence(sig, self.plan)
+        if self.scheme == "hex1":
+            p = self.plan.w2b[None] * hex1.divergence(sig, self.plan)
+            s2 = hex1.stress_norm2(sig)
+        else:
+            p = self.plan.w2b[None] * tetra2.divergence(sig, self.plan)
+            s2 = tetra2.stress_norm2(sig)
         p[self.plan.amask] = 0.0
-        return p, sig, tetra2.stress_norm2(sig), G
+        return p, sig, s2, G
 
     def reference_term(self, G):
         """Reference-medium term: 2^b div_D(R0 : grad_D u) (A-DOFs 0)."""
+        if self.scheme == "hex1":
+            flux = hex1.iso(G, self.lam0, self.mu0) if self.reference == "iso" else tetra2.paux(G, self.lam0, self.mu0)
+            q = self.plan.w2b[None] * hex1.divergence(flux, self.plan)
+            q[self.plan.amask] = 0.0
+            return q
         q = self.plan.w2b[None] * tetra2.divergence(tetra2.paux(G, self.lam0, self.mu0), self.plan)
         q[self.plan.amask] = 0.0
         return q
@@ -225,7 +245,7 @@ class Solver:
         tot = self.cons.totals(parts["f_strong"], parts["f_weak"], self.nsets)
         out = dict(u=u, iterations=it, converged=converged, residual=hist[-1], totals=tot,
                    f_strong=parts["f_strong"], f_weak=parts["f_weak"],
-                   mean_stress=tetra2.mean_stress(parts["sig"]))
+                   mean_stress=(hex1 if self.scheme == "hex1" else tetra2).mean_stress(parts["sig"]))
         if history:
             out["history"] = np.array(hist)
         if snapshots:

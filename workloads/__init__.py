@@ -84,6 +84,8 @@ class Problem:
     sphere: Optional[Sphere] = None
     r0_factor: float = 1.0    # reference medium = factor * (max lambda, max mu)
     finite_strain: bool = False   # Saint-Venant-Kirchhoff PK1 instead of linear stress (Section 5.2)
+    scheme: str = "tetra2"        # discrete gradient: "tetra2" or "hex1" (Section 3.1.2)
+    reference: str = "paux"       # reference medium: "paux" or "iso" (isotropic; periodic cells)
     tol: float = 1e-6
     acv: str = "P"            # "NONE", "U" or "P"
     acv_period: int = 2
@@ -247,6 +249,36 @@ def c3_indentation(n=(256, 256, 128), R=96.0, d_over_R=0.002, E=1.0, nu=0.3, fin
     sph = Sphere(np.array([nx / 2.0, ny / 2.0, nz + R - d]), R, face=5)
     return Problem("C3", n, lam, mu, bc, sphere=sph, r0_factor=10.0 if finite_strain else 5.0, tol=1e-6,
                    finite_strain=finite_strain, meta={"E": E, "nu": nu, "d": d})
+
+
+def periodic_centrosymmetric(n=(6, 6, 6), seed=BASE_SEED + 7_000_000, scheme="hex1", reference="iso"):
+    """Cell periodic on all axes, stiffness symmetric under the point reflection x -> -x about
+    node 0, and voxel-average conditions in reflected pairs with opposite values, so that the
+    solution is odd: its mean and its (pi, pi, pi) coefficient vanish, the frequencies where
+    the Green operator is set to 0.  Two pairs of voxels, all three components."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+
+    def refl(f):
+        return f[::-1, ::-1, ::-1]
+
+    lam = rng.uniform(0.5, 2.0, (nz, ny, nx)); lam = 0.5 * (lam + refl(lam))
+    mu = rng.uniform(0.4, 1.5, (nz, ny, nx)); mu = 0.5 * (mu + refl(mu))
+
+    def vox(a, b, c):
+        return [[(a + i) % nx, (b + j) % ny, (c + k) % nz] for i in (0, 1) for j in (0, 1) for k in (0, 1)]
+
+    pairs = [((1, 1, 1), (0.02, -0.01, 0.015)), ((1, 3, 0), (-0.01, 0.02, 0.01))]
+    sup, comp, val = [], [], []
+    for (a, b, c), U in pairs:
+        r = ((-a - 1) % nx, (-b - 1) % ny, (-c - 1) % nz)
+        for cc in range(3):
+            sup.append(vox(a, b, c)); comp.append(cc); val.append(U[cc])
+            sup.append(vox(*r)); comp.append(cc); val.append(-U[cc])
+    avg = [Average(np.array(sup, np.int64), np.array(comp, np.int8), np.array(val))]
+    bc = np.full((3, 3, 2), BC_P, np.int8)
+    return Problem("periodic-odd", tuple(n), lam, mu, bc, average=avg, tol=1e-8, scheme=scheme,
+                   reference=reference)
 
 
 def random_cell(seed, n=None, edges=(32, 48, 64, 96, 128), with_patches=True):
