@@ -100,14 +100,30 @@ void fftc_destroy(fftc_h h);
  * faces of an axis for all components, else FFTC_E_BC.  Must precede constraints. */
 int fftc_set_bc(fftc_h h, const int8_t* bc_host);
 
-/* Reference medium of Paux et al. (Section 3.2.3): R0:grad u = lam0 (grad u o I) + 2 mu0 grad u.
- * Requires mu0 > 0 and lam0 + 2 mu0 > 0 (FFTC_E_ARG).  Default: max(lam), max(mu) of the
- * stiffness field. */
-int fftc_set_reference(fftc_h h, double lam0, double mu0);
+/* Reference medium R0 (Section 3.2.3, eq 3-4).  kind FFTC_REF_PAUX: the medium of Paux et
+ * al., R0 : grad u = lam0 (grad u o I) + 2 mu0 grad u, one diagonal symbol per component, any
+ * boundary table.  FFTC_REF_ISO: the isotropic medium lam0 tr(eps) I + 2 mu0 eps, whose symbol
+ * couples the three components (a 3x3 solve per frequency, complex coefficients over periodic
+ * axes, Section 3.2.4); it needs the HEX1 scheme, FP64 and all three axes periodic (checked
+ * at binding: FFTC_E_UNSUPPORTED).  Requires mu0 > 0 and lam0 + 2 mu0 > 0 (FFTC_E_ARG).  The
+ * kind is fixed at binding (FFTC_E_STATE afterwards).  Default: Paux, max(lam), max(mu). */
+#define FFTC_REF_PAUX 0
+#define FFTC_REF_ISO 1
+int fftc_set_reference(fftc_h h, int32_t kind, double lam0, double mu0);
 
 /* Reference medium as a multiple of the stiffness field: (lam0, mu0) = factor * (max lam,
- * max mu), evaluated by fftc_set_stiffness (the default, factor 1). */
-int fftc_set_reference_factor(fftc_h h, double factor);
+ * max mu), evaluated by fftc_set_stiffness (the default: Paux, factor 1). */
+int fftc_set_reference_factor(fftc_h h, int32_t kind, double factor);
+
+/* Discrete gradient (Section 3.1.2).  FFTC_TETRA2 (default): two tetrahedra per voxel, two
+ * integration points of weight 1/2.  FFTC_HEX1: the gradient of the trilinear interpolant at
+ * the voxel centre, one integration point of weight 1; its hourglass modes (zero centre
+ * gradient in every voxel) get no Green correction, and single-node conditions excite them
+ * (Section 4.2.3: use average relations).  HEX1 runs in FP64 and without contact
+ * (FFTC_E_UNSUPPORTED at binding otherwise).  Before binding (FFTC_E_STATE). */
+#define FFTC_TETRA2 0
+#define FFTC_HEX1 1
+int fftc_set_scheme(fftc_h h, int32_t scheme);
 
 /* Strong nodal constraints u[comp[k]](node[k]) = value[k] (Section 4.1, eq 8-9).
  * node_host: m triples (i, j, k).  set_id groups DOFs for reaction totals (0..63).

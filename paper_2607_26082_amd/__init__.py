@@ -46,8 +46,9 @@ _SIGS = {
     "fftc_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32]),
     "fftc_destroy": (None, [_P]),
     "fftc_set_bc": (C.c_int, [_P, C.POINTER(C.c_int8)]),
-    "fftc_set_reference": (C.c_int, [_P, C.c_double, C.c_double]),
-    "fftc_set_reference_factor": (C.c_int, [_P, C.c_double]),
+    "fftc_set_reference": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
+    "fftc_set_reference_factor": (C.c_int, [_P, C.c_int32, C.c_double]),
+    "fftc_set_scheme": (C.c_int, [_P, C.c_int32]),
     "fftc_add_dirichlet": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
                                      C.POINTER(C.c_double), C.c_int32]),
     "fftc_add_average": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
@@ -166,12 +167,20 @@ def fftc_set_bc(h, bc):
     return _check(h, load().fftc_set_bc(h, _ptr(a, C.c_int8)), "fftc_set_bc")
 
 
-def fftc_set_reference(h, lam0, mu0):
-    return _check(h, load().fftc_set_reference(h, float(lam0), float(mu0)), "fftc_set_reference")
+FFTC_REF_PAUX, FFTC_REF_ISO = 0, 1
+FFTC_TETRA2, FFTC_HEX1 = 0, 1
 
 
-def fftc_set_reference_factor(h, factor):
-    return _check(h, load().fftc_set_reference_factor(h, float(factor)), "fftc_set_reference_factor")
+def fftc_set_reference(h, lam0, mu0, kind=FFTC_REF_PAUX):
+    return _check(h, load().fftc_set_reference(h, int(kind), float(lam0), float(mu0)), "fftc_set_reference")
+
+
+def fftc_set_reference_factor(h, factor, kind=FFTC_REF_PAUX):
+    return _check(h, load().fftc_set_reference_factor(h, int(kind), float(factor)), "fftc_set_reference_factor")
+
+
+def fftc_set_scheme(h, scheme):
+    return _check(h, load().fftc_set_scheme(h, int(scheme)), "fftc_set_scheme")
 
 
 def fftc_add_dirichlet(h, node, comp, value, set_id=0):
@@ -516,7 +525,7 @@ class Solver:
 
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
                  precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
-                 smooth=(), static_workspace=False, finite_strain=False):
+                 smooth=(), static_workspace=False, finite_strain=False, scheme="tetra2", reference="paux"):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -538,7 +547,8 @@ class Solver:
             self.nsets = max(self.nsets, m.set_id + 1)
         if sphere is not None:
             fftc_set_sphere(self.h, sphere.center, sphere.radius, sphere.face)
-        fftc_set_reference_factor(self.h, r0_factor)
+        fftc_set_scheme(self.h, FFTC_HEX1 if scheme == "hex1" else FFTC_TETRA2)
+        fftc_set_reference_factor(self.h, r0_factor, FFTC_REF_ISO if reference == "iso" else FFTC_REF_PAUX)
         if finite_strain:
             fftc_set_kinematics(self.h, FFTC_FINITE_STRAIN)
         fftc_set_solver(self.h, tol=tol, max_iter=max_iter,
@@ -568,7 +578,8 @@ class Solver:
         kw.setdefault("acv", prob.acv)
         kw.setdefault("period", prob.acv_period)
         return cls(prob.n, prob.lam, prob.mu, prob.bc, prob.strong, prob.average, prob.sphere,
-                   prob.r0_factor, precision=precision, smooth=prob.smooth, finite_strain=prob.finite_strain, **kw)
+                   prob.r0_factor, precision=precision, smooth=prob.smooth, finite_strain=prob.finite_strain,
+                   scheme=prob.scheme, reference=prob.reference, **kw)
 
     def solve(self, zero_start=True):
         rc, rep = fftc_solve(self.h, self.u, zero_start)

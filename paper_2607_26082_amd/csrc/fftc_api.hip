@@ -33,6 +33,8 @@ struct fftc_problem {
   int aface = 0;
   double lam0 = 0, mu0 = 0, r0_factor = 1.0;
   int ref_mode = 0;  // 0 = factor of max stiffness, 1 = explicit
+  int ref_kind = FFTC_REF_PAUX;
+  int scheme = FFTC_TETRA2;
   // constraints
   std::vector<long long> s_node;
   std::vector<int8_t> s_comp;
@@ -284,6 +286,8 @@ size_t carve(fftc_problem* h, char* base) {
 }
 
 void set_stencil(fftc_problem* h) {
+  h->g.lam0 = h->lam0;
+  h->g.mu0 = h->mu0;
   for (int c = 0; c < 3; ++c) {
     double cj[3];
     for (int J = 0; J < 3; ++J) cj[J] = 2.0 * h->mu0 + (J == c ? h->lam0 : 0.0);
@@ -490,8 +494,17 @@ void enqueue_green(fftc_problem* h, int src, const T* in, int store_s, int force
   a = dtt_args<T>(h, 1, PASS_FWD, force);
   launch_dtt<T>(a, h->ept, h->stream);
   if (tm) tm->mark(h->stream);
-  a = dtt_args<T>(h, 2, PASS_FWD_GREEN_INV, force);
-  launch_dtt<T>(a, h->ept, h->stream);
+  if (h->g.iso) {
+    // coupled 3x3 Green solve between the forward and the inverse z transforms
+    if constexpr (sizeof(T) == 8) {
+      launch_dtt<T>(dtt_args<T>(h, 2, PASS_FWD, force), h->ept, h->stream);
+      launch_green_iso(h->g, (double*)h->fld[0], h->st, force, h->stream);
+      launch_dtt<T>(dtt_args<T>(h, 2, PASS_INV, force), h->ept, h->stream);
+    }
+  } else {
+    a = dtt_args<T>(h, 2, PASS_FWD_GREEN_INV, force);
+    launch_dtt<T>(a, h->ept, h->stream);
+  }
   if (tm) tm->mark(h->stream);
   a = dtt_args<T>(h, 1, PASS_INV, force);
   launch_dtt<T>(a, h->ept, h->stream);
@@ -863,10 +876,13 @@ int fftc_set_bc(fftc_h h, const int8_t* bc) {
   return FFTC_OK;
 }
 
-int fftc_set_reference(fftc_h h, double lam0, double mu0) {
+int fftc_set_reference(fftc_h h, int32_t kind, double lam0, double mu0) {
   if (!h) return FFTC_E_ARG;
+  if (kind != FFTC_REF_PAUX && kind != FFTC_REF_ISO) return fail(h, FFTC_E_ARG, "unknown reference medium");
   if (!(mu0 > 0.0) || !(lam0 + 2.0 * mu0 > 0.0) || !isfinite(lam0) || !isfinite(mu0))
     return fail(h, FFTC_E_ARG, "reference medium needs mu0 > 0 and lam0 + 2 mu0 > 0");
+  if (h->bound && kind != h->ref_kind) return fail(h, FFTC_E_STATE, "choose the reference medium before binding");
+  h->ref_kind = kind;
   h->lam0 = lam0;
   h->mu0 = mu0;
   h->ref_mode = 1;
@@ -874,11 +890,22 @@ int fftc_set_reference(fftc_h h, double lam0, double mu0) {
   return FFTC_OK;
 }
 
-int fftc_set_reference_factor(fftc_h h, double factor) {
+int fftc_set_reference_factor(fftc_h h, int32_t kind, double factor) {
   if (!h) return FFTC_E_ARG;
+  if (kind != FFTC_REF_PAUX && kind != FFTC_REF_ISO) return fail(h, FFTC_E_ARG, "unknown reference medium");
   if (!(factor > 0.0) || !isfinite(factor)) return fail(h, FFTC_E_ARG, "reference factor must be positive");
+  if (h->bound && kind != h->ref_kind) return fail(h, FFTC_E_STATE, "choose the reference medium before binding");
+  h->ref_kind = kind;
   h->r0_factor = factor;
   h->ref_mode = 0;
+  return FFTC_OK;
+}
+
+int fftc_set_scheme(fftc_h h, int32_t scheme) {
+  if (!h) return FFTC_E_ARG;
+  if (scheme != FFTC_TETRA2 && scheme != FFTC_HEX1) return fail(h, FFTC_E_ARG, "unknown scheme");
+  if (h->bound) return fail(h, FFTC_E_STATE, "choose the scheme before binding");
+  h->scheme = scheme;
   return FFTC_OK;
 }
 
@@ -1081,6 +1108,12 @@ namespace {
 // block sizes of every transform pass; without tuning every pass takes the larger block.
 int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   if (!h || !ws) return FFTC_E_ARG;
+  if (h->scheme == FFTC_HEX1 && h->precision != FFTC_FP64)
+    return fail(h, FFTC_E_UNSUPPORTED, "the HEX1 scheme runs in FP64 (its hourglass modes have no FP32 residual form)");
+  if (h->scheme == FFTC_HEX1 && h->has_sphere) return fail(h, FFTC_E_UNSUPPORTED, "contact uses the TETRA2 scheme");
+  if (h->ref_kind == FFTC_REF_ISO &&
+      (h->scheme != FFTC_HEX1 || !h->periodic[0] || !h->periodic[1] || !h->periodic[2]))
+    return fail(h, FFTC_E_UNSUPPORTED, "the isotropic reference medium needs HEX1 and periodic axes");
   if (((uintptr_t)ws) % kAlign) return fail(h, FFTC_E_WORKSPACE, "workspace must be 256-byte aligned");
   const size_t need = carve(h, nullptr);
   if (bytes < need) return fail(h, FFTC_E_WORKSPACE, "workspace too small");
@@ -1115,6 +1148,8 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   g.Nv = h->Nv;
   g.aface = h->aface;
   g.fs = h->fs;
+  g.hex = h->scheme == FFTC_HEX1;
+  g.iso = h->ref_kind == FFTC_REF_ISO;
   // singular modes of each component: theta = 0 needs DCT1 or DFT on all axes; theta = pi
   // additionally needs an even length on DFT axes
   for (int c = 0; c < 3; ++c) {

@@ -122,10 +122,13 @@ __device__ __forceinline__ int fft_sign(int type, int inv) {
 // Symbol of the Paux stencil for component c from per-axis s = sin^2(theta/2),
 // q = cos^2(theta/2): M = 4 sum_J a_J (s_J q_K q_L + q_J s_K s_L) -- the factored form of
 // d + 4 (e_xy Cx Cy + e_xz Cx Cz + e_yz Cy Cz), exact at theta = 0 and (pi, pi, pi).
+// HEX1 (hex = 1) keeps the first term of each pair only: M = 4 sum_J a_J s_J q_K q_L, the
+// centre-gradient symbol, which also vanishes on the hourglass lines (two angles equal to pi).
 __device__ __forceinline__ double paux_symbol(const double a[3], double sx, double qx, double sy, double qy,
-                                              double sz, double qz) {
-  return 4.0 * (a[0] * (sx * qy * qz + qx * sy * sz) + a[1] * (sy * qx * qz + qy * sx * sz) +
-                a[2] * (sz * qx * qy + qz * sx * sy));
+                                              double sz, double qz, int hex) {
+  const double h = hex ? 0.0 : 1.0;
+  return 4.0 * (a[0] * (sx * qy * qz + h * qx * sy * sz) + a[1] * (sy * qx * qz + h * qy * sx * sz) +
+                a[2] * (sz * qx * qy + h * qz * sx * sy));
 }
 
 // Residual-form update in the last inverse pass: delta = K0^+ e - (I - Pi) u, u += delta,
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
       T v = dtt_post<T>(type, 0, cb + l * cstride, n, m, tw);
       if (lg < nlines) {
         const int mx = (int)(lg % Nx), my = (int)(lg / Nx);
-        const double M = paux_symbol(a.g.ac[c], sxT[mx], qxT[mx], syT[my], qyT[my], szT[m], qzT[m]);
+        const double M = paux_symbol(a.g.ac[c], sxT[mx], qxT[mx], syT[my], qyT[my], szT[m], qzT[m], a.g.hex);
         v = (M > a.thr[c]) ? (T)((double)v / M) : T(0);
       } else {
         v = T(0);
@@ -532,13 +535,15 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     // A = 4 (a0 sx qy + a1 sy qx + a2 sx sy), B = 4 (a0 qx sy + a1 qy sx + a2 qx qy)
     const T sy = (T)syT[(int)byi], qy = (T)qyT[(int)byi];
     const T a0 = (T)a.g.ac[c][0], a1 = (T)a.g.ac[c][1], a2 = (T)a.g.ac[c][2];
+    // the second-tetrahedron terms of the TETRA2 symbol; 0 for HEX1 (centre gradient)
+    const T e0 = a.g.hex ? T(0) : a0, e1 = a.g.hex ? T(0) : a1, e2 = a.g.hex ? T(0) : a2;
     const T thr = (T)a.thr[c];
     const unsigned x0 = bxi * LB;
     auto green = [&](unsigned l, unsigned m) -> T {
       const T v = post_ct<T, NF>(type, 0, cb + l * CS, m, tw);
       const T sx = (T)sxT[x0 + l], qx = (T)qxT[x0 + l];
-      const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + a2 * sx * sy);
-      const T B = T(4) * (a0 * qx * sy + a1 * qy * sx + a2 * qx * qy);
+      const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + e2 * sx * sy);
+      const T B = T(4) * (e0 * qx * sy + e1 * qy * sx + a2 * qx * qy);
       const T M = (T)qzT[m] * A + (T)szT[m] * B;
       return (M > thr) ? v / M : T(0);
     };

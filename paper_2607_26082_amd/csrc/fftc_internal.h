@@ -42,6 +42,9 @@ struct Geo {
   int sing[3];
   double sing_scale[3];   // inverse-transform factor of one singular coefficient (prod 1/2n or 1/n)
   int fs;                 // finite strain: Saint-Venant-Kirchhoff PK1 in place of the linear stress
+  int hex;                // HEX1 scheme (centre gradient, one integration point) instead of TETRA2
+  int iso;                // isotropic reference medium (coupled Green operator; periodic cells)
+  double lam0, mu0;       // reference medium
 };
 
 // Device-resident iteration state (one per handle, in the workspace).

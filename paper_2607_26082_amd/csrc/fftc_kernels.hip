@@ -137,10 +137,118 @@ __device__ __forceinline__ void node_eval(const Geo& g, const T* __restrict__ u,
   }
 }
 
+// HEX1 (Section 3.1.2): the gradient of the trilinear interpolant at the centre of each of
+// the 8 voxels around the node, B_corner = (2a - 1, 2b - 1, 2c - 1) / 4, one integration point
+// of weight 1; p = -2^b sum B_node^T sigma, and the reference term K0 u = 2^b sum B_node^T
+// sigma0 with sigma0 = R0 : G of the Paux or the isotropic medium, both over in-cell voxels.
+template <typename T, bool SIG, bool FS = false>
+__device__ __forceinline__ void node_eval_hex(const Geo& g, const T* __restrict__ u, const T* __restrict__ lam,
+                                              const T* __restrict__ mu, int i, int j, int k, T p[3], T k0[3],
+                                              double& sn, double ms[6]) {
+  const int Nx = g.N[0], Ny = g.N[1];
+  const long long Nn = g.Nn;
+  const int xs[3] = {mirror_coord(g, i - 1, 0), i, mirror_coord(g, i + 1, 0)};
+  const int ys[3] = {mirror_coord(g, j - 1, 1), j, mirror_coord(g, j + 1, 1)};
+  const int zs[3] = {mirror_coord(g, k - 1, 2), k, mirror_coord(g, k + 1, 2)};
+  T F[3] = {T(0), T(0), T(0)}, F0[3] = {T(0), T(0), T(0)};
+  const T l0 = (T)g.lam0, m0 = (T)g.mu0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    int vx = i - ax, vy = j - ay, vz = k - az;
+    bool inside = true;
+    if (g.periodic[0]) { if (vx < 0) vx += g.n[0]; } else inside &= (vx >= 0 && vx < g.n[0]);
+    if (g.periodic[1]) { if (vy < 0) vy += g.n[1]; } else inside &= (vy >= 0 && vy < g.n[1]);
+    if (g.periodic[2]) { if (vz < 0) vz += g.n[2]; } else inside &= (vz >= 0 && vz < g.n[2]);
+    if (!inside) continue;
+    const long long vid = (long long)vx + (long long)g.n[0] * ((long long)vy + (long long)g.n[1] * vz);
+    const T l = lam[vid], m = mu[vid];
+    T G[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) G[r][q] = T(0);
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+      // corner cc of the voxel sits at node offset (cx - ax, cy - ay, cz - az)
+      const long long idx = (long long)xs[cx - ax + 1] + (long long)Nx * ((long long)ys[cy - ay + 1] + (long long)Ny * zs[cz - az + 1]);
+      const T bx = T(cx ? 0.25 : -0.25), by = T(cy ? 0.25 : -0.25), bz = T(cz ? 0.25 : -0.25);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const T v = u[r * Nn + idx];
+        G[r][0] += bx * v;
+        G[r][1] += by * v;
+        G[r][2] += bz * v;
+      }
+    }
+    T P[3][3], P0[3][3];
+    if constexpr (FS) {
+      svk_pk1<T>(G, l, m, P);
+    } else {
+      const T tr = G[0][0] + G[1][1] + G[2][2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[r][q] = m * (G[r][q] + G[q][r]) + (r == q ? l * tr : T(0));
+    }
+    if (g.iso) {
+      const T tr = G[0][0] + G[1][1] + G[2][2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P0[r][q] = m0 * (G[r][q] + G[q][r]) + (r == q ? l0 * tr : T(0));
+    } else {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P0[r][q] = T(2) * m0 * G[r][q] + (r == q ? l0 * G[r][r] : T(0));
+    }
+    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      F[r] += bx * P[r][0] + by * P[r][1] + bz * P[r][2];
+      F0[r] += bx * P0[r][0] + by * P0[r][1] + bz * P0[r][2];
+    }
+    if (SIG && a == 0) {   // the voxel whose corner 000 is this node
+      double q = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q += (double)P[r][c] * (double)P[r][c];
+      sn += q;
+      ms[0] += (double)P[0][0]; ms[1] += (double)P[1][1]; ms[2] += (double)P[2][2];
+      ms[3] += (double)P[1][2]; ms[4] += (double)P[0][2]; ms[5] += (double)P[0][1];
+    }
+  }
+  const int xyz[3] = {i, j, k};
+  const T w2b = T(1 << bcount(g, xyz));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const bool A = is_antisym(g, c, xyz);
+    p[c] = A ? T(0) : -w2b * F[c];
+    k0[c] = A ? T(0) : w2b * F0[c];
+  }
+}
+
+// node evaluation of the scheme in use (runtime dispatch for the kernels off the hot path)
+template <typename T, bool SIG>
+__device__ __forceinline__ void node_eval_any(const Geo& g, const T* __restrict__ u, const T* __restrict__ lam,
+                                              const T* __restrict__ mu, int i, int j, int k, T p[3], T k0[3],
+                                              double& sn, double ms[6]) {
+  if (g.hex) {
+    if (g.fs) node_eval_hex<T, SIG, true>(g, u, lam, mu, i, j, k, p, k0, sn, ms);
+    else node_eval_hex<T, SIG, false>(g, u, lam, mu, i, j, k, p, k0, sn, ms);
+  } else {
+    if (g.fs) node_eval<T, SIG, true>(g, u, lam, mu, i, j, k, p, k0, sn, ms);
+    else node_eval<T, SIG, false>(g, u, lam, mu, i, j, k, p, k0, sn, ms);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Residual pass
 // ---------------------------------------------------------------------------
-template <typename T, bool FS>
+template <typename T, bool FS, bool HEX>
 __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, int force, int write_p) {
   __shared__ double sh[kPartStride * 16];
@@ -160,7 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDe
     const int k = r / Ny, j = r - k * Ny;
     T p[3], k0[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
-    node_eval<T, true, FS>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+    if constexpr (HEX) node_eval_hex<T, true, FS>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+    else node_eval<T, true, FS>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
     acc[1] += sn;
 #pragma unroll
     for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
@@ -211,8 +320,7 @@ __device__ __forceinline__ void node_p(const Geo& g, const Bufs<T>& B, long long
   const int j = (int)(r % Ny), k = (int)(r / Ny);
   T k0[3];
   double sn = 0.0, ms[6];
-  if (g.fs) node_eval<T, false, true>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
-  else node_eval<T, false, false>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
+  node_eval_any<T, false>(g, B.u, B.lam, B.mu, i, j, k, p, k0, sn, ms);
   const int xyz[3] = {i, j, k};
   b = bcount(g, xyz);
 }
@@ -468,6 +576,107 @@ __global__ __launch_bounds__(kBlock) void k_alpha(DevState* st, const double* __
 
 
 // ---------------------------------------------------------------------------
+// Isotropic reference medium on a cell periodic on every axis (eq 4, Section 3.2.4).  After
+// the forward half-complex transforms of the three axes, storage index m of an axis of n
+// voxels holds the cosine part of frequency m (2m <= n) or the sine part of frequency n - m
+// (as the imaginary part of the DFT).  Per frequency class (k1, k2, k3), 0 <= k_J <= n_J / 2,
+// the up to eight cosine/sine combinations of each component give the complex coefficients
+// at (theta1, +-theta2, +-theta3); each is solved with the HEX1 symbol
+// M = mu0 |d|^2 I + (lam0 + mu0) d d^T, d_J = 2 sin(theta_J / 2) prod_{K != J} cos(theta_K / 2)
+// (real, so its inverse acts on real and imaginary parts alike; 0 where |d| = 0: theta = 0
+// and the hourglass lines), and the combinations are formed back.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ipow(int n, double& re, double& im) {   // i^n
+  const int r = n & 3;
+  re = r == 0 ? 1.0 : (r == 2 ? -1.0 : 0.0);
+  im = r == 1 ? 1.0 : (r == 3 ? -1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_green_iso(Geo g, double* buf, DevState* st, int force) {
+  if (!force && st->done) return;
+  const int nn[3] = {g.n[0], g.n[1], g.n[2]};
+  const int h1 = nn[0] / 2 + 1, h2 = nn[1] / 2 + 1, h3 = nn[2] / 2 + 1;
+  const long long cls = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (cls >= (long long)h1 * h2 * h3) return;
+  const int kk[3] = {(int)(cls % h1), (int)((cls / h1) % h2), (int)(cls / ((long long)h1 * h2))};
+  int np[3], idx[3][2];
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    np[J] = (kk[J] == 0 || 2 * kk[J] == nn[J]) ? 1 : 2;
+    idx[J][0] = kk[J];
+    idx[J][1] = nn[J] - kk[J];
+  }
+  const long long Nn = g.Nn;
+  const int Nx = g.N[0], Ny = g.N[1];
+  double Tv[3][2][2][2], Tu[3][2][2][2];
+  for (int c = 0; c < 3; ++c)
+    for (int a1 = 0; a1 < 2; ++a1)
+      for (int a2 = 0; a2 < 2; ++a2)
+        for (int a3 = 0; a3 < 2; ++a3) {
+          Tu[c][a1][a2][a3] = 0.0;
+          Tv[c][a1][a2][a3] = 0.0;
+          if (a1 < np[0] && a2 < np[1] && a3 < np[2])
+            Tv[c][a1][a2][a3] = buf[c * Nn + idx[0][a1] + (long long)Nx * (idx[1][a2] + (long long)Ny * idx[2][a3])];
+        }
+  const double bcoef = (g.lam0 + g.mu0) / (g.lam0 + 2.0 * g.mu0);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int s2i = 0; s2i < np[1]; ++s2i)
+    for (int s3i = 0; s3i < np[2]; ++s3i) {
+      const double sg[3] = {1.0, s2i ? -1.0 : 1.0, s3i ? -1.0 : 1.0};
+      double Xr[3], Xi[3];
+      for (int c = 0; c < 3; ++c) {
+        Xr[c] = Xi[c] = 0.0;
+        for (int a1 = 0; a1 < np[0]; ++a1)
+          for (int a2 = 0; a2 < np[1]; ++a2)
+            for (int a3 = 0; a3 < np[2]; ++a3) {
+              double wr, wi;
+              ipow(a1 + a2 + a3, wr, wi);
+              const double sgn = (a2 ? sg[1] : 1.0) * (a3 ? sg[2] : 1.0);
+              Xr[c] += sgn * wr * Tv[c][a1][a2][a3];
+              Xi[c] += sgn * wi * Tv[c][a1][a2][a3];
+            }
+      }
+      double th[3], d[3];
+      for (int J = 0; J < 3; ++J) th[J] = sg[J] * two_pi * kk[J] / nn[J];
+      for (int J = 0; J < 3; ++J)
+        d[J] = 2.0 * sin(0.5 * th[J]) * cos(0.5 * th[(J + 1) % 3]) * cos(0.5 * th[(J + 2) % 3]);
+      const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      double Ur[3] = {0.0, 0.0, 0.0}, Ui[3] = {0.0, 0.0, 0.0};
+      if (d2 > 1e-13) {
+        const double dr = d[0] * Xr[0] + d[1] * Xr[1] + d[2] * Xr[2];
+        const double di = d[0] * Xi[0] + d[1] * Xi[1] + d[2] * Xi[2];
+        const double inv = 1.0 / (g.mu0 * d2);
+        for (int c = 0; c < 3; ++c) {
+          Ur[c] = (Xr[c] - bcoef * d[c] * dr / d2) * inv;
+          Ui[c] = (Xi[c] - bcoef * d[c] * di / d2) * inv;
+        }
+      }
+      // T[a] = (1 / number of sign combinations) Re(sum_s conj(w_a(s)) U(s))
+      for (int c = 0; c < 3; ++c)
+        for (int a1 = 0; a1 < np[0]; ++a1)
+          for (int a2 = 0; a2 < np[1]; ++a2)
+            for (int a3 = 0; a3 < np[2]; ++a3) {
+              double wr, wi;
+              ipow(a1 + a2 + a3, wr, wi);
+              const double sgn = (a2 ? sg[1] : 1.0) * (a3 ? sg[2] : 1.0);
+              Tu[c][a1][a2][a3] += sgn * (wr * Ur[c] + wi * Ui[c]);
+            }
+    }
+  const double inv_ns = 1.0 / (np[1] * np[2]);
+  for (int c = 0; c < 3; ++c)
+    for (int a1 = 0; a1 < np[0]; ++a1)
+      for (int a2 = 0; a2 < np[1]; ++a2)
+        for (int a3 = 0; a3 < np[2]; ++a3)
+          buf[c * Nn + idx[0][a1] + (long long)Nx * (idx[1][a2] + (long long)Ny * idx[2][a3])] =
+              Tu[c][a1][a2][a3] * inv_ns;
+}
+
+void launch_green_iso(const Geo& g, double* buf, DevState* st, int force, hipStream_t s) {
+  const long long ncls = (long long)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
+  hipLaunchKernelGGL(k_green_iso, dim3(grid_for(ncls, 1 << 30)), dim3(kBlock), 0, s, g, buf, st, force);
+}
+
+// ---------------------------------------------------------------------------
 // proj_U kernels and bookkeeping
 // ---------------------------------------------------------------------------
 // proj_U of the relations (eq 11, eq 15): u += wd (val - wa . u) / (wa . wd) over the support.
@@ -686,8 +895,13 @@ __global__ void k_extend(DevState* st, int iters, double tol) {
 template <typename T>
 void launch_residual(const Geo& g, const Bufs<T>& B, const ContactDev& ct, DevState* st, double* part, int nblk,
                      int force, int write_p, hipStream_t s) {
-  if (g.fs) hipLaunchKernelGGL((k_residual<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
-  else hipLaunchKernelGGL((k_residual<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+  if (g.hex) {
+    if (g.fs) hipLaunchKernelGGL((k_residual<T, true, true>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+    else hipLaunchKernelGGL((k_residual<T, false, true>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+  } else {
+    if (g.fs) hipLaunchKernelGGL((k_residual<T, true, false>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+    else hipLaunchKernelGGL((k_residual<T, false, false>), dim3(nblk), dim3(kBlock), 0, s, g, B, ct, st, part, force, write_p);
+  }
 }
 
 template <typename T>

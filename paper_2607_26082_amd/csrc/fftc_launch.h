@@ -52,6 +52,9 @@ void launch_convert(const A* in, B* out, long long n, hipStream_t s);
 template <typename T>
 void launch_zero_amask(const Geo& g, T* u, hipStream_t s);
 void launch_extend(DevState* st, int iters, double tol, hipStream_t s);
+// Isotropic reference medium on a cell periodic on every axis: Green solve on the forward
+// half-complex coefficients of the three components (FP64).
+void launch_green_iso(const Geo& g, double* buf, DevState* st, int force, hipStream_t s);
 void launch_check_stiffness(const double* lam, const double* mu, long long nv, double* out, int nblk, hipStream_t s);
 
 }  // namespace fftc
