@@ -13,7 +13,7 @@
  * Conventions
  *  - Every call returns an int status (FFTC_OK = 0, errors negative); nothing
  *    aborts or throws across the ABI; fftc_last_error() returns a message.
- *  - Grid: n[3] = voxels (nx, ny, nz), h = 1.  Nodes per axis N_J = n_J + 1, or
+ *  - Grid: n[3] = voxels (nx, ny, nz) of edge h.  Nodes per axis N_J = n_J + 1, or
  *    n_J on a periodic axis.  Node (i, j, k) has flat index i + N_x (j + N_y k).
  *    Vector node fields are component-planar [3][N_z][N_y][N_x], x fastest;
  *    voxel fields are [n_z][n_y][n_x].
@@ -90,9 +90,20 @@ typedef struct {
   double mean_stress[6];      /* <sigma>: xx, yy, zz, yz, xz, xy                   */
 } fftc_report;
 
-/* Create a problem on n[3] voxels.  Errors: FFTC_E_ARG (n_J < 2), FFTC_E_UNSUPPORTED
- * (axis length with a prime factor > 5, or precision unknown). */
-int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision);
+/* Discrete gradient (Section 3.1.2).  FFTC_TETRA2: two tetrahedra per voxel, two integration
+ * points of weight 1/2.  FFTC_HEX1: the gradient of the trilinear interpolant at the voxel
+ * centre, one integration point of weight 1; its hourglass modes (zero centre gradient in every
+ * voxel) get no Green correction, and single-node conditions excite them (Section 4.2.3: use
+ * average relations).  HEX1 runs in FP64 and without contact (FFTC_E_UNSUPPORTED at binding). */
+#define FFTC_TETRA2 0
+#define FFTC_HEX1 1
+
+/* Create a problem on n[3] voxels of edge h (all lengths at the ABI -- prescribed values,
+ * sphere, displacements, gaps -- are in the unit of h; forces are stress times that unit
+ * squared; the kernels work in voxel units).  scheme: FFTC_TETRA2 or FFTC_HEX1.
+ * Errors: FFTC_E_ARG (n_J < 2 or > 4096, h not positive), FFTC_E_UNSUPPORTED (axis length
+ * with a prime factor > 5, unknown scheme or precision, more than 2^31 DOFs). */
+int fftc_create(fftc_h* out, const int32_t n[3], double h, int32_t scheme, int32_t precision);
 void fftc_destroy(fftc_h h);
 
 /* Boundary table bc_host[comp*6 + axis*2 + face] (Section 3.2.1, Table 1; Section 3.2.2,
@@ -115,18 +126,10 @@ int fftc_set_reference(fftc_h h, int32_t kind, double lam0, double mu0);
  * max mu), evaluated by fftc_set_stiffness (the default: Paux, factor 1). */
 int fftc_set_reference_factor(fftc_h h, int32_t kind, double factor);
 
-/* Discrete gradient (Section 3.1.2).  FFTC_TETRA2 (default): two tetrahedra per voxel, two
- * integration points of weight 1/2.  FFTC_HEX1: the gradient of the trilinear interpolant at
- * the voxel centre, one integration point of weight 1; its hourglass modes (zero centre
- * gradient in every voxel) get no Green correction, and single-node conditions excite them
- * (Section 4.2.3: use average relations).  HEX1 runs in FP64 and without contact
- * (FFTC_E_UNSUPPORTED at binding otherwise).  Before binding (FFTC_E_STATE). */
-#define FFTC_TETRA2 0
-#define FFTC_HEX1 1
-int fftc_set_scheme(fftc_h h, int32_t scheme);
-
 /* Strong nodal constraints u[comp[k]](node[k]) = value[k] (Section 4.1, eq 8-9).
- * node_host: m triples (i, j, k).  set_id groups DOFs for reaction totals (0..63).
+ * node_host: m triples (i, j, k).  set_id groups DOFs for reaction totals (0..63; several
+ * calls may share one).  The arrays of this call and of fftc_add_average / fftc_add_smooth may
+ * be host or device memory (device arrays are copied to the host).
  * Errors: FFTC_E_ARG (index out of range, DOF constrained twice), FFTC_E_BC (nonzero
  * value on an eliminated DOF; zero values there are dropped). */
 int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node_host, const int8_t* comp_host,
@@ -190,10 +193,16 @@ int fftc_bind_workspace(fftc_h h, void* ws_dev, size_t bytes, void* stream);
 #define FFTC_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
 int fftc_bind_workspace_static(fftc_h h, void* stream);
 
-/* Per-voxel isotropic stiffness, FP64 device arrays [nz][ny][nx] (paper eq 1: sigma =
- * C : eps).  lam = mu = 0 marks void voxels.  Errors: FFTC_E_NAN (non-finite),
- * FFTC_E_ARG (mu < 0 or 3 lam + 2 mu < 0), FFTC_E_STATE (no workspace). */
-int fftc_set_stiffness(fftc_h h, const double* lam_dev, const double* mu_dev);
+/* Per-voxel isotropic stiffness (paper eq 1: sigma = C : eps), device arrays [nz][ny][nx] of
+ * dtype FFTC_F64 or FFTC_F32, copied into the workspace in the working precision.
+ * fftc_set_stiffness takes the Lame constants (lam = mu = 0 marks void voxels);
+ * fftc_set_stiffness_Enu Young's modulus and Poisson's ratio (E = 0: void).  Errors:
+ * FFTC_E_NAN (non-finite), FFTC_E_ARG (mu < 0 or 3 lam + 2 mu < 0; E < 0 or nu outside
+ * (-1, 1/2); unknown dtype), FFTC_E_STATE (no workspace). */
+#define FFTC_F64 0
+#define FFTC_F32 1
+int fftc_set_stiffness(fftc_h h, const void* lam_dev, const void* mu_dev, int32_t dtype);
+int fftc_set_stiffness_Enu(fftc_h h, const void* E_dev, const void* nu_dev, int32_t dtype);
 
 /* Algorithm 1.  u_dev: FP64 [3][Nz][Ny][Nx]; on entry the initial guess unless
  * zero_start != 0, on return the last iterate (after the final equilibrium test).
@@ -214,9 +223,13 @@ int fftc_get_reactions(fftc_h h, double* per_dof_host, double* per_relation_host
                        double* totals_host, int32_t nsets);
 int fftc_num_constraints(fftc_h h, int64_t* n_strong, int64_t* n_average);
 
-/* Active set of the last contact solve: mask_host[face nodes] (1 = in C), normal reaction
- * f_nc and gap per face node (face nodes in flat order of the two in-plane axes). */
-int fftc_get_contact(fftc_h h, uint8_t* mask_host, double* fnc_host, double* gap_host);
+/* Active set of the last contact solve (Section 5.1, eq 26): mask_host[face nodes] (1 = in C),
+ * normal reaction f_nc and gap per face node (face nodes in flat order of the two in-plane
+ * axes), the total contact force along the face normal (as fftc_report.force_contact) and the
+ * contact area (the face area of the nodes of C, half a voxel face along an edge of the face;
+ * its equivalent radius is sqrt(area / pi)).  Any pointer may be NULL. */
+int fftc_get_contact(fftc_h h, uint8_t* mask_host, double* fnc_host, double* gap_host, double* force_host,
+                     double* area_host);
 int fftc_num_face_nodes(fftc_h h, int64_t* count);
 
 /* Stage entry points (one step of the iteration on caller data, for testing):

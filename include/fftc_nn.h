@@ -119,6 +119,12 @@ int fftc_nn_train_step(fftc_nn_h nn, const uint16_t* feat_dev, const float* targ
  * refreshed. */
 int fftc_nn_adam_step(fftc_nn_h nn, float lr, float beta1, float beta2, float eps);
 
+/* Training target t = (u* - u1) / s_u as FP32 (count values, component-planar like the
+ * displacement) on the HIP stream given: u_dev a converged solve, u1_dev the first iterate of
+ * fftc_nn_features, both FP64 device arrays.  Errors: FFTC_E_ARG, FFTC_E_HIP. */
+int fftc_nn_make_target(const double* u_dev, const double* u1_dev, int64_t count, double s_u, float* target_dev,
+                        void* stream);
+
 /* Message of the last failing call on this network. */
 const char* fftc_nn_last_error(fftc_nn_h nn);
 

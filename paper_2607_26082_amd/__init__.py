@@ -43,12 +43,11 @@ class fftc_report(C.Structure):
 
 _P = C.c_void_p
 _SIGS = {
-    "fftc_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_int32]),
+    "fftc_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int32), C.c_double, C.c_int32, C.c_int32]),
     "fftc_destroy": (None, [_P]),
     "fftc_set_bc": (C.c_int, [_P, C.POINTER(C.c_int8)]),
     "fftc_set_reference": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
     "fftc_set_reference_factor": (C.c_int, [_P, C.c_int32, C.c_double]),
-    "fftc_set_scheme": (C.c_int, [_P, C.c_int32]),
     "fftc_add_dirichlet": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
                                      C.POINTER(C.c_double), C.c_int32]),
     "fftc_add_average": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int8),
@@ -64,12 +63,14 @@ _SIGS = {
     "fftc_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "fftc_bind_workspace": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "fftc_bind_workspace_static": (C.c_int, [_P, _P]),
-    "fftc_set_stiffness": (C.c_int, [_P, _P, _P]),
+    "fftc_set_stiffness": (C.c_int, [_P, _P, _P, C.c_int32]),
+    "fftc_set_stiffness_Enu": (C.c_int, [_P, _P, _P, C.c_int32]),
     "fftc_solve": (C.c_int, [_P, _P, C.c_int32, C.POINTER(fftc_report)]),
     "fftc_get_reactions": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_int32]),
     "fftc_num_constraints": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
-    "fftc_get_contact": (C.c_int, [_P, C.POINTER(C.c_uint8), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fftc_get_contact": (C.c_int, [_P, C.POINTER(C.c_uint8), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fftc_num_face_nodes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "fftc_stage_residual": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_double)]),
     "fftc_stage_green": (C.c_int, [_P, _P, _P]),
@@ -93,6 +94,7 @@ _SIGS = {
     "fftc_nn_forward": (C.c_int, [_P, _P, _P, C.c_double, _P, _P]),
     "fftc_nn_train_step": (C.c_int, [_P, _P, _P, _P]),
     "fftc_nn_adam_step": (C.c_int, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "fftc_nn_make_target": (C.c_int, [_P, _P, C.c_int64, C.c_double, _P, _P]),
     "fftc_nn_last_error": (C.c_char_p, [_P]),
     "fftc_solve_judged": (C.c_int, [_P, _P, _P, C.POINTER(fftc_report), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double)]),
@@ -141,14 +143,18 @@ def _dev(t):
 # thin wrappers, named after the C entry points
 # ---------------------------------------------------------------------------
 
-def fftc_create(n, precision=FFTC_FP64):
+FFTC_TETRA2, FFTC_HEX1 = 0, 1
+FFTC_F64, FFTC_F32 = 0, 1
+
+
+def fftc_create(n, precision=FFTC_FP64, h=1.0, scheme=FFTC_TETRA2):
     lib = load()
-    h = C.c_void_p()
+    hd = C.c_void_p()
     arr = (C.c_int32 * 3)(*[int(v) for v in n])
-    rc = lib.fftc_create(C.byref(h), arr, int(precision))
+    rc = lib.fftc_create(C.byref(hd), arr, float(h), int(scheme), int(precision))
     if rc != FFTC_OK:
         raise FftcError(rc, "fftc_create: " + lib.fftc_status_str(rc).decode())
-    return h
+    return hd
 
 
 def fftc_destroy(h):
@@ -168,7 +174,6 @@ def fftc_set_bc(h, bc):
 
 
 FFTC_REF_PAUX, FFTC_REF_ISO = 0, 1
-FFTC_TETRA2, FFTC_HEX1 = 0, 1
 
 
 def fftc_set_reference(h, lam0, mu0, kind=FFTC_REF_PAUX):
@@ -178,9 +183,6 @@ def fftc_set_reference(h, lam0, mu0, kind=FFTC_REF_PAUX):
 def fftc_set_reference_factor(h, factor, kind=FFTC_REF_PAUX):
     return _check(h, load().fftc_set_reference_factor(h, int(kind), float(factor)), "fftc_set_reference_factor")
 
-
-def fftc_set_scheme(h, scheme):
-    return _check(h, load().fftc_set_scheme(h, int(scheme)), "fftc_set_scheme")
 
 
 def fftc_add_dirichlet(h, node, comp, value, set_id=0):
@@ -249,8 +251,23 @@ def fftc_bind_workspace_static(h, stream):
 FFTC_STATIC_WORKSPACE_BYTES = 128 << 20
 
 
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return FFTC_F64
+    if t.dtype == torch.float32:
+        return FFTC_F32
+    raise TypeError("stiffness arrays must be float64 or float32")
+
+
 def fftc_set_stiffness(h, lam_dev, mu_dev):
-    return _check(h, load().fftc_set_stiffness(h, _dev(lam_dev), _dev(mu_dev)), "fftc_set_stiffness")
+    return _check(h, load().fftc_set_stiffness(h, _dev(lam_dev), _dev(mu_dev), _dtype_code(lam_dev)),
+                  "fftc_set_stiffness")
+
+
+def fftc_set_stiffness_Enu(h, E_dev, nu_dev):
+    return _check(h, load().fftc_set_stiffness_Enu(h, _dev(E_dev), _dev(nu_dev), _dtype_code(E_dev)),
+                  "fftc_set_stiffness_Enu")
 
 
 def fftc_solve(h, u_dev, zero_start=True):
@@ -275,9 +292,10 @@ def fftc_get_contact(h):
     m = C.c_int64()
     lib.fftc_num_face_nodes(h, C.byref(m))
     mask = np.zeros(m.value, np.uint8); fnc = np.zeros(m.value); gap = np.zeros(m.value)
-    _check(h, lib.fftc_get_contact(h, _ptr(mask, C.c_uint8), _ptr(fnc, C.c_double), _ptr(gap, C.c_double)),
-           "fftc_get_contact")
-    return mask, fnc, gap
+    force, area = C.c_double(), C.c_double()
+    _check(h, lib.fftc_get_contact(h, _ptr(mask, C.c_uint8), _ptr(fnc, C.c_double), _ptr(gap, C.c_double),
+                                   C.byref(force), C.byref(area)), "fftc_get_contact")
+    return mask, fnc, gap, force.value, area.value
 
 
 def fftc_stage_residual(h, u_dev, p_dev=None, ptil_dev=None):
@@ -440,6 +458,13 @@ def fftc_nn_adam_step(nn, lr, beta1=0.9, beta2=0.999, eps=1e-8):
              "fftc_nn_adam_step")
 
 
+def fftc_nn_make_target(u_dev, u1_dev, s_u, target_dev, stream):
+    rc = load().fftc_nn_make_target(_dev(u_dev), _dev(u1_dev), int(u_dev.numel()), float(s_u), _dev(target_dev),
+                                    C.c_void_p(stream))
+    if rc != FFTC_OK:
+        raise FftcError(rc, "fftc_nn_make_target")
+
+
 def fftc_solve_judged(h, u0_dev, u_dev):
     rep = fftc_report()
     used = C.c_int32()
@@ -525,12 +550,13 @@ class Solver:
 
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
                  precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
-                 smooth=(), static_workspace=False, finite_strain=False, scheme="tetra2", reference="paux"):
+                 smooth=(), static_workspace=False, finite_strain=False, scheme="tetra2", reference="paux",
+                 voxel=1.0):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
         self.precision = FFTC_FP64 if precision == "fp64" else FFTC_FP32
-        self.h = fftc_create(self.n, self.precision)
+        self.h = fftc_create(self.n, self.precision, voxel, FFTC_HEX1 if scheme == "hex1" else FFTC_TETRA2)
         bc = np.asarray(bc, np.int8).reshape(3, 3, 2)
         fftc_set_bc(self.h, bc)
         periodic = [bool((bc[:, J, :] == 2).all()) for J in range(3)]
@@ -547,7 +573,6 @@ class Solver:
             self.nsets = max(self.nsets, m.set_id + 1)
         if sphere is not None:
             fftc_set_sphere(self.h, sphere.center, sphere.radius, sphere.face)
-        fftc_set_scheme(self.h, FFTC_HEX1 if scheme == "hex1" else FFTC_TETRA2)
         fftc_set_reference_factor(self.h, r0_factor, FFTC_REF_ISO if reference == "iso" else FFTC_REF_PAUX)
         if finite_strain:
             fftc_set_kinematics(self.h, FFTC_FINITE_STRAIN)
@@ -604,7 +629,12 @@ class Solver:
         return fftc_get_reactions(self.h, self.nsets)
 
     def contact(self):
-        return fftc_get_contact(self.h)
+        """Active set, normal reaction and gap per face node."""
+        return fftc_get_contact(self.h)[:3]
+
+    def contact_force_area(self):
+        """Contact force along the face normal and contact area of the last solve."""
+        return fftc_get_contact(self.h)[3:]
 
     def stage_residual(self, u):
         t = self.torch

@@ -27,6 +27,8 @@ struct fftc_problem {
   int n[3] = {0, 0, 0}, N[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
   int precision = FFTC_FP64;
   int fs = 0;   // FFTC_FINITE_STRAIN
+  double hlen = 1.0;   // voxel size: lengths at the ABI are physical, the kernels work in voxel units
+  double last_force = 0.0;   // contact force of the last solve
   long long Nn = 0, Nv = 0;
   int8_t bc[18];
   int type[3][3];
@@ -571,7 +573,7 @@ int init_literal(fftc_problem* h, const double* u_dev, int zero_start) {
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
   if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(B.u, 0, sizeof(T) * n3, s));
-  else launch_convert<double, T>(u_dev, B.u, n3, s);
+  else launch_convert<double, T>(u_dev, B.u, n3, s, 1.0 / h->hlen);
   launch_zero_amask<T>(h->g, B.u, s);
   const ContactDev ct = contact_dev(h);
   // initial proj_U (and the initial active set from the gaps)
@@ -585,6 +587,7 @@ int init_delta(fftc_problem* h, const double* u_dev, int zero_start) {
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
   if (zero_start || !u_dev) HIPCHK(h, hipMemsetAsync(D.u, 0, 8 * n3, s));
+  else if (h->hlen != 1.0) launch_convert<double, double>(u_dev, D.u, n3, s, 1.0 / h->hlen);
   else HIPCHK(h, hipMemcpyAsync(D.u, u_dev, 8 * n3, hipMemcpyDeviceToDevice, s));
   launch_zero_amask<double>(h->g, D.u, s);
   const ContactDev ct = contact_dev(h);
@@ -624,8 +627,9 @@ int finish_report(fftc_problem* h, const DevState& out, double force_c, int nC, 
       double A0 = 1.0;
       for (int J = 0; J < 3; ++J)
         if (J != a) A0 *= h->n[J];
-      rep->force_mean_stress = -A0 * rep->mean_stress[a];
+      rep->force_mean_stress = -A0 * h->hlen * h->hlen * rep->mean_stress[a];
       rep->force_contact = force_c;
+      h->last_force = force_c;
       rep->contact_nodes = nC;
     }
   }
@@ -644,17 +648,18 @@ int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
   if (h->delta_mode) {
     DeltaBufs<float> D = dbufs(h);
     launch_reactions_d<float>(h->g, D, sd, h->sreact, s);
-    if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
+    if (u_dev && h->hlen != 1.0) launch_convert<double, double>(D.u, u_dev, n3, s, h->hlen);
+    else if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
     if (ct.on) launch_contact_force<double>(h->g, D.u, ct, h->chk, 64, s);
   } else if (h->precision == FFTC_FP64) {
     Bufs<double> B = bufs<double>(h);
     launch_reactions<double>(h->g, B, sd, h->sreact, s);
-    if (u_dev) launch_convert<double, double>(B.u, u_dev, n3, s);
+    if (u_dev) launch_convert<double, double>(B.u, u_dev, n3, s, h->hlen);
     if (ct.on) launch_contact_force<double>(h->g, B.u, ct, h->chk, 64, s);
   } else {
     Bufs<float> B = bufs<float>(h);
     launch_reactions<float>(h->g, B, sd, h->sreact, s);
-    if (u_dev) launch_convert<float, double>(B.u, u_dev, n3, s);
+    if (u_dev) launch_convert<float, double>(B.u, u_dev, n3, s, h->hlen);
     if (ct.on) launch_contact_force<float>(h->g, B.u, ct, h->chk, 64, s);
   }
   h->react_strong.assign(h->s_comp.size(), 0.0);
@@ -666,6 +671,9 @@ int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
   std::vector<double> cf(2 * 64, 0.0);
   if (ct.on) HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  const double h2 = h->hlen * h->hlen;   // forces: voxel units -> physical
+  for (double& v : h->react_strong) v *= h2;
+  for (double& v : h->react_weak) v *= h2;
   double force_c = 0.0;
   int nC = 0;
   if (ct.on) {
@@ -674,7 +682,7 @@ int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
       fs += cf[2 * b];
       cnt += cf[2 * b + 1];
     }
-    force_c = -((h->face % 2) ? 1.0 : -1.0) * fs;
+    force_c = -((h->face % 2) ? 1.0 : -1.0) * fs * h2;
     nC = (int)cnt;
   }
   return finish_report(h, h->last, force_c, nC, rep);
@@ -821,10 +829,12 @@ void release_static(fftc_problem* h) {
 
 extern "C" {
 
-int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision) {
+int fftc_create(fftc_h* out, const int32_t n[3], double hlen, int32_t scheme, int32_t precision) {
   if (!out || !n) return FFTC_E_ARG;
   *out = nullptr;
   if (precision != FFTC_FP64 && precision != FFTC_FP32) return FFTC_E_UNSUPPORTED;
+  if (scheme != FFTC_TETRA2 && scheme != FFTC_HEX1) return FFTC_E_UNSUPPORTED;
+  if (!(hlen > 0.0) || !isfinite(hlen)) return FFTC_E_ARG;
   for (int J = 0; J < 3; ++J)
     if (n[J] < 2 || n[J] > 4096) return FFTC_E_ARG;
   fftc_problem* h = new (std::nothrow) fftc_problem();
@@ -841,6 +851,8 @@ int fftc_create(fftc_h* out, const int32_t n[3], int32_t precision) {
     for (size_t q = 0; q < rad.size(); ++q) h->ap[J].rad[q] = rad[q];
   }
   h->precision = precision;
+  h->scheme = scheme;
+  h->hlen = hlen;
   h->ept = precision == FFTC_FP64 ? 8 : 16;
   memset(h->bc, FFTC_BC_NEUMANN, sizeof(h->bc));
   build_plan(h);
@@ -901,16 +913,8 @@ int fftc_set_reference_factor(fftc_h h, int32_t kind, double factor) {
   return FFTC_OK;
 }
 
-int fftc_set_scheme(fftc_h h, int32_t scheme) {
-  if (!h) return FFTC_E_ARG;
-  if (scheme != FFTC_TETRA2 && scheme != FFTC_HEX1) return fail(h, FFTC_E_ARG, "unknown scheme");
-  if (h->bound) return fail(h, FFTC_E_STATE, "choose the scheme before binding");
-  h->scheme = scheme;
-  return FFTC_OK;
-}
-
-int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value,
-                       int32_t set_id) {
+static int add_dirichlet_host(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value,
+                              int32_t set_id) {
   if (!h || m < 0 || (m > 0 && (!node || !comp || !value))) return FFTC_E_ARG;
   if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
   if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
@@ -937,15 +941,15 @@ int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node, const int8_t* c
     if (node_antisym(h, comp[e], xyz)) continue;
     h->s_node.push_back(node_flat(h, xyz[0], xyz[1], xyz[2]));
     h->s_comp.push_back(comp[e]);
-    h->s_val.push_back(value[e]);
+    h->s_val.push_back(value[e] / h->hlen);
     h->s_set.push_back(set_id);
     h->dof_used.insert(keys[t++]);
   }
   return FFTC_OK;
 }
 
-int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, const int8_t* comp, const double* value,
-                     int32_t set_id) {
+static int add_average_host(fftc_h h, int64_t m, int32_t k, const int64_t* support, const int8_t* comp,
+                            const double* value, int32_t set_id) {
   if (!h || m < 0 || (m > 0 && (!support || !comp || !value))) return FFTC_E_ARG;
   if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
   if (k < 2 || k > kMaxRelSlots) return fail(h, FFTC_E_ARG, "support size must be 2..64 nodes");
@@ -974,14 +978,15 @@ int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, con
     }
     h->w_off.push_back((long long)h->w_nodes.size());
     h->w_comp.push_back(comp[r]);
-    h->w_val.push_back(value[r]);
+    h->w_val.push_back(value[r] / h->hlen);
     h->w_set.push_back(set_id);
   }
   for (long long key : mine) h->dof_used.insert(key);
   return FFTC_OK;
 }
 
-int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value, int32_t set_id) {
+static int add_smooth_host(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value,
+                           int32_t set_id) {
   if (!h || m < 0 || (m > 0 && (!node || !comp || !value))) return FFTC_E_ARG;
   if (h->bound) return fail(h, FFTC_E_STATE, "constraints must be added before binding the workspace");
   if (set_id < 0 || set_id >= kMaxSets) return fail(h, FFTC_E_ARG, "set_id out of range");
@@ -1048,11 +1053,67 @@ int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp
     }
     h->w_off.push_back((long long)h->w_nodes.size());
     h->w_comp.push_back(comp[r]);
-    h->w_val.push_back(value[r]);
+    h->w_val.push_back(value[r] / h->hlen);
     h->w_set.push_back(set_id);
   }
   for (long long key : mine) h->dof_used.insert(key);
   return FFTC_OK;
+}
+
+// The constraint calls take host or device arrays: device arrays are copied to the host first.
+extern "C++" template <typename T>
+static const T* host_view(const T* p, size_t count, std::vector<T>& tmp, bool& ok) {
+  ok = true;
+  if (!p || count == 0) return p;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) == hipSuccess && at.type == hipMemoryTypeDevice) {
+    tmp.resize(count);
+    ok = hipMemcpy(tmp.data(), p, count * sizeof(T), hipMemcpyDeviceToHost) == hipSuccess;
+    return tmp.data();
+  }
+  (void)hipGetLastError();   // a plain host pointer is not registered with the runtime
+  return p;
+}
+
+int fftc_add_dirichlet(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value,
+                       int32_t set_id) {
+  if (!h || m < 0) return FFTC_E_ARG;
+  std::vector<int64_t> tn;
+  std::vector<int8_t> tc;
+  std::vector<double> tv;
+  bool o1, o2, o3;
+  const int64_t* n2 = host_view(node, 3 * (size_t)m, tn, o1);
+  const int8_t* c2 = host_view(comp, (size_t)m, tc, o2);
+  const double* v2 = host_view(value, (size_t)m, tv, o3);
+  if (!o1 || !o2 || !o3) return fail(h, FFTC_E_HIP, "copying constraint arrays from the device failed");
+  return add_dirichlet_host(h, m, n2, c2, v2, set_id);
+}
+
+int fftc_add_average(fftc_h h, int64_t m, int32_t k, const int64_t* support, const int8_t* comp, const double* value,
+                     int32_t set_id) {
+  if (!h || m < 0 || k < 0) return FFTC_E_ARG;
+  std::vector<int64_t> tn;
+  std::vector<int8_t> tc;
+  std::vector<double> tv;
+  bool o1, o2, o3;
+  const int64_t* n2 = host_view(support, 3 * (size_t)m * (size_t)k, tn, o1);
+  const int8_t* c2 = host_view(comp, (size_t)m, tc, o2);
+  const double* v2 = host_view(value, (size_t)m, tv, o3);
+  if (!o1 || !o2 || !o3) return fail(h, FFTC_E_HIP, "copying constraint arrays from the device failed");
+  return add_average_host(h, m, k, n2, c2, v2, set_id);
+}
+
+int fftc_add_smooth(fftc_h h, int64_t m, const int64_t* node, const int8_t* comp, const double* value, int32_t set_id) {
+  if (!h || m < 0) return FFTC_E_ARG;
+  std::vector<int64_t> tn;
+  std::vector<int8_t> tc;
+  std::vector<double> tv;
+  bool o1, o2, o3;
+  const int64_t* n2 = host_view(node, 3 * (size_t)m, tn, o1);
+  const int8_t* c2 = host_view(comp, (size_t)m, tc, o2);
+  const double* v2 = host_view(value, (size_t)m, tv, o3);
+  if (!o1 || !o2 || !o3) return fail(h, FFTC_E_HIP, "copying constraint arrays from the device failed");
+  return add_smooth_host(h, m, n2, c2, v2, set_id);
 }
 
 int fftc_set_sphere(fftc_h h, const double center[3], double radius, int32_t face) {
@@ -1061,8 +1122,8 @@ int fftc_set_sphere(fftc_h h, const double center[3], double radius, int32_t fac
   if (!(radius > 0.0) || face < 0 || face > 5) return fail(h, FFTC_E_ARG, "invalid sphere");
   if (h->periodic[face / 2]) return fail(h, FFTC_E_ARG, "contact face on a periodic axis");
   h->has_sphere = 1;
-  for (int c = 0; c < 3; ++c) h->center[c] = center[c];
-  h->radius = radius;
+  for (int c = 0; c < 3; ++c) h->center[c] = center[c] / h->hlen;
+  h->radius = radius / h->hlen;
   h->face = face;
   int t = 0, bb[2];
   for (int J = 0; J < 3; ++J)
@@ -1074,7 +1135,7 @@ int fftc_set_sphere(fftc_h h, const double center[3], double radius, int32_t fac
 
 int fftc_move_sphere(fftc_h h, const double center[3]) {
   if (!h || !center || !h->has_sphere) return FFTC_E_ARG;
-  for (int c = 0; c < 3; ++c) h->center[c] = center[c];
+  for (int c = 0; c < 3; ++c) h->center[c] = center[c] / h->hlen;
   return FFTC_OK;
 }
 
@@ -1324,39 +1385,43 @@ int fftc_bind_workspace_static(fftc_h h, void* stream) {
   return rc;
 }
 
-int fftc_set_stiffness(fftc_h h, const double* lam, const double* mu) {
-  if (!h || !lam || !mu) return FFTC_E_ARG;
+static int set_stiffness_impl(fftc_h h, const void* a, const void* b, int dtype, int enu) {
+  if (!h || !a || !b) return FFTC_E_ARG;
+  if (dtype != FFTC_F64 && dtype != FFTC_F32) return fail(h, FFTC_E_ARG, "unknown dtype");
   if (!h->bound) return fail(h, FFTC_E_STATE, "bind the workspace first");
   hipStream_t s = h->stream;
   const int nblk = (int)std::min<long long>(1024, (h->Nv + kBlock - 1) / kBlock);
-  launch_check_stiffness(lam, mu, h->Nv, h->chk, nblk, s);
+  h->stiff_set = 0;
+  launch_stiffness_in(a, b, dtype == FFTC_F32, enu, h->Nv, h->lam, h->mu, h->precision == FFTC_FP32, h->chk, nblk, s);
   std::vector<double> chk(3 * nblk);
   HIPCHK(h, hipMemcpyAsync(chk.data(), h->chk, 8 * chk.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   double bad = 0, ml = -INFINITY, mm = -INFINITY;
-  for (int b = 0; b < nblk; ++b) {
-    bad = std::max(bad, chk[3 * b]);
-    ml = std::max(ml, chk[3 * b + 1]);
-    mm = std::max(mm, chk[3 * b + 2]);
+  for (int k = 0; k < nblk; ++k) {
+    bad = std::max(bad, chk[3 * k]);
+    ml = std::max(ml, chk[3 * k + 1]);
+    mm = std::max(mm, chk[3 * k + 2]);
   }
   if (bad >= 2.0) return fail(h, FFTC_E_NAN, "non-finite stiffness");
-  if (bad >= 1.0) return fail(h, FFTC_E_ARG, "stiffness must satisfy mu >= 0 and 3 lam + 2 mu >= 0");
+  if (bad >= 1.0)
+    return fail(h, FFTC_E_ARG, enu ? "stiffness must satisfy E >= 0 and -1 < nu < 1/2"
+                                   : "stiffness must satisfy mu >= 0 and 3 lam + 2 mu >= 0");
   if (h->ref_mode == 0) {
     h->lam0 = h->r0_factor * ml;
     h->mu0 = h->r0_factor * mm;
     if (!(h->mu0 > 0.0) || !(h->lam0 + 2 * h->mu0 > 0.0)) return fail(h, FFTC_E_ARG, "degenerate reference medium");
   }
   set_stencil(h);
-  if (h->precision == FFTC_FP64) {
-    HIPCHK(h, hipMemcpyAsync(h->lam, lam, 8 * h->Nv, hipMemcpyDeviceToDevice, s));
-    HIPCHK(h, hipMemcpyAsync(h->mu, mu, 8 * h->Nv, hipMemcpyDeviceToDevice, s));
-  } else {
-    launch_convert<double, float>(lam, (float*)h->lam, h->Nv, s);
-    launch_convert<double, float>(mu, (float*)h->mu, h->Nv, s);
-  }
-  HIPCHK(h, hipStreamSynchronize(s));
   h->stiff_set = 1;
   return FFTC_OK;
+}
+
+int fftc_set_stiffness(fftc_h h, const void* lam_dev, const void* mu_dev, int32_t dtype) {
+  return set_stiffness_impl(h, lam_dev, mu_dev, dtype, 0);
+}
+
+int fftc_set_stiffness_Enu(fftc_h h, const void* E_dev, const void* nu_dev, int32_t dtype) {
+  return set_stiffness_impl(h, E_dev, nu_dev, dtype, 1);
 }
 
 int fftc_solve(fftc_h h, double* u_dev, int32_t zero_start, fftc_report* rep) {
@@ -1576,6 +1641,7 @@ int fftc_nn_features(fftc_h h, uint16_t* feat_dev, double* u1_dev) {
   a.scratch = h->gpart;
   a.feat = feat_dev;
   nnk::launch_features(a, h->stream);
+  if (h->hlen != 1.0) launch_scale(u1_dev, n3, h->hlen, h->stream);   // channels in voxel units, u1 physical
   HIPCHK(h, hipGetLastError());
   return FFTC_OK;
 }
@@ -1645,13 +1711,34 @@ int fftc_num_face_nodes(fftc_h h, int64_t* count) {
   return FFTC_OK;
 }
 
-int fftc_get_contact(fftc_h h, uint8_t* mask, double* fnc, double* gap) {
+int fftc_get_contact(fftc_h h, uint8_t* mask, double* fnc, double* gap, double* force, double* area) {
   if (!h || !h->has_sphere || !h->bound) return FFTC_E_ARG;
   hipStream_t s = h->stream;
-  if (mask) HIPCHK(h, hipMemcpyAsync(mask, h->C, h->nface, hipMemcpyDeviceToHost, s));
+  std::vector<uint8_t> m((size_t)h->nface);
+  HIPCHK(h, hipMemcpyAsync(m.data(), h->C, h->nface, hipMemcpyDeviceToHost, s));
   if (fnc) HIPCHK(h, hipMemcpyAsync(fnc, h->fnc, 8 * h->nface, hipMemcpyDeviceToHost, s));
   if (gap) HIPCHK(h, hipMemcpyAsync(gap, h->gap, 8 * h->nface, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  const double h2 = h->hlen * h->hlen;
+  if (mask) memcpy(mask, m.data(), m.size());
+  if (fnc)
+    for (long long f = 0; f < h->nface; ++f) fnc[f] *= h2;
+  if (gap)
+    for (long long f = 0; f < h->nface; ++f) gap[f] *= h->hlen;
+  if (force) *force = h->last_force;
+  if (area) {
+    // tributary face area of every node of C: half a voxel face along an edge of the face
+    double A = 0.0;
+    const int N1 = h->N[h->b1], N2 = h->N[h->b2];
+    for (long long f = 0; f < h->nface; ++f) {
+      if (!m[f]) continue;
+      const int i1 = (int)(f % N1), i2 = (int)(f / N1);
+      const double w1 = (!h->periodic[h->b1] && (i1 == 0 || i1 == h->n[h->b1])) ? 0.5 : 1.0;
+      const double w2 = (!h->periodic[h->b2] && (i2 == 0 || i2 == h->n[h->b2])) ? 0.5 : 1.0;
+      A += w1 * w2;
+    }
+    *area = A * h2;
+  }
   return FFTC_OK;
 }
 

@@ -771,9 +771,15 @@ __global__ __launch_bounds__(kBlock) void k_reactions(Geo g, Bufs<T> B, StrongDe
 
 // elementwise conversion / utility kernels
 template <typename A, typename Bt>
-__global__ __launch_bounds__(kBlock) void k_convert(const A* __restrict__ in, Bt* __restrict__ out, long long n) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-    out[e] = (Bt)in[e];
+__global__ __launch_bounds__(kBlock) void k_convert(const A* __restrict__ in, Bt* __restrict__ out, long long n,
+                                                    double f) {
+  if (f == 1.0) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+      out[e] = (Bt)in[e];
+  } else {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+      out[e] = (Bt)((double)in[e] * f);
+  }
 }
 
 template <typename T>
@@ -788,15 +794,36 @@ __global__ __launch_bounds__(kBlock) void k_zero_amask(Geo g, T* u) {
   }
 }
 
-// stiffness check: finite values, mu >= 0, 3 lam + 2 mu >= 0; max lam, max mu
-__global__ __launch_bounds__(kBlock) void k_check_stiffness(const double* lam, const double* mu, long long nv,
-                                                            double* out /* per block: bad, maxl, maxm */) {
+// Stiffness intake: per voxel (lam, mu), or (E, nu) when enu, of type Ti -> lam, mu of the
+// working type To in the workspace, with the checks finite values, mu >= 0 and 3 lam + 2 mu >= 0
+// (for E, nu: E >= 0 and -1 < nu < 1/2); per block: worst check (2 non-finite, 1 out of range),
+// max lam, max mu.  Fixed reduction order.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_stiffness_in(const Ti* __restrict__ a, const Ti* __restrict__ b, int enu,
+                                                         long long nv, To* __restrict__ lam, To* __restrict__ mu,
+                                                         double* __restrict__ out) {
   __shared__ double sh[3 * 64];
   double bad = 0.0, ml = -INFINITY, mm = -INFINITY;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nv; e += (long long)gridDim.x * blockDim.x) {
-    const double l = lam[e], m = mu[e];
-    if (!isfinite(l) || !isfinite(m)) bad = fmax(bad, 2.0);
-    else if (m < 0.0 || 3.0 * l + 2.0 * m < 0.0) bad = fmax(bad, 1.0);
+    const double x = (double)a[e], y = (double)b[e];
+    double l = x, m = y;
+    if (enu) {
+      l = m = 0.0;
+      if (!isfinite(x) || !isfinite(y)) {
+        bad = fmax(bad, 2.0);
+      } else if (x < 0.0 || !(y > -1.0 && y < 0.5)) {
+        bad = fmax(bad, 1.0);
+      } else {
+        l = x * y / ((1.0 + y) * (1.0 - 2.0 * y));
+        m = x / (2.0 * (1.0 + y));
+      }
+    } else if (!isfinite(l) || !isfinite(m)) {
+      bad = fmax(bad, 2.0);
+    } else if (m < 0.0 || 3.0 * l + 2.0 * m < 0.0) {
+      bad = fmax(bad, 1.0);
+    }
+    lam[e] = (To)l;
+    mu[e] = (To)m;
     ml = fmax(ml, l);
     mm = fmax(mm, m);
   }
@@ -822,6 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_check_stiffness(const double* lam, c
     out[blockIdx.x * 3 + 1] = sh[64];
     out[blockIdx.x * 3 + 2] = sh[128];
   }
+}
+
+// x *= s over n values (length unit of the ABI <-> voxel units)
+__global__ __launch_bounds__(kBlock) void k_scale(double* __restrict__ x, long long n, double s) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    x[e] *= s;
 }
 
 // Anderson on the displacement (ACV_U): flags at the start of the iteration, then the
@@ -957,8 +990,8 @@ void launch_reactions(const Geo& g, const Bufs<T>& B, const StrongDev& sd, doubl
 }
 
 template <typename A, typename Bt>
-void launch_convert(const A* in, Bt* out, long long n, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<A, Bt>), dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, in, out, n);
+void launch_convert(const A* in, Bt* out, long long n, hipStream_t s, double f) {
+  hipLaunchKernelGGL((k_convert<A, Bt>), dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, in, out, n, f);
 }
 
 template <typename T>
@@ -970,8 +1003,24 @@ void launch_extend(DevState* st, int iters, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_extend, dim3(1), dim3(1), 0, s, st, iters, tol);
 }
 
-void launch_check_stiffness(const double* lam, const double* mu, long long nv, double* out, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_stiffness, dim3(nblk), dim3(kBlock), 0, s, lam, mu, nv, out);
+void launch_stiffness_in(const void* a, const void* b, int in_f32, int enu, long long nv, void* lam, void* mu,
+                         int out_f32, double* out, int nblk, hipStream_t s) {
+  if (in_f32 && out_f32)
+    hipLaunchKernelGGL((k_stiffness_in<float, float>), dim3(nblk), dim3(kBlock), 0, s, (const float*)a, (const float*)b, enu,
+                       nv, (float*)lam, (float*)mu, out);
+  else if (in_f32)
+    hipLaunchKernelGGL((k_stiffness_in<float, double>), dim3(nblk), dim3(kBlock), 0, s, (const float*)a, (const float*)b,
+                       enu, nv, (double*)lam, (double*)mu, out);
+  else if (out_f32)
+    hipLaunchKernelGGL((k_stiffness_in<double, float>), dim3(nblk), dim3(kBlock), 0, s, (const double*)a,
+                       (const double*)b, enu, nv, (float*)lam, (float*)mu, out);
+  else
+    hipLaunchKernelGGL((k_stiffness_in<double, double>), dim3(nblk), dim3(kBlock), 0, s, (const double*)a,
+                       (const double*)b, enu, nv, (double*)lam, (double*)mu, out);
+}
+
+void launch_scale(double* x, long long n, double f, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n, 8192)), dim3(kBlock), 0, s, x, n, f);
 }
 
 #define FFTC_INST(T)                                                                                              \
@@ -989,8 +1038,8 @@ void launch_check_stiffness(const double* lam, const double* mu, long long nv, d
 
 FFTC_INST(double)
 FFTC_INST(float)
-template void launch_convert<double, double>(const double*, double*, long long, hipStream_t);
-template void launch_convert<double, float>(const double*, float*, long long, hipStream_t);
-template void launch_convert<float, double>(const float*, double*, long long, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, long long, hipStream_t, double);
+template void launch_convert<double, float>(const double*, float*, long long, hipStream_t, double);
+template void launch_convert<float, double>(const float*, double*, long long, hipStream_t, double);
 
 }  // namespace fftc

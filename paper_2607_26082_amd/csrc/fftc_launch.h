@@ -47,14 +47,19 @@ template <typename T>
 void launch_contact_force(const Geo& g, const T* u, const ContactDev& ct, double* out, int nblk, hipStream_t s);
 template <typename T>
 void launch_reactions(const Geo& g, const Bufs<T>& B, const StrongDev& sd, double* out, hipStream_t s);
+// out = (B)(in * f)
 template <typename A, typename B>
-void launch_convert(const A* in, B* out, long long n, hipStream_t s);
+void launch_convert(const A* in, B* out, long long n, hipStream_t s, double f = 1.0);
 template <typename T>
 void launch_zero_amask(const Geo& g, T* u, hipStream_t s);
 void launch_extend(DevState* st, int iters, double tol, hipStream_t s);
 // Isotropic reference medium on a cell periodic on every axis: Green solve on the forward
 // half-complex coefficients of the three components (FP64).
 void launch_green_iso(const Geo& g, double* buf, DevState* st, int force, hipStream_t s);
-void launch_check_stiffness(const double* lam, const double* mu, long long nv, double* out, int nblk, hipStream_t s);
+// Stiffness intake (lam, mu or E, nu; FP32 or FP64 in and out) with its checks, per-block
+// (worst check, max lam, max mu) rows in out.
+void launch_stiffness_in(const void* a, const void* b, int in_f32, int enu, long long nv, void* lam, void* mu,
+                         int out_f32, double* out, int nblk, hipStream_t s);
+void launch_scale(double* x, long long n, double f, hipStream_t s);
 
 }  // namespace fftc

@@ -685,6 +685,14 @@ void launch_features(const FeatArgs& a, hipStream_t s) {
 
 using namespace nnk;
 
+// Training target of the learned start: t = (u* - u1) / s_u in FP32 (u* a converged solve,
+// u1 the first iterate the input channels carry).
+__global__ __launch_bounds__(256) void k_target(const double* __restrict__ u, const double* __restrict__ u1, long long n,
+                                                double inv_su, float* __restrict__ t) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    t[e] = (float)((u[e] - u1[e]) * inv_su);
+}
+
 struct fftc_nn {
   int m = 6, blocks = 4, M3 = 216, KP = 224, ksteps = 14;
   Offsets off{};
@@ -1117,6 +1125,16 @@ int fftc_nn_adam_step(fftc_nn_h nn, float lr, float beta1, float beta2, float ep
                      (const float*)nn->p, nn->off, nn->blocks, nn->img);
   NNCHK(nn, hipGetLastError());
   return FFTC_OK;
+}
+
+int fftc_nn_make_target(const double* u_dev, const double* u1_dev, int64_t count, double s_u, float* target_dev,
+                        void* stream) {
+  if (!u_dev || !u1_dev || !target_dev || count < 0 || !(s_u > 0.0)) return FFTC_E_ARG;
+  if (count == 0) return FFTC_OK;
+  const unsigned nb = (unsigned)std::min<long long>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_target, dim3(nb), dim3(256), 0, (hipStream_t)stream, u_dev, u1_dev, (long long)count,
+                     1.0 / s_u, target_dev);
+  return hipGetLastError() == hipSuccess ? FFTC_OK : FFTC_E_HIP;
 }
 
 const char* fftc_nn_last_error(fftc_nn_h nn) { return nn ? nn->err.c_str() : "null network"; }

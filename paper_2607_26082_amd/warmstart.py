@@ -74,7 +74,7 @@ def make_dataset(specs, n0=N0, log=_log):
         g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=4000)
         F.fftc_nn_features(g.h, feat[i], u1)
         rc, r = g.solve()
-        tgt[i].copy_(((g.u.reshape(3, Nn) - u1) / su).to(torch.float32))
+        F.fftc_nn_make_target(g.u.reshape(3, Nn), u1, su, tgt[i], g.stream.cuda_stream)
         ok[i] = r.status == 0
         iters[i] = r.iterations
         del g

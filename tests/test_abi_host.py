@@ -126,18 +126,20 @@ def test_scheme_and_reference_validation():
     if torch.cuda.is_available():
         pytest.skip("passes a placeholder workspace address: run where no device is visible")
     fake = C.c_void_p(1 << 20)             # never touched: the checks come first
-    h = F.fftc_create((8, 8, 8), F.FFTC_FP32)
-    F.fftc_set_scheme(h, F.FFTC_HEX1)
+    h = F.fftc_create((8, 8, 8), F.FFTC_FP32, scheme=F.FFTC_HEX1)
     assert F.load().fftc_bind_workspace(h, fake, 1 << 30, None) == F.FFTC_E_UNSUPPORTED
     F.fftc_destroy(h)
     h = F.fftc_create((8, 8, 8), F.FFTC_FP64)
     F.fftc_set_reference_factor(h, 1.0, F.FFTC_REF_ISO)
     assert F.load().fftc_bind_workspace(h, fake, 1 << 30, None) == F.FFTC_E_UNSUPPORTED   # TETRA2
-    F.fftc_set_scheme(h, F.FFTC_HEX1)
+    F.fftc_destroy(h)
+    h = F.fftc_create((8, 8, 8), F.FFTC_FP64, scheme=F.FFTC_HEX1)
+    F.fftc_set_reference_factor(h, 1.0, F.FFTC_REF_ISO)
     assert F.load().fftc_bind_workspace(h, fake, 1 << 30, None) == F.FFTC_E_UNSUPPORTED   # not periodic
-    assert _code(F.fftc_set_scheme, h, 7) == F.FFTC_E_ARG
     assert _code(F.fftc_set_reference, h, 1.0, 1.0, 5) == F.FFTC_E_ARG
     F.fftc_destroy(h)
+    assert _code(F.fftc_create, (8, 8, 8), F.FFTC_FP64, 1.0, 7) == F.FFTC_E_UNSUPPORTED     # unknown scheme
+    assert _code(F.fftc_create, (8, 8, 8), F.FFTC_FP64, 0.0) == F.FFTC_E_ARG                # voxel size
 
 
 def test_workspace_sizes_grow_with_the_grid_and_precision():
