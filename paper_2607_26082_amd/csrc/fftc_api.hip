@@ -645,8 +645,12 @@ int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
   const ContactDev ct = contact_dev(h);
   const StrongDev sd = strong_dev(h);
   HIPCHK(h, hipMemcpyAsync(&h->last, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  std::vector<double> msp;
   if (h->delta_mode) {
     DeltaBufs<float> D = dbufs(h);
+    // the residual-form pass carries only the norms; the mean stress is formed here, once
+    msp.assign(6 * (size_t)launch_mean_stress_d<float>(h->g, D, h->part, s), 0.0);
+    HIPCHK(h, hipMemcpyAsync(msp.data(), h->part, 8 * msp.size(), hipMemcpyDeviceToHost, s));
     launch_reactions_d<float>(h->g, D, sd, h->sreact, s);
     if (u_dev && h->hlen != 1.0) launch_convert<double, double>(D.u, u_dev, n3, s, h->hlen);
     else if (u_dev) HIPCHK(h, hipMemcpyAsync(u_dev, D.u, 8 * n3, hipMemcpyDeviceToDevice, s));
@@ -671,6 +675,14 @@ int solve_finish(fftc_problem* h, double* u_dev, fftc_report* rep) {
   std::vector<double> cf(2 * 64, 0.0);
   if (ct.on) HIPCHK(h, hipMemcpyAsync(cf.data(), h->chk, 8 * cf.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  if (!msp.empty()) {
+    const size_t nb = msp.size() / 6;
+    for (int q = 0; q < 6; ++q) {
+      double a = 0.0;
+      for (size_t b = 0; b < nb; ++b) a += msp[6 * b + q];
+      h->last.ms[q] = a;
+    }
+  }
   const double h2 = h->hlen * h->hlen;   // forces: voxel units -> physical
   for (double& v : h->react_strong) v *= h2;
   for (double& v : h->react_weak) v *= h2;

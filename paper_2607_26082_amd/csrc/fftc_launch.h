@@ -28,6 +28,10 @@ void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, do
 template <typename T>
 void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, const WeakDev& w,
                        const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s);
+// Mean stress of the residual-form iterate: per-block sums of the six components (xx, yy, zz,
+// yz, xz, xy) times the voxel volume, rows of 6 in part; returns the number of rows.
+template <typename T>
+int launch_mean_stress_d(const Geo& g, const DeltaBufs<T>& D, double* part, hipStream_t s);
 template <typename T>
 void launch_reactions_d(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, double* out, hipStream_t s);
 template <typename T>

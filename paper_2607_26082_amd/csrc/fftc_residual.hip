@@ -181,7 +181,8 @@ __device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, b
   }
 }
 
-template <typename T>
+// GEN = false: no rigid obstacle and no singular modes (both checked by the launcher).
+template <typename T, bool GEN>
 __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, int cur,
                                            bool kd_used, int il, int slot, T* pc, T* Rc, int i, int j, int k,
                                            long long node, T p[3], const T kd[3], const TailIn<T>& tin,
@@ -191,13 +192,13 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
   // singular-mode coefficients of u (projection Pi of the update)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (!g.sing[c]) continue;
+    if (!GEN || !g.sing[c]) continue;
     const double wu = sing_weight(g, xyz) * D.u[c * Nn + node];
     acc[8 + 2 * c] += wu;
     if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
   }
   const uint8_t m = tin.m;
-  if (ct.on && (m & M_FACE)) {
+  if (GEN && ct.on && (m & M_FACE)) {
     const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
     const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
     const double d0 = X0 - ct.center[0], d1 = X1 - ct.center[1], d2 = X2 - ct.center[2];
@@ -271,13 +272,11 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
     node_eval_d<T, true, FS>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
     acc[1] += sn;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) acc[2 + q] += ms[q];
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
     TailIn<T> tin;
     tail_load<T>(D, Nn, kd_used, il, pp, Rp, node, tin);
-    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
+    delta_tail<T, true>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
   }
   block_sum<kPartStrideD>(acc, sh);
   if (threadIdx.x == 0)
@@ -303,14 +302,16 @@ constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
 // slot of node plane p in the four-plane ring of delta planes (p may be -1)
 __device__ __forceinline__ int ring4(int p) { return p & 3; }
 
-template <typename T, bool FS>
+template <typename T, bool FS, bool GEN>
 __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, TileGrid tg) {
   constexpr int NQ = FS ? 9 : 6;      // stored stress components per tetrahedron (PK1: all nine)
   __shared__ double su[2][3][kHY][kHX];
   __shared__ T sdl[4][3][kHY][kHX];
   __shared__ T ss[2][2 * NQ][kVY][kVX];   // stress component q of the voxels of a layer
-  __shared__ double sh[kPartStrideD * 16];
+  // the final block sum reuses the stress buffer (block_sum starts with a barrier)
+  static_assert(sizeof(ss) >= sizeof(double) * kPartStrideD * 16, "block-sum scratch");
+  double* sh = reinterpret_cast<double*>(&ss[0][0][0][0]);
   if (st->done) return;
   const int tid = threadIdx.x;
   // contiguous ranges of tiles per XCD (blocks go to the 8 XCDs round-robin), so that
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         }
       }
       const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
-      T vs[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+      T vs = T(0);
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         T G[3][3];
@@ -463,13 +464,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) vs[0] += P[r][c] * P[r][c];
-            vs[1] += P[0][0];
-            vs[2] += P[1][1];
-            vs[3] += P[2][2];
-            vs[4] += P[1][2];
-            vs[5] += P[0][2];
-            vs[6] += P[0][1];
+              for (int c = 0; c < 3; ++c) vs += P[r][c] * P[r][c];
           }
           continue;
         }
@@ -486,20 +481,10 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         out[t * 6 + 3][ly][lx] = s01;
         out[t * 6 + 4][ly][lx] = s02;
         out[t * 6 + 5][ly][lx] = s12;
-        if (own) {
-          // the voxel's two tetrahedra in T, added to the FP64 block sums once per voxel
-          vs[0] += s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
-          vs[1] += s00;
-          vs[2] += s11;
-          vs[3] += s22;
-          vs[4] += s12;
-          vs[5] += s02;
-          vs[6] += s01;
-        }
+        // the voxel's two tetrahedra in T, added to the FP64 block sum once per voxel
+        if (own) vs += s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
       }
-      if (own)
-#pragma unroll
-        for (int q = 0; q < 7; ++q) acc[1 + q] += 0.5 * (double)vs[q];
+      if (own) acc[1] += 0.5 * (double)vs;
     }
   };
   const int nlx = tid % kTX, nly = tid / kTX;
@@ -539,7 +524,9 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     if (kd_used) {
       const int zm = ring4(z - 1), z0 = ring4(z), zp = ring4(z + 1);
       const int hx = lx + 1, hy = ly + 1;
-#pragma unroll
+      // one component at a time: keeps the 13 LDS reads of a component, not all 39, in
+      // flight (194 -> 155 VGPRs, three waves per SIMD instead of two)
+#pragma unroll 1
       for (int c = 0; c < 3; ++c) {
         const T sxy = sdl[z0][c][hy - 1][hx - 1] + sdl[z0][c][hy - 1][hx + 1] + sdl[z0][c][hy + 1][hx - 1] +
                       sdl[z0][c][hy + 1][hx + 1];
@@ -552,7 +539,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       }
     }
     const long long node = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * z);
-    delta_tail<T>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
+    delta_tail<T, GEN>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
   };
 
   T lcur, mcur, lnext, mnext;
@@ -591,6 +578,86 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   if (threadIdx.x == 0)
 #pragma unroll
     for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+}
+
+// Mean stress of the residual-form iterate, once, when the solve is reported: per voxel the
+// stresses of its two tetrahedra as the tiled residual pass forms them (differences of the
+// FP64 displacement against corner 000, rounded to T; the stress arithmetic in T), added in T
+// and weighted by the integration-point weight 1/2 into FP64 block sums.  Components in the
+// order xx, yy, zz, yz, xz, xy (first Piola-Kirchhoff for finite strain).
+template <typename T, bool FS>
+__global__ __launch_bounds__(kBlock) void k_mean_stress_d(Geo g, const double* __restrict__ u,
+                                                          const T* __restrict__ lam, const T* __restrict__ mu,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[6 * 16];
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int nx = g.n[0], ny = g.n[1];
+  const long long Nn = g.Nn;
+  long long lo, hi;
+  xcd_chunk(g.Nv, lo, hi);
+  for (long long v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+    const int vx = (int)(v % nx);
+    const long long r = v / nx;
+    const int vy = (int)(r % ny), vz = (int)(r / ny);
+    double uc[8][3];
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      int x = vx + (cc & 1), y = vy + ((cc >> 1) & 1), z = vz + ((cc >> 2) & 1);
+      if (x == g.N[0]) x = 0;   // only on a periodic axis, where there are n nodes
+      if (y == g.N[1]) y = 0;
+      if (z == g.N[2]) z = 0;
+      const long long node = (long long)x + (long long)g.N[0] * ((long long)y + (long long)g.N[1] * z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uc[cc][c] = u[c * Nn + node];
+    }
+    const T l = lam[v], m = mu[v];
+    T vs[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      T G[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G[a][b] = T(0);
+#pragma unroll
+      for (int cc = 1; cc < 8; ++cc) {
+        const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+        if (((cx + cy + cz) & 1) != t) continue;
+        const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const T d = (T)(uc[cc][a] - uc[0][a]);
+          G[a][0] += sx * d;
+          G[a][1] += sy * d;
+          G[a][2] += sz * d;
+        }
+      }
+      if constexpr (FS) {
+        T P[3][3];
+        svk_pk1<T>(G, l, m, P);
+        vs[0] += P[0][0];
+        vs[1] += P[1][1];
+        vs[2] += P[2][2];
+        vs[3] += P[1][2];
+        vs[4] += P[0][2];
+        vs[5] += P[0][1];
+      } else {
+        const T tr = G[0][0] + G[1][1] + G[2][2];
+        vs[0] += l * tr + T(2) * m * G[0][0];
+        vs[1] += l * tr + T(2) * m * G[1][1];
+        vs[2] += l * tr + T(2) * m * G[2][2];
+        vs[3] += m * (G[1][2] + G[2][1]);
+        vs[4] += m * (G[0][2] + G[2][0]);
+        vs[5] += m * (G[0][1] + G[1][0]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] += 0.5 * (double)vs[q];
+  }
+  block_sum<6>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) part[blockIdx.x * 6 + q] = acc[q];
 }
 
 // proj_P of the relations on several nodes (eq 14, eq 17) on p and on the quantities linear
@@ -812,12 +879,23 @@ int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
   const TileGrid tg = residual_tiles(g);
   if (tg.tx > 0) {
     nblk = tg.tx * tg.ty * tg.nseg;
-    if (g.fs) hipLaunchKernelGGL((k_residual_dt<T, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
-    else hipLaunchKernelGGL((k_residual_dt<T, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
+    if (g.fs && gen) hipLaunchKernelGGL((k_residual_dt<T, true, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else if (g.fs) hipLaunchKernelGGL((k_residual_dt<T, true, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else if (gen) hipLaunchKernelGGL((k_residual_dt<T, false, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else hipLaunchKernelGGL((k_residual_dt<T, false, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
   } else {
     if (g.fs) hipLaunchKernelGGL((k_residual_d<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
     else hipLaunchKernelGGL((k_residual_d<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
   }
+  return nblk;
+}
+
+template <typename T>
+int launch_mean_stress_d(const Geo& g, const DeltaBufs<T>& D, double* part, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, (g.Nv + kBlock - 1) / kBlock));
+  if (g.fs) hipLaunchKernelGGL((k_mean_stress_d<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, D.u, D.lam, D.mu, part);
+  else hipLaunchKernelGGL((k_mean_stress_d<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, D.u, D.lam, D.mu, part);
   return nblk;
 }
 
@@ -837,7 +915,7 @@ static int residual_resident() {
   int r = cache[dev].load(std::memory_order_relaxed);
   if (!r) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -911,6 +989,7 @@ template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, c
 template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
 template void launch_delta_proj<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, const WeakDev&,
                                        const ContactDev&, DevState*, int, int, hipStream_t);
+template int launch_mean_stress_d<float>(const Geo&, const DeltaBufs<float>&, double*, hipStream_t);
 template void launch_reactions_d<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, double*, hipStream_t);
 
 }  // namespace fftc

@@ -87,3 +87,25 @@ def test_stage_residual_form(idx, il):
             dYe = pe - p_prev + k0d
             assert np.abs(dR - dRe)[free].max() <= tol * np.abs(dRe).max()
             assert np.abs(dY - dYe)[free].max() <= tol * np.abs(dYe).max()
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_mean_stress_of_returned_iterate(idx):
+    """The FP32 form reports the mean stress of the iterate it returns, formed once at the end:
+    compared with the oracle's volume average of the stress (PK1 in finite strain) of that same
+    FP64 displacement, on heterogeneous cells with and without a periodic axis.  The solve is
+    cut after a few iterations so that the field is far from any closed form."""
+    F = _lib()
+    n, per, fs = SHAPES[idx]
+    print(f"[mean stress] n={n} periodic={per} finite_strain={fs}", flush=True)
+    lam, mu, bc, strong, avg = _case(70 + idx, n, per)
+    g = F.Solver(n, lam, mu, bc, strong, avg, r0_factor=1.3, precision="fp32", finite_strain=fs, max_iter=12)
+    rc, rep = g.solve()
+    assert rep.iterations <= 12 and np.isfinite(rep.residual)
+    o = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.3, finite_strain=fs)
+    u = g.u.cpu().numpy().reshape(o.zeros().shape)
+    sig = o.iterate_parts(u)["sig"]
+    M = tetra2.mean_stress(sig)
+    want = np.array([M[0, 0], M[1, 1], M[2, 2], M[1, 2], M[0, 2], M[0, 1]])
+    scale = np.abs(sig).mean()
+    assert np.abs(np.array(rep.mean_stress) - want).max() <= 2e-6 * scale
