@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfftc.so")
+# FFTC_LIB may name another build of the same sources (the host-sanitized one)
+LIB_PATH = os.environ.get("FFTC_LIB") or os.path.join(_HERE, "libfftc.so")
 
 FFTC_OK = 0
 FFTC_E_ARG, FFTC_E_BC, FFTC_E_OVERLAP, FFTC_E_WORKSPACE = -1, -2, -3, -4
