@@ -60,20 +60,36 @@ def bonded_layer_factor(nu, chi):
             - 8.0 / np.pi ** 3 * (a0 ** 3 + 4.0 * np.pi ** 2 / 15.0 * b0) * chi ** 3)
 
 
-def test_c3_hertz_indentation_fp32():
+_C3 = {}
+
+
+def _c3_run(prec):
+    """The ten C3 increments in one precision: per increment the report, the active set and the
+    face fields (kept for the FP32 / FP64 active-set comparison)."""
+    if prec in _C3:
+        return _C3[prec]
     F = _lib()
     n, R = (256, 256, 128), 96.0
     prob = W.c3_indentation(n=n, R=R, d_over_R=0.002)
-    g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=20000)
-    rows = []
+    g = F.Solver.from_problem(prob, precision=prec, tol=1e-6, max_iter=20000)
+    out = []
     for k in range(1, 11):
         d = 0.002 * k * R
         g.move_sphere(np.array([n[0] / 2.0, n[1] / 2.0, n[2] + R - d]))
         rc, rep = g.solve(zero_start=(k == 1))
-        assert rc == 0, (k, rc)
+        assert rc == 0, (prec, k, rc)
         mask, fnc, gap = g.contact()
-        C = mask.reshape(-1).astype(bool)
-        fnc, gap = fnc.reshape(-1), gap.reshape(-1)
+        out.append((d, rep, mask.reshape(-1).astype(bool), fnc.reshape(-1).copy(), gap.reshape(-1).copy()))
+        print(f"[c3] {prec} d/R={d / R:.3f} it={rep.iterations} updates={rep.contact_updates} "
+              f"F={rep.force_contact:.6e} |C|={int(out[-1][2].sum())}", flush=True)
+    _C3[prec] = out
+    return out
+
+
+def _c3_check(prec):
+    n, R = (256, 256, 128), 96.0
+    rows = []
+    for d, rep, C, fnc, gap in _c3_run(prec):
         FH = hertz_force(1.0, 0.3, R, d)
         aH = hertz_radius(R, d)
         corr = bonded_layer_factor(0.3, aH / n[2])
@@ -83,7 +99,7 @@ def test_c3_hertz_indentation_fp32():
                    and (fnc[C] <= 1e-6 * fmax).all())
         rows.append(dict(dR=d / R, it=rep.iterations, F=rep.force_contact, Fs=rep.force_mean_stress,
                          ratio=rep.force_contact / FH, corr=corr, a=a_eq, aH=aH, kkt=kkt))
-        print(f"[c3] d/R={d / R:.3f} it={rep.iterations} F={rep.force_contact:.5e} "
+        print(f"[c3] {prec} d/R={d / R:.3f} it={rep.iterations} F={rep.force_contact:.5e} "
               f"F_sigma={rep.force_mean_stress:.5e} F/F_H={rep.force_contact / FH:.4f} "
               f"layer-corrected {corr:.4f} a={a_eq:.2f} a_H={aH:.2f} kkt={kkt}", flush=True)
     for r in rows:
@@ -92,3 +108,24 @@ def test_c3_hertz_indentation_fp32():
         assert abs(r["ratio"] / r["corr"] - 1) <= 0.02, r
         if r["dR"] >= 0.006 - 1e-12:
             assert abs(r["a"] - r["aH"]) <= 1.0, r
+
+
+def test_c3_hertz_indentation_fp32():
+    _c3_check("fp32")
+
+
+def test_c3_hertz_indentation_fp64_and_active_sets():
+    """The plain FP64 method on the same ten increments passes the same checks, and its active
+    sets equal the FP32 form's outside the band of degenerate nodes (|g| <= 1e-5 R and
+    |f_nc| <= 1e-5 max |f_nc|, where several sets are correct); flips inside it are printed."""
+    _c3_check("fp64")
+    R = 96.0
+    for (d, r64, C64, f64, g64), (_, r32, C32, f32, g32) in zip(_c3_run("fp64"), _c3_run("fp32")):
+        diff = C64 != C32
+        fmax = np.abs(f64[C64]).max()
+        band = (np.abs(g64) <= 1e-5 * R) & (np.abs(f64) <= 1e-5 * fmax)
+        print(f"[c3] d/R={d / R:.3f} |C| fp64 {int(C64.sum())} fp32 {int(C32.sum())}, flips in band "
+              f"{int((diff & band).sum())}, outside {int((diff & ~band).sum())}; "
+              f"F fp32/fp64 - 1 = {r32.force_contact / r64.force_contact - 1:.2e}", flush=True)
+        assert not (diff & ~band).any(), d
+        assert abs(r32.force_contact / r64.force_contact - 1) <= 1e-4
