@@ -31,9 +31,9 @@ def stage_bytes(N, nv, precision):
     if precision == "fp32":
         f = 3 * N * 4
         return {
-            # read u (FP64), delta, e, R_prev, p_prev, lam, mu; write p, R, dR, dY
-            "residual": 2 * f + 5 * f + 2 * nv * 4 + 4 * f,
-            "anderson": 4 * f / 2,             # read dR x3, R (accelerating iterations)
+            # read u (FP64), delta, e, p_prev, lam, mu; write p, R, dY
+            "residual": 2 * f + 3 * f + 2 * nv * 4 + 3 * f,
+            "anderson": 4 * f / 2,             # read the ring of four R (accelerating iterations)
             "dtt_x_fwd": f + 3 * f / 2 + 2 * f,  # read p, dY x3 (accelerating); write e, t
             "dtt_y_fwd": 2 * f, "dtt_z_green": 2 * f, "dtt_y_inv": 2 * f,
             "dtt_x_inv": f + 2 * f + 2 * f + f,  # read t, u (FP64); write u (FP64), delta

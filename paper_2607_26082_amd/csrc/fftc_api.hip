@@ -64,7 +64,7 @@ struct fftc_problem {
   int nlit = 10;       // literal fields carved at binding
   int static_dev = -1; // device whose static workspace is bound, else -1
   // residual-form (FP32) fields: delta, e, p0, p1, R0, R1, dR0..2, dY0..2, t; FP64 u
-  void* dfld[13] = {};
+  void* dfld[12] = {};
   double* u64 = nullptr;
   int delta_mode = 0;
   void* lam = nullptr;
@@ -245,7 +245,7 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(8 * nface);
   off[q++] = L.take(8 * (ms + 1));
   off[q++] = L.take(sizeof(double) * 3 * 1024);
-  const int nd = h->precision == FFTC_FP32 ? 13 : 0;
+  const int nd = h->precision == FFTC_FP32 ? 12 : 0;
   for (int i = 0; i < nd; ++i) off[q++] = L.take(4 * 3 * (size_t)h->Nn);
   if (nd) off[q++] = L.take(8 * 3 * (size_t)h->Nn);
   if (base) {
@@ -323,13 +323,9 @@ DeltaBufs<float> dbufs(fftc_problem* h) {
   D.e = (float*)h->dfld[1];
   D.p[0] = (float*)h->dfld[2];
   D.p[1] = (float*)h->dfld[3];
-  D.R[0] = (float*)h->dfld[4];
-  D.R[1] = (float*)h->dfld[5];
-  for (int q = 0; q < 3; ++q) {
-    D.dR[q] = (float*)h->dfld[6 + q];
-    D.dY[q] = (float*)h->dfld[9 + q];
-  }
-  D.t = (float*)h->dfld[12];
+  for (int q = 0; q < 4; ++q) D.R[q] = (float*)h->dfld[4 + q];
+  for (int q = 0; q < 3; ++q) D.dY[q] = (float*)h->dfld[8 + q];
+  D.t = (float*)h->dfld[11];
   D.lam = (const float*)h->lam;
   D.mu = (const float*)h->mu;
   D.mask = h->mask;
@@ -593,7 +589,7 @@ int init_delta(fftc_problem* h, const double* u_dev, int zero_start) {
   const ContactDev ct = contact_dev(h);
   if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
   launch_delta_proj<float>(h->g, D, strong_dev(h), weak_dev(h), ct, h->st, 1, 0, s);
-  for (int q = 0; q < 12; ++q) HIPCHK(h, hipMemsetAsync(h->dfld[q], 0, 4 * n3, s));
+  for (int q = 0; q < 11; ++q) HIPCHK(h, hipMemsetAsync(h->dfld[q], 0, 4 * n3, s));
   return init_state(h);
 }
 
@@ -765,15 +761,14 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, doub
   const long long n3 = 3 * h->Nn;
   const int slot = (il + 1) % 3;
   HIPCHK(h, hipMemcpyAsync(D.u, in[0], 8 * n3, hipMemcpyDeviceToDevice, s));
-  float* dst[4] = {D.delta, D.e, D.p[1], D.R[1]};
+  float* const Rcur = D.R[il & 3];
+  float* const Rprev = D.R[(il + 3) & 3];
+  float* dst[4] = {D.delta, D.e, D.p[1], Rprev};
   for (int q = 0; q < 4; ++q) {
     if (in[q + 1]) launch_convert<double, float>(in[q + 1], dst[q], n3, s);
     else HIPCHK(h, hipMemsetAsync(dst[q], 0, 4 * n3, s));
   }
-  for (int q = 0; q < 3; ++q) {
-    HIPCHK(h, hipMemsetAsync(D.dR[q], 0, 4 * n3, s));
-    HIPCHK(h, hipMemsetAsync(D.dY[q], 0, 4 * n3, s));
-  }
+  for (int q = 0; q < 3; ++q) HIPCHK(h, hipMemsetAsync(D.dY[q], 0, 4 * n3, s));
   DevState hs{};
   hs.acv = FFTC_ACV_P;
   hs.i_local = il;
@@ -789,7 +784,9 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, doub
   if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
   const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, s);
   launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
-  const float* src[4] = {D.p[0], D.R[0], D.dR[slot], D.dY[slot]};
+  // R difference as the Gram pass forms it, from the R ring (staged in the transform buffer)
+  if (out[2]) launch_diff<float>(Rcur, Rprev, D.t, n3, s);
+  const float* src[4] = {D.p[0], Rcur, D.t, D.dY[slot]};
   for (int q = 0; q < 4; ++q)
     if (out[q]) launch_convert<float, double>(src[q], out[q], n3, s);
   if (sums) {

@@ -177,8 +177,7 @@ struct DeltaBufs {
   T* delta;                  // u_i - u_{i-1}
   T* e;                      // Green input of the last iteration
   T* p[2];                   // residual after proj_P (ping-pong by iteration parity)
-  T* R[2];                   // R_i = p_i + K0 delta_i - e_{i-1} (ping-pong)
-  T* dR[3];                  // R differences (ring of 3)
+  T* R[4];                   // R_i = p_i + K0 delta_i - e_{i-1}, ring by local iteration (i & 3)
   T* dY[3];                  // Y differences (ring of 3)
   T* t;                      // transform buffer
   const T* lam;

@@ -28,6 +28,9 @@ void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, do
 template <typename T>
 void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd, const WeakDev& w,
                        const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s);
+// out = a - b elementwise (FP32 R differences for the stage entry)
+template <typename T>
+void launch_diff(const T* a, const T* b, T* out, long long n, hipStream_t s);
 // Mean stress of the residual-form iterate: per-block sums of the six components (xx, yy, zz,
 // yz, xz, xy) times the voxel volume, rows of 6 in part; returns the number of rows.
 template <typename T>

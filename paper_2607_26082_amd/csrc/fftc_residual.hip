@@ -154,29 +154,27 @@ __device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
 // Per-node part of the residual pass of the residual-form iteration, once p is known:
 // singular-mode coefficients of u, contact bookkeeping or constraint masking, the norm of
 // p, p itself, and (ACV_P, from the second iteration on) R_i = p_i + K0 delta_i - e_{i-1}
-// with its differences.  kd = K0 delta at the node (read only when kd_used).
-// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}, R_{i-1}.
+// and dY_i = p_i - p_{i-1} + K0 delta_i.  The R differences are not stored: R_i goes to a
+// ring of four, from which the Gram pass forms them with the same FP32 subtraction.
+// kd = K0 delta at the node (read only when kd_used).
+// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}.
 template <typename T>
 struct TailIn {
   uint8_t m;
-  T e[3], pp[3], rp[3];
+  T e[3], pp[3];
 };
 
 template <typename T>
 __device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, const T* pp,
-                                          const T* Rp, long long node, TailIn<T>& t) {
+                                          long long node, TailIn<T>& t) {
   t.m = D.mask[node];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     t.e[c] = T(0);
     t.pp[c] = T(0);
-    t.rp[c] = T(0);
     if (kd_used) {
       t.e[c] = D.e[c * Nn + node];
-      if (il >= 2) {
-        t.pp[c] = pp[c * Nn + node];
-        t.rp[c] = Rp[c * Nn + node];
-      }
+      if (il >= 2) t.pp[c] = pp[c * Nn + node];
     }
   }
 }
@@ -233,12 +231,8 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
       // At a DOF held at 0 by a Dirichlet face p is 0 and K0 delta is taken from the
       // symmetric image; the transforms drop these entries, but they stay in the Gram matrix
       // of the differences (measured: zeroing them makes the FP32 least squares less robust).
-      const T Ri = p[c] + kd[c] - tin.e[c];
-      Rc[e] = Ri;
-      if (il >= 2) {
-        D.dR[slot][e] = Ri - tin.rp[c];
-        D.dY[slot][e] = p[c] - tin.pp[c] + kd[c];
-      }
+      Rc[e] = p[c] + kd[c] - tin.e[c];
+      if (il >= 2) D.dY[slot][e] = p[c] - tin.pp[c] + kd[c];
     }
   }
 }
@@ -259,8 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
   const bool kd_used = acvp && il >= 1;
   T* pc = D.p[par];
   const T* pp = D.p[par ^ 1];
-  T* Rc = D.R[par];
-  const T* Rp = D.R[par ^ 1];
+  T* Rc = D.R[il & 3];
   long long lo, hi;
   xcd_chunk(Nn, lo, hi);
   for (long long node = lo + threadIdx.x; node < hi; node += blockDim.x) {
@@ -275,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
     TailIn<T> tin;
-    tail_load<T>(D, Nn, kd_used, il, pp, Rp, node, tin);
+    tail_load<T>(D, Nn, kd_used, il, pp, node, tin);
     delta_tail<T, true>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
   }
   block_sum<kPartStrideD>(acc, sh);
@@ -335,8 +328,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   const bool kd_used = acvp && il >= 1;
   T* pc = D.p[par];
   const T* pp = D.p[par ^ 1];
-  T* Rc = D.R[par];
-  const T* Rp = D.R[par ^ 1];
+  T* Rc = D.R[il & 3];
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
@@ -567,7 +559,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
     if (nact) {
       const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
-      tail_load<T>(D, g.Nn, kd_used, il, pp, Rp, node, tin);
+      tail_load<T>(D, g.Nn, kd_used, il, pp, node, tin);
     }
     __syncthreads();
     layer(z, true, lcur, mcur, okcur);
@@ -661,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_mean_stress_d(Geo g, const double* _
 }
 
 // proj_P of the relations on several nodes (eq 14, eq 17) on p and on the quantities linear
-// in p (R, and the differences dR, dY): one wavefront per relation, one lane per support node.
+// in p (R, and the difference dY): one wavefront per relation, one lane per support node.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st) {
   if (st->done) return;
@@ -699,11 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
     const T sh = (T)(wb * f * scale);
     D.p[par][e] = (T)pnew;
     if (acvp && il >= 1) {
-      D.R[par][e] -= sh;
-      if (il >= 2) {
-        D.dR[slot][e] -= sh;
-        D.dY[slot][e] -= sh;
-      }
+      D.R[il & 3][e] -= sh;
+      if (il >= 2) D.dY[slot][e] -= sh;
     }
   }
   if (lane == 0) {
@@ -712,17 +701,29 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
   }
 }
 
-// Gram matrix of the R differences and their products with R_i (accelerating iterations)
+// Gram matrix of the R differences and their products with R_i (accelerating iterations).
+// The difference formed at local iteration j >= 2, R_j - R_{j-1} (FP32), pairs with the Y
+// difference in slot (j + 1) mod 3; the three latest, j = i, i-1, i-2, come from the ring of
+// four R fields (acceleration starts at i = 4, so all four are of the current run).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gram3(DeltaBufs<T> D, long long n3, DevState* st, double* __restrict__ gpart) {
   __shared__ double sh[9 * 16];
   if (st->done || !st->accel) return;
-  const T* Ri = D.R[st->it & 1];
+  const int il = st->i_local;
+  const T* Ri = D.R[il & 3];
+  const T *Ra[3], *Rb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int j = il - k, slot = (j + 1) % 3;
+    Ra[slot] = D.R[j & 3];
+    Rb[slot] = D.R[(j + 3) & 3];
+  }
   double acc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n3; e += (long long)gridDim.x * blockDim.x) {
-    const double a0 = D.dR[0][e], a1 = D.dR[1][e], a2 = D.dR[2][e], r = Ri[e];
+    const T d0 = Ra[0][e] - Rb[0][e], d1 = Ra[1][e] - Rb[1][e], d2 = Ra[2][e] - Rb[2][e];
+    const double a0 = d0, a1 = d1, a2 = d2, r = Ri[e];
     acc[0] += a0 * a0; acc[1] += a0 * a1; acc[2] += a0 * a2;
     acc[3] += a1 * a1; acc[4] += a1 * a2; acc[5] += a2 * a2;
     acc[6] += a0 * r; acc[7] += a1 * r; acc[8] += a2 * r;
@@ -892,6 +893,19 @@ int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diff(const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ out,
+                                                 long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = a[e] - b[e];
+}
+
+template <typename T>
+void launch_diff(const T* a, const T* b, T* out, long long n, hipStream_t s) {
+  const int nblk = (int)std::max<long long>(1, std::min<long long>(4096, (n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_diff<T>, dim3(nblk), dim3(kBlock), 0, s, a, b, out, n);
+}
+
+template <typename T>
 int launch_mean_stress_d(const Geo& g, const DeltaBufs<T>& D, double* part, hipStream_t s) {
   const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, (g.Nv + kBlock - 1) / kBlock));
   if (g.fs) hipLaunchKernelGGL((k_mean_stress_d<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, D.u, D.lam, D.mu, part);
@@ -989,6 +1003,7 @@ template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, c
 template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
 template void launch_delta_proj<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, const WeakDev&,
                                        const ContactDev&, DevState*, int, int, hipStream_t);
+template void launch_diff<float>(const float*, const float*, float*, long long, hipStream_t);
 template int launch_mean_stress_d<float>(const Geo&, const DeltaBufs<float>&, double*, hipStream_t);
 template void launch_reactions_d<float>(const Geo&, const DeltaBufs<float>&, const StrongDev&, double*, hipStream_t);
 
