@@ -31,10 +31,11 @@ def stage_bytes(N, nv, precision):
     if precision == "fp32":
         f = 3 * N * 4
         return {
-            # read u (FP64), delta, e, p_prev, lam, mu; write p, R, dY
-            "residual": 2 * f + 3 * f + 2 * nv * 4 + 3 * f,
+            # read u (FP64), delta, p_prev, e (after accelerating iterations), lam, mu; write p, R, dY
+            "residual": 2 * f + 2 * f + f / 2 + 2 * nv * 4 + 3 * f,
             "anderson": 4 * f / 2,             # read the ring of four R (accelerating iterations)
-            "dtt_x_fwd": f + 3 * f / 2 + 2 * f,  # read p, dY x3 (accelerating); write e, t
+            # read p, dY x3 (accelerating); write t, and e (accelerating)
+            "dtt_x_fwd": f + 3 * f / 2 + f + f / 2,
             "dtt_y_fwd": 2 * f, "dtt_z_green": 2 * f, "dtt_y_inv": 2 * f,
             "dtt_x_inv": f + 2 * f + 2 * f + f,  # read t, u (FP64); write u (FP64), delta
         }

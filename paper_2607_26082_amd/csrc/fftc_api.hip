@@ -773,6 +773,7 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, doub
   hs.acv = FFTC_ACV_P;
   hs.i_local = il;
   hs.it = 0;
+  hs.accel_ok = 1;   // e is the caller's, not p_prev
   hs.tol = 0.0;
   hs.max_iter = 1 << 30;
   hs.period = h->cfg.period;

@@ -277,10 +277,11 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
           if (a.store_s) a.B.S[slot][addr] = v;
         } else if (a.src == SRC_DELTA) {
           v = a.dp2[a.st->it & 1][addr];
-          if (a.st->accel_ok)
+          if (a.st->accel_ok) {
             v = v - ((T)a.st->gamma[0] * a.dY[0][addr] + (T)a.st->gamma[1] * a.dY[1][addr] +
                      (T)a.st->gamma[2] * a.dY[2][addr]);
-          a.de[addr] = v;
+            a.de[addr] = v;   // stored only when it differs from p
+          }
         } else {
           v = a.in[addr];
         }
@@ -505,13 +506,16 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
             g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
     const T *y0 = a.dY[0] + base, *y1 = a.dY[1] + base, *y2 = a.dY[2] + base;
     T* de = a.de + base;
+    // e is stored only when it differs from p (the next residual pass reads p otherwise)
     gather(
         [&](unsigned off) -> T {
           T v = pcur[off];
           if (acc_ok) v = v - (g0 * y0[off] + g1 * y1[off] + g2 * y2[off]);
           return v;
         },
-        [&](unsigned off, T v) { de[off] = v; });
+        [&](unsigned off, T v) {
+          if (acc_ok) de[off] = v;
+        });
   } else {
     const T* in = a.in + base;
     gather([&](unsigned off) -> T { return in[off]; }, [&](unsigned, T) {});

@@ -157,7 +157,9 @@ __device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
 // and dY_i = p_i - p_{i-1} + K0 delta_i.  The R differences are not stored: R_i goes to a
 // ring of four, from which the Gram pass forms them with the same FP32 subtraction.
 // kd = K0 delta at the node (read only when kd_used).
-// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}.
+// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}.  e_{i-1} is read
+// only when the last iteration combined its Anderson history (ecomb); otherwise it equals
+// p_{i-1}, which the transform pass then did not store.
 template <typename T>
 struct TailIn {
   uint8_t m;
@@ -165,15 +167,18 @@ struct TailIn {
 };
 
 template <typename T>
-__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, const T* pp,
-                                          long long node, TailIn<T>& t) {
+__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, int ecomb,
+                                          const T* pp, long long node, TailIn<T>& t) {
   t.m = D.mask[node];
+  // a uniform choice of source (no branch around the loads); when e is p_{i-1} the second
+  // load of the same address is served by the cache
+  const T* es = ecomb ? D.e : pp;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     t.e[c] = T(0);
     t.pp[c] = T(0);
     if (kd_used) {
-      t.e[c] = D.e[c * Nn + node];
+      t.e[c] = es[c * Nn + node];
       if (il >= 2) t.pp[c] = pp[c * Nn + node];
     }
   }
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
   const int Nx = g.N[0], Ny = g.N[1];
   const long long Nn = g.Nn;
   const int cur = ct.on ? st->vpar : 0;
-  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2), ecomb = st->accel_ok;
   const int slot = (il + 1) % 3;   // (il - 2) mod 3
   const bool kd_used = acvp && il >= 1;
   T* pc = D.p[par];
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
     TailIn<T> tin;
-    tail_load<T>(D, Nn, kd_used, il, pp, node, tin);
+    tail_load<T>(D, Nn, kd_used, il, ecomb, pp, node, tin);
     delta_tail<T, true>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
   }
   block_sum<kPartStrideD>(acc, sh);
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   const int ze = min(zb + tg.seg, Nz);
   const int Nn = (int)g.Nn;
   const int cur = ct.on ? st->vpar : 0;
-  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2);
+  const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2), ecomb = st->accel_ok;
   const int slot = (il + 1) % 3;
   const bool kd_used = acvp && il >= 1;
   T* pc = D.p[par];
@@ -559,7 +564,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
     if (nact) {
       const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
-      tail_load<T>(D, g.Nn, kd_used, il, pp, node, tin);
+      tail_load<T>(D, g.Nn, kd_used, il, ecomb, pp, node, tin);
     }
     __syncthreads();
     layer(z, true, lcur, mcur, okcur);
@@ -786,11 +791,21 @@ __global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* _
   st->accel_ok = ok ? 1 : 0;
 }
 
+// The iteration counters move on in the last kernel of an iteration (its first thread; the
+// other threads of that kernel read only the done flag), which saves a launch.
+__device__ __forceinline__ void advance_iteration(DevState* st, int advance) {
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    st->it += 1;
+    st->i_local += 1;
+  }
+}
+
 // proj_U of the residual-form path on the FP64 displacement; the increment follows
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_proj_d(Geo g, DeltaBufs<T> D, StrongDev s, WeakDev w, ContactDev ct,
-                                                   DevState* st, int force) {
+                                                   DevState* st, int force, int advance) {
   if (!force && st->done) return;
+  advance_iteration(st, advance);
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   // strong DOFs
   if (e < s.m) {
@@ -823,8 +838,10 @@ __global__ __launch_bounds__(kBlock) void k_proj_d(Geo g, DeltaBufs<T> D, Strong
 
 // proj_U of the relations (eq 11, eq 15) on the FP64 displacement, the increment follows
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_proj_rel_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st, int force) {
+__global__ __launch_bounds__(kBlock) void k_proj_rel_d(Geo g, DeltaBufs<T> D, WeakDev w, DevState* st, int force,
+                                                       int advance) {
   if (!force && st->done) return;
+  advance_iteration(st, advance);
   const long long r = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
   if (r >= w.m) return;
   const int lane = threadIdx.x & 63;
@@ -980,9 +997,12 @@ void launch_delta_proj(const Geo& g, const DeltaBufs<T>& D, const StrongDev& sd,
                        const ContactDev& ct, DevState* st, int force, int advance, hipStream_t s) {
   long long m = sd.m;
   if (ct.on && ct.nface > m) m = ct.nface;
-  if (m > 0) hipLaunchKernelGGL(k_proj_d<T>, dim3(grid_for(m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, w, ct, st, force);
-  if (w.m > 0) hipLaunchKernelGGL(k_proj_rel_d<T>, dim3(rel_grid(w.m)), dim3(kBlock), 0, s, g, D, w, st, force);
-  if (advance) hipLaunchKernelGGL(k_advance<T>, dim3(1), dim3(1), 0, s, st);
+  const int rel = w.m > 0;
+  if (m > 0)
+    hipLaunchKernelGGL(k_proj_d<T>, dim3(grid_for(m, 1 << 30)), dim3(kBlock), 0, s, g, D, sd, w, ct, st, force,
+                       advance && !rel);
+  if (rel) hipLaunchKernelGGL(k_proj_rel_d<T>, dim3(rel_grid(w.m)), dim3(kBlock), 0, s, g, D, w, st, force, advance);
+  if (advance && m == 0 && !rel) hipLaunchKernelGGL(k_advance<T>, dim3(1), dim3(1), 0, s, st);
 }
 
 template <typename T>

@@ -197,19 +197,16 @@ def test_contact_other_faces(face, prec):
 
     g = F.Solver(n, lam, mu, bc, sphere=W.Sphere(centre(0.0), R, face), r0_factor=5.0, precision=prec,
                  tol=1e-6 if prec == "fp32" else 1e-12)
-    # FP32 bar: 1e-5, or twice the distance from the oracle's own solution stopped at the same
-    # 1e-6 residual to its converged one where the body's conditioning makes that larger
-    # (the y = max face here: 2.4e-5 and 2.0e-5)
+    # FP32: parity bar of _fp32_check (on the y = max face the oracle stopped at 1e-6 is itself
+    # 2.4e-5 and 2.0e-5 from its converged solution)
     cs6 = ContactSolver(n, lam, mu, bc, face=face, radius=R, r0_factor=5.0) if prec == "fp32" else None
     u_o = u_6 = None
     for k in range(1, 3):
         c = centre(0.01 * k * R)
         o = cs.solve_increment(u_o, c, tol=1e-12 if prec == "fp64" else 1e-11)
         u_o = o["u"]
-        tol = 1e-10
         if prec == "fp32":
             u_6 = cs6.solve_increment(u_6, c, tol=1e-6)["u"]
-            tol = max(1e-5, 2.0 * np.linalg.norm(u_6 - u_o) / np.linalg.norm(u_o))
         g.move_sphere(c)
         rc, rep = g.solve(zero_start=(k == 1))
         assert rc == 0
@@ -217,9 +214,10 @@ def test_contact_other_faces(face, prec):
         assert o["C"].sum() > 0
         assert np.array_equal(mask.reshape(-1).astype(bool), o["C"])
         u = g.u.cpu().numpy()
-        print(f"[contact face {face}] {prec} increment {k}: rel-L2 {np.linalg.norm(u - u_o) / np.linalg.norm(u_o):.2e} "
-              f"(bar {tol:.1e})", flush=True)
-        assert np.linalg.norm(u - u_o) <= tol * np.linalg.norm(u_o)
+        if prec == "fp32":
+            _fp32_check(f"contact face {face} increment {k}", u, u_o, u_6)
+        else:
+            assert np.linalg.norm(u - u_o) <= 1e-10 * np.linalg.norm(u_o)
         assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
 
 
@@ -298,7 +296,7 @@ def test_periodic_solves(case, prec):
         assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()
     else:
         o6 = OSolver(n, lam, mu, bc, strong, avg, r0_factor=1.5).solve(tol=1e-6, max_iter=8000)
-        assert np.linalg.norm(u - o["u"]) <= _fp32_bar(o6["u"], o["u"]) * np.linalg.norm(o["u"])
+        _fp32_check(f"periodic solve {case}", u, o["u"], o6["u"])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -366,10 +364,18 @@ def _box(xs, ys, zs):
     return np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
 
 
-def _fp32_bar(u_stop, u_ref):
-    """Solution-parity bar of the FP32 path: 1e-5, or twice the distance from the oracle's
-    own solution stopped at the same 1e-6 residual where the conditioning makes it larger."""
-    return max(1e-5, 2.0 * np.linalg.norm(u_stop - u_ref) / np.linalg.norm(u_ref))
+def _fp32_check(tag, u, u_ref, u_stop):
+    """FP32 solution parity.  The stated bar is a relative L2 error of 1e-5 against the converged
+    oracle; where the cell's conditioning puts the oracle's own iterate stopped at the same 1e-6
+    residual farther than that, the test accepts twice that distance and prints the case as a
+    miss of the 1e-5 bar (the misses are listed with the parity results)."""
+    err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    err6 = np.linalg.norm(u_stop - u_ref) / np.linalg.norm(u_ref)
+    verdict = "meets 1e-5" if err <= 1e-5 else "MISSES 1e-5"
+    print(f"[fp32 parity] {tag}: rel-L2 to the converged oracle {err:.2e} ({verdict}); oracle stopped "
+          f"at 1e-6: {err6:.2e}", flush=True)
+    assert err <= max(1e-5, 2.0 * err6), (tag, err, err6)
+    return err
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -399,7 +405,7 @@ def test_weak_face_and_interior_supports(prec):
         assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()
     else:
         o6 = OSolver(n, lam, mu, bc, (), avg, r0_factor=1.5).solve(tol=1e-6, max_iter=5000)
-        assert np.linalg.norm(u - o["u"]) <= _fp32_bar(o6["u"], o["u"]) * np.linalg.norm(o["u"])
+        _fp32_check("weak face and interior supports", u, o["u"], o6["u"])
         assert np.abs(tot - o["totals"]).max() <= 1e-4 * np.abs(o["totals"]).max()
 
 
@@ -426,10 +432,8 @@ def test_contact_periodic_lateral(prec):
         c = centre(0.01 * k * R)
         o = cs.solve_increment(u_o, c, tol=1e-12 if prec == "fp64" else 1e-11)
         u_o = o["u"]
-        tol = 1e-10
         if prec == "fp32":
             u_6 = cs6.solve_increment(u_6, c, tol=1e-6)["u"]
-            tol = _fp32_bar(u_6, u_o)
         g.move_sphere(c)
         rc, rep = g.solve(zero_start=(k == 1))
         assert rc == 0
@@ -437,9 +441,10 @@ def test_contact_periodic_lateral(prec):
         assert o["C"].sum() > 0
         assert np.array_equal(mask.reshape(-1).astype(bool), o["C"])
         u = g.u.cpu().numpy()
-        print(f"[contact periodic] {prec} increment {k}: rel-L2 {np.linalg.norm(u - u_o) / np.linalg.norm(u_o):.2e} "
-              f"(bar {tol:.1e})", flush=True)
-        assert np.linalg.norm(u - u_o) <= tol * np.linalg.norm(u_o)
+        if prec == "fp32":
+            _fp32_check(f"contact periodic increment {k}", u, u_o, u_6)
+        else:
+            assert np.linalg.norm(u - u_o) <= 1e-10 * np.linalg.norm(u_o)
         assert abs(rep.force_contact - o["force_contact"]) <= (1e-6 if prec == "fp64" else 1e-4) * abs(o["force_contact"])
 
 
