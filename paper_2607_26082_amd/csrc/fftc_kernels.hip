@@ -371,39 +371,40 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
                                                     int pstride) {
   __shared__ double sh[kPartStrideD * 16];
   __shared__ int flags[4];
+  __shared__ int decide, s_done, changed;
   if (st->done) return;
+  // the state this step reads, loaded once up front (independent loads; reading the fields
+  // back after the stores and barriers below made a chain of dependent round trips)
+  const int vpar = st->vpar, it = st->it, max_iter = st->max_iter, have_prev = st->have_prev;
+  const int acv = st->acv, period = st->period, i_local0 = st->i_local;
+  const double tol = st->tol, gate = st->gate;
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
     for (int q = 0; q < pstride; ++q) acc[q] += part[b * pstride + q];
   for (long long r = threadIdx.x; r < nweak; r += blockDim.x) acc[0] += wpart[r];
-  block_sum<kPartStrideD>(acc, sh);
-  if (threadIdx.x == 0) {
-    st->pnorm2 = acc[0];
-    st->snorm2 = acc[1];
-    for (int q = 0; q < 6; ++q) st->ms[q] = acc[2 + q];
-    if (pstride > kPartStride)
-      for (int q = 0; q < 6; ++q) st->sing[q] = acc[8 + q];
-    flags[0] = flags[1] = 0;
-  }
-  __syncthreads();
+  if (threadIdx.x == 0) flags[0] = flags[1] = 0;
+  block_sum<kPartStrideD>(acc, sh);   // ends with a barrier
   // contact: compare V with the previous iteration, test emptiness
   if (ct.on) {
-    const int cur = st->vpar;
     int differ = 0, nonempty = 0;
     for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
-      const uint8_t v = ct.V[cur][f];
+      const uint8_t v = ct.V[vpar][f];
       nonempty |= (v != 0);
-      differ |= (v != ct.V[cur ^ 1][f]);
+      differ |= (v != ct.V[vpar ^ 1][f]);
     }
     if (differ) atomicOr(&flags[0], 1);
     if (nonempty) atomicOr(&flags[1], 1);
     __syncthreads();
   }
-  __shared__ int decide, s_done, changed;
   if (threadIdx.x == 0) {
-    const double pn = st->pnorm2, sn = st->snorm2;
+    const double pn = acc[0], sn = acc[1];
+    st->pnorm2 = pn;
+    st->snorm2 = sn;
+    for (int q = 0; q < 6; ++q) st->ms[q] = acc[2 + q];
+    if (pstride > kPartStride)
+      for (int q = 0; q < 6; ++q) st->sing[q] = acc[8 + q];
     double res;
     if (pn == 0.0) res = 0.0;
     else if (sn == 0.0) res = INFINITY;
@@ -417,25 +418,25 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
     if (!isfinite(pn) || !isfinite(sn)) {
       st->status = ST_NAN;
       s_done = 1;
-    } else if (res < st->tol && !nonempty) {
+    } else if (res < tol && !nonempty) {
       st->status = ST_CONVERGED;
       s_done = 1;
-    } else if (st->it >= st->max_iter) {
+    } else if (it >= max_iter) {
       st->status = ST_NOCONV;
       s_done = 1;
     } else {
-      if (ct.on && st->have_prev && !flags[0] && nonempty && res < st->gate) decide = 1;
+      if (ct.on && have_prev && !flags[0] && nonempty && res < gate) decide = 1;
     }
     if (s_done) st->done = 1;
   }
   __syncthreads();
   if (s_done) return;
+  int i_local = i_local0;
   if (ct.on) {
     if (decide) {
-      const int cur = st->vpar;
       int ch = 0;
       for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
-        const uint8_t v = ct.V[cur][f];
+        const uint8_t v = ct.V[vpar][f];
         const uint8_t old = ct.C[f];
         const uint8_t nw = (uint8_t)((old || (v & 1)) && !(v & 2));
         if (nw != old) {
@@ -450,18 +451,18 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
       if (decide) {
         st->updates += 1;
         if (changed) {
+          i_local = 0;
           st->i_local = 0;
           st->restarts += 1;
         }
       }
       st->have_prev = 1;
-      st->vpar ^= 1;
+      st->vpar = vpar ^ 1;
     }
   }
   if (threadIdx.x == 0) {
-    const int i = st->i_local;
-    st->store_r = (st->acv == 2) && (i > 0);
-    st->accel = (st->acv == 2) && (i >= 4) && (i % st->period == 0);
+    st->store_r = (acv == 2) && (i_local > 0);
+    st->accel = (acv == 2) && (i_local >= 4) && (i_local % period == 0);
     st->accel_ok = 0;
   }
 }
