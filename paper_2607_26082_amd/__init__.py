@@ -113,6 +113,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libfftc.so not built at {LIB_PATH}; run paper_2607_26082_amd/build.py")
+    # torch first: its wheel carries its own HIP runtime, and the library must bind to the
+    # runtime torch initialises (loaded the other way round, torch then finds no GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)

@@ -3,8 +3,9 @@
 at small sizes in test_gpu_parity.py).
 
 C2  compact-tension plate 256 x 256 x 16: the two pin sets' y-reactions balance
-    (global equilibrium, Section 4.3), prescribed DOFs hold exactly, and FP32
-    reactions agree with FP64 ones.
+    (global equilibrium, Section 4.3), prescribed DOFs hold exactly, FP32
+    reactions agree with FP64 ones, and both with the FP64 oracle's reactions
+    (tests/golden/c2_reactions.txt).
 C3  Hertz indentation 256 x 256 x 128, R = 96, d/R = 0.002 k, k = 1..10, each
     increment warm-started from the previous one (Algorithm 2).  The block is
     bonded to a fixed base 128 voxels below the contact, so the force follows Hertz
@@ -50,6 +51,24 @@ def test_c2_compact_tension_reactions():
             assert np.array_equal(got, s.value)
     r64, r32 = tot["fp64"][:, 1], tot["fp32"][:, 1]
     assert np.max(np.abs(r32 - r64)) <= 1e-4 * np.max(np.abs(r64))
+    # against the FP64 oracle's reactions (tests/golden/c2_reactions.txt, written by
+    # make_c2_reactions.py from oracle/ only): both converged to 1e-9, the FP32 form to 1e-6
+    ref = _golden_c2()
+    for prec, bar in (("fp64", 1e-7), ("fp32", 1e-4)):
+        err = np.abs(tot[prec] - ref).max() / np.abs(ref).max()
+        print(f"[c2] {prec} reactions against the FP64 oracle: {err:.2e} (bar {bar:.0e})", flush=True)
+        assert err <= bar, (prec, err)
+
+
+def _golden_c2():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_reactions.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("set"):
+            k, v = line.split(":", 1)
+            rows[int(k[3:])] = [float(x) for x in v.split()]
+    return np.array([rows[k] for k in sorted(rows)])
 
 
 def bonded_layer_factor(nu, chi):

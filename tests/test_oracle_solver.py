@@ -178,3 +178,19 @@ def test_too_soft_reference_medium_diverges():
     assert not o["converged"] and not np.isfinite(o["residual"]) and o["iterations"] < 3000
     assert np.isnan(Solver.residual(1e307, np.inf)) and np.isnan(Solver.residual(np.inf, 1.0))
     assert Solver.residual(0.0, 0.0) == 0.0
+
+
+def test_c2_golden_reactions_balance():
+    """The stored FP64 oracle reactions of the C2 plate (tests/golden/c2_reactions.txt) satisfy
+    global equilibrium: the y reactions of the two pin sets are equal and opposite (no other
+    condition acts along y), and nothing acts along x or z on them."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_reactions.txt")
+    rows = {}
+    for line in open(path):
+        if line.startswith("set"):
+            k, v = line.split(":", 1)
+            rows[int(k[3:])] = np.array([float(x) for x in v.split()])
+    r0, r1 = rows[0], rows[1]
+    assert r0[1] > 0 and abs(r0[1] + r1[1]) <= 1e-8 * r0[1]
+    assert r0[0] == r0[2] == r1[0] == r1[2] == 0.0
