@@ -87,8 +87,8 @@ struct fftc_problem {
   int b1 = 0, b2 = 1;
   AxisPlan ap[3];
   int ept = 8, nblk_res = 1, maxN = 1;
-  int dtt_nt[3] = {0, 0, 0};   // autotuned block size per axis pass
-  double tune_ms[3][2];
+  int dtt_nt[5] = {0, 0, 0, 0, 0};   // autotuned block size per transform pass (TP_*)
+  double tune_ms[5][2];
   Geo g;
   std::string err;
   DevState last{};
@@ -361,6 +361,14 @@ WeakDev weak_dev(fftc_problem* h) {
   return w;
 }
 
+// The transform passes of one iteration, in order; each has its own tuned block size.
+enum { TP_XF = 0, TP_YF, TP_Z, TP_YI, TP_XI, TP_N };
+int pass_of(int axis, int mode) {
+  if (axis == 2) return TP_Z;
+  if (mode == PASS_INV) return axis == 0 ? TP_XI : TP_YI;
+  return axis == 0 ? TP_XF : TP_YF;
+}
+
 template <typename T>
 DttArgs<T> dtt_args(fftc_problem* h, int axis, int mode, int force) {
   DttArgs<T> a{};
@@ -381,7 +389,29 @@ DttArgs<T> dtt_args(fftc_problem* h, int axis, int mode, int force) {
   // the symbol vanishes only at theta = 0 and (pi, pi, pi) (exact zeros of the factored
   // form); any positive value is at least ~ a theta_min^2, far above this threshold
   for (int c = 0; c < 3; ++c) a.thr[c] = 1e-13 * std::max(h->g.ac[c][0], std::max(h->g.ac[c][1], h->g.ac[c][2]));
-  a.nt = h->dtt_nt[axis];
+  a.nt = h->dtt_nt[pass_of(axis, mode)];
+  return a;
+}
+
+// Arguments of transform pass p of the FP32 residual-form iteration: the x forward pass forms
+// e = p - sum gamma dY from the residual fields, the x inverse pass updates the FP64 u and delta.
+DttArgs<float> delta_pass(fftc_problem* h, int p, const DeltaBufs<float>& D) {
+  static const int axis[TP_N] = {0, 1, 2, 1, 0};
+  static const int mode[TP_N] = {PASS_FWD, PASS_FWD, PASS_FWD_GREEN_INV, PASS_INV, PASS_INV};
+  DttArgs<float> a = dtt_args<float>(h, axis[p], mode[p], 0);
+  a.buf = D.t;
+  a.in = D.t;
+  if (p == TP_XF) {
+    a.src = SRC_DELTA;
+    a.dp2[0] = D.p[0];
+    a.dp2[1] = D.p[1];
+    for (int q = 0; q < 3; ++q) a.dY[q] = D.dY[q];
+    a.de = D.e;
+  } else if (p == TP_XI) {
+    a.dst = DST_UPDATE;
+    a.u64 = D.u;
+    a.delta = D.delta;
+  }
   return a;
 }
 
@@ -413,38 +443,10 @@ void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
   if (tm) tm->mark(s);
   if (h->cfg.acv == FFTC_ACV_P) launch_delta_anderson<float>(D, n3, h->st, h->gpart, h->nblk_res, s);
   if (tm) tm->mark(s);
-  DttArgs<float> a = dtt_args<float>(h, 0, PASS_FWD, 0);
-  a.src = SRC_DELTA;
-  a.dp2[0] = D.p[0];
-  a.dp2[1] = D.p[1];
-  for (int q = 0; q < 3; ++q) a.dY[q] = D.dY[q];
-  a.de = D.e;
-  a.buf = D.t;
-  launch_dtt<float>(a, h->ept, s);
-  if (tm) tm->mark(s);
-  a = dtt_args<float>(h, 1, PASS_FWD, 0);
-  a.buf = D.t;
-  a.in = D.t;
-  launch_dtt<float>(a, h->ept, s);
-  if (tm) tm->mark(s);
-  a = dtt_args<float>(h, 2, PASS_FWD_GREEN_INV, 0);
-  a.buf = D.t;
-  a.in = D.t;
-  launch_dtt<float>(a, h->ept, s);
-  if (tm) tm->mark(s);
-  a = dtt_args<float>(h, 1, PASS_INV, 0);
-  a.buf = D.t;
-  a.in = D.t;
-  launch_dtt<float>(a, h->ept, s);
-  if (tm) tm->mark(s);
-  a = dtt_args<float>(h, 0, PASS_INV, 0);
-  a.buf = D.t;
-  a.in = D.t;
-  a.dst = DST_UPDATE;
-  a.u64 = D.u;
-  a.delta = D.delta;
-  launch_dtt<float>(a, h->ept, s);
-  if (tm) tm->mark(s);
+  for (int p = 0; p < TP_N; ++p) {
+    launch_dtt<float>(delta_pass(h, p, D), h->ept, s);
+    if (tm) tm->mark(s);
+  }
   launch_delta_proj<float>(h->g, D, sd, w, ct, h->st, 0, 1, s);
   if (tm) tm->mark(s);
 }
@@ -1310,34 +1312,38 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
     HIPCHK(h, hipMemcpyAsync(h->d_wd, h->w_d.data(), 8 * h->w_d.size(), hipMemcpyHostToDevice, s));
   }
   h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
-  // autotune the block size of each axis pass: time both variants on the bound buffers
+  // autotune the block size of each transform pass: time both variants of the pass as the
+  // iteration runs it (the FP32 form's x passes with their residual-form source and FP64
+  // update), on the bound buffers with a cleared state (no acceleration, nothing done)
   if (!tune) {
-    for (int J = 0; J < 3; ++J) h->dtt_nt[J] = h->precision == FFTC_FP64 ? 256 : 512;
+    for (int p = 0; p < TP_N; ++p) h->dtt_nt[p] = h->precision == FFTC_FP64 ? 256 : 512;
   } else {
+    HIPCHK(h, hipMemsetAsync(h->st, 0, sizeof(DevState), s));
+    const bool delta = h->precision == FFTC_FP32 && h->nlit < 10;   // runs the residual form
+    static const int axis[TP_N] = {0, 1, 2, 1, 0};
+    static const int mode[TP_N] = {PASS_FWD, PASS_FWD, PASS_FWD_GREEN_INV, PASS_INV, PASS_INV};
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
     const int cand[2] = {h->precision == FFTC_FP64 ? 128 : 256, h->precision == FFTC_FP64 ? 256 : 512};
-    for (int J = 0; J < 3; ++J) {
-      float best = 1e30f;
+    for (int p = 0; p < TP_N; ++p) {
       for (int v = 0; v < 2; ++v) {
-        h->dtt_nt[J] = cand[v];
-        const int mode = J == 2 ? PASS_FWD_GREEN_INV : PASS_FWD;
+        h->dtt_nt[p] = cand[v];
         float tot = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
           HIPCHK(h, hipEventRecord(e0, s));
-          if (h->precision == FFTC_FP64) launch_dtt<double>(dtt_args<double>(h, J, mode, 1), h->ept, s);
-          else launch_dtt<float>(dtt_args<float>(h, J, mode, 1), h->ept, s);
+          if (h->precision == FFTC_FP64) launch_dtt<double>(dtt_args<double>(h, axis[p], mode[p], 1), h->ept, s);
+          else if (delta) launch_dtt<float>(delta_pass(h, p, dbufs(h)), h->ept, s);
+          else launch_dtt<float>(dtt_args<float>(h, axis[p], mode[p], 1), h->ept, s);
           HIPCHK(h, hipEventRecord(e1, s));
           HIPCHK(h, hipEventSynchronize(e1));
           float ms = 0.f;
           HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
           if (rep > 0) tot += ms;
         }
-        h->tune_ms[J][v] = tot / 2;
-        if (tot < best) best = tot;
+        h->tune_ms[p][v] = tot / 2;
       }
-      h->dtt_nt[J] = (h->tune_ms[J][0] <= h->tune_ms[J][1]) ? cand[0] : cand[1];
+      h->dtt_nt[p] = (h->tune_ms[p][0] <= h->tune_ms[p][1]) ? cand[0] : cand[1];
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
