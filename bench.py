@@ -165,7 +165,7 @@ def bench_warmstart(args):
     torch.cuda.set_device(0)
     net = F.Net(6, 4)
     net.set_params(WS.load_weights())
-    rows = WS.evaluate(net, specs, scale=scale)
+    rows = WS.evaluate(net, specs, scale=scale, ref64=args.ref64)
     s = WS.summary(rows)
     n = 64 * scale
     out = {
@@ -326,6 +326,8 @@ def main():
                          "c5: time to 1e-6 with the learned start vs the plain start on held-out cases; "
                          "nn: the learned-start network alone (inference and a training step)")
     ap.add_argument("--cells", type=int, default=BATCH_CELLS_MAX)
+    ap.add_argument("--ref64", type=int, default=16,
+                    help="c5: cases also solved by the FP64 path to 1e-10 as the reference solution")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU per process; multi-GPU runs are not supported, --gpus must be 1"}))

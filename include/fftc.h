@@ -102,7 +102,8 @@ typedef struct {
  * sphere, displacements, gaps -- are in the unit of h; forces are stress times that unit
  * squared; the kernels work in voxel units).  scheme: FFTC_TETRA2 or FFTC_HEX1.
  * Errors: FFTC_E_ARG (n_J < 2 or > 4096, h not positive), FFTC_E_UNSUPPORTED (axis length
- * with a prime factor > 5, unknown scheme or precision, more than 2^31 DOFs). */
+ * with a prime factor other than 2, 3, 5, 7, 11, 13, unknown scheme or precision, more than
+ * 2^31 DOFs). */
 int fftc_create(fftc_h* out, const int32_t n[3], double h, int32_t scheme, int32_t precision);
 void fftc_destroy(fftc_h h);
 

@@ -131,9 +131,12 @@ const char* fftc_nn_last_error(fftc_nn_h nn);
 /* Judged start (the plain iteration always finishes the solve): measures the
  * equilibrium residual of the projected start proj_U(u0) and of the plain
  * start, solves from u0 when its residual is smaller and from the plain
- * start otherwise.  *used_u0 = 1 when u0 was used; residual_host (may be
- * NULL) receives {residual of u0, residual of the plain start}.  Other
- * arguments as fftc_solve. */
+ * start otherwise.  A solve from u0 that does not converge (FFTC_E_NOCONV or
+ * FFTC_E_NAN: with an obstacle, a start can hold a contact set the iteration
+ * does not leave within max_iter) is repeated from the plain start, and its
+ * result and report are those of that repeat.  *used_u0 = 1 when the returned
+ * solution comes from u0; residual_host (may be NULL) receives {residual of u0,
+ * residual of the plain start}.  Other arguments as fftc_solve. */
 int fftc_solve_judged(fftc_h h, const double* u0_dev, double* u_dev, fftc_report* rep, int32_t* used_u0,
                       double* residual_host);
 

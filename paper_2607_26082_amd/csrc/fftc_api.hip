@@ -132,6 +132,8 @@ bool factor_ok(int n, std::vector<int>& rad) {
   while (m % 2 == 0) { rad.push_back(2); m /= 2; }
   while (m % 3 == 0) { rad.push_back(3); m /= 3; }
   while (m % 5 == 0) { rad.push_back(5); m /= 5; }
+  for (int r : {7, 11, 13})
+    while (m % r == 0) { rad.push_back(r); m /= r; }
   return m == 1 && (int)rad.size() <= kMaxRadices;
 }
 
@@ -1694,7 +1696,13 @@ int fftc_solve_judged(fftc_h h, const double* u0_dev, double* u_dev, fftc_report
   }
   if (use && u0_dev != u_dev)
     HIPCHK(h, hipMemcpyAsync(u_dev, u0_dev, 8 * 3 * (size_t)h->Nn, hipMemcpyDeviceToDevice, h->stream));
-  return solve_all(h, u_dev, use ? 0 : 1, rep);
+  rc = solve_all(h, u_dev, use ? 0 : 1, rep);
+  if (use && (rc == FFTC_E_NOCONV || rc == FFTC_E_NAN)) {
+    // the plain iteration finishes the solve: fall back to the plain start
+    if (used_u0) *used_u0 = 0;
+    rc = solve_all(h, u_dev, 1, rep);
+  }
+  return rc;
 }
 
 const char* fftc_batch_last_error(fftc_batch_h b) { return b ? b->err.c_str() : "null batch"; }

@@ -15,6 +15,60 @@ namespace fftc {
 // ---------------------------------------------------------------------------
 // Batched per-axis discrete trigonometric transforms in LDS
 // ---------------------------------------------------------------------------
+// cos(2 pi k / R) and sin(2 pi k / R), k = 1 .. (R - 1) / 2, of the odd prime radices 7, 11, 13
+template <int R> struct OddRadix;
+template <> struct OddRadix<7> {
+  static constexpr double c[3] = {0.6234898018587336, -0.22252093395631434, -0.900968867902419};
+  static constexpr double s[3] = {0.7818314824680298, 0.9749279121818236, 0.43388373911755823};
+};
+template <> struct OddRadix<11> {
+  static constexpr double c[5] = {0.8412535328311812, 0.41541501300188644, -0.142314838273285, -0.654860733945285,
+                                  -0.9594929736144974};
+  static constexpr double s[5] = {0.5406408174555976, 0.9096319953545183, 0.9898214418809328, 0.7557495743542583,
+                                  0.28173255684142967};
+};
+template <> struct OddRadix<13> {
+  static constexpr double c[6] = {0.8854560256532099, 0.5680647467311559, 0.120536680255323, -0.35460488704253545,
+                                  -0.7485107481711012, -0.970941817426052};
+  static constexpr double s[6] = {0.4647231720437685, 0.8229838658936564, 0.992708874098054, 0.9350162426854148,
+                                  0.6631226582407952, 0.23931566428755768};
+};
+
+// Length-R DFT, R an odd prime, X_m = sum_j a_j e^{i sgn 2 pi j m / R}: with b_j = a_j + a_{R-j}
+// and d_j = a_j - a_{R-j} (j = 1 .. H), X_m and X_{R-m} are A_m +- i sgn S_m, where
+// A_m = a_0 + sum_j cos(2 pi j m / R) b_j and S_m = sum_j sin(2 pi j m / R) d_j.
+template <typename T, int R>
+__device__ __forceinline__ void dft_odd(cplx<T> (&a)[R], int sgn) {
+  constexpr int H = (R - 1) / 2;
+  cplx<T> b[H], d[H];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    b[j - 1] = cadd(a[j], a[R - j]);
+    d[j - 1] = csub(a[j], a[R - j]);
+  }
+  cplx<T> x[R];
+  x[0] = a[0];
+#pragma unroll
+  for (int j = 0; j < H; ++j) x[0] = cadd(x[0], b[j]);
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    cplx<T> A = a[0], S = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const int k = (j * m) % R;
+      const T cv = T(k <= H ? OddRadix<R>::c[k - 1] : OddRadix<R>::c[R - k - 1]);
+      const T sv = T(k <= H ? OddRadix<R>::s[k - 1] : -OddRadix<R>::s[R - k - 1]);
+      A = {A.re + cv * b[j - 1].re, A.im + cv * b[j - 1].im};
+      S = {S.re + sv * d[j - 1].re, S.im + sv * d[j - 1].im};
+    }
+    const cplx<T> B = {-T(sgn) * S.im, T(sgn) * S.re};   // i sgn S
+    x[m] = cadd(A, B);
+    x[R - m] = csub(A, B);
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) a[q] = x[q];
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dft_small(cplx<T> (&a)[R], int sgn) {
   if constexpr (R == 2) {
@@ -52,6 +106,8 @@ __device__ __forceinline__ void dft_small(cplx<T> (&a)[R], int sgn) {
     a[4] = csub(m1, r1);
     a[2] = cadd(m2, r2);
     a[3] = csub(m2, r2);
+  } else {
+    dft_odd<T, R>(a, sgn);
   }
 }
 
@@ -99,7 +155,9 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, int cstride, int L, int 
   __syncthreads();
 }
 
-template <typename T, int EPT>
+// BIG: the plan has a radix 7, 11 or 13 (a separate kernel instance, so that the register
+// budget of those stages does not lower the occupancy of the 2-3-5 lengths)
+template <typename T, int EPT, bool BIG>
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, int cstride, int L, const AxisPlan& ap, int sgn) {
   const cplx<T>* tw = (const cplx<T>*)ap.tw;
   int Ns = 1;
@@ -108,9 +166,20 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, int cstride, int L, cons
     if (r == 4) fft_stage<T, 4, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
     else if (r == 2) fft_stage<T, 2, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
     else if (r == 3) fft_stage<T, 3, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
-    else fft_stage<T, 5, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    else if (!BIG || r == 5) fft_stage<T, 5, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    else if constexpr (BIG) {
+      if (r == 7) fft_stage<T, 7, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+      else if (r == 11) fft_stage<T, 11, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+      else fft_stage<T, 13, EPT>(buf, cstride, L, ap.n, Ns, sgn, tw);
+    }
     Ns *= r;
   }
+}
+
+__host__ __device__ inline bool plan_has_big_radix(const AxisPlan& ap) {
+  for (int s = 0; s < ap.nrad; ++s)
+    if (ap.rad[s] > 5) return true;
+  return false;
 }
 
 // FFT direction of each (type, forward/inverse): -1 = e^{-i}, +1 = e^{+i}
@@ -223,7 +292,7 @@ __device__ __forceinline__ T dtt_post(int type, int inv, const cplx<T>* Z, int n
 }
 
 
-template <typename T, int EPT>
+template <typename T, int EPT, bool BIG>
 __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (!a.force && a.st->done) return;
@@ -298,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
       cb[l * cstride + k] = dtt_pre<T>(type, inv_first, rb + l * rstride, n, k, tw);
     }
     __syncthreads();
-    fft_lines<T, EPT>(cb, cstride, L, a.ap, sg);
+    fft_lines<T, EPT, BIG>(cb, cstride, L, a.ap, sg);
   }
   if (a.mode == PASS_FWD_GREEN_INV) {
     // forward post-processing, Green operator M^-1, back into LDS
@@ -329,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
       cb[l * cstride + k] = dtt_pre<T>(itype, 1, rb + l * rstride, n, k, tw);
     }
     __syncthreads();
-    fft_lines<T, EPT>(cb, cstride, L, a.ap, sg);
+    fft_lines<T, EPT, BIG>(cb, cstride, L, a.ap, sg);
   }
   // phase 4: post-process and write
   const int inv_out = (a.mode != PASS_FWD);
@@ -702,10 +771,14 @@ void launch_dtt(const DttArgs<T>& a, int ept, hipStream_t s) {
   const long long nlines = a.axis == 0 ? (long long)Ny * Nz : a.axis == 1 ? (long long)Nx * Nz : (long long)Nx * Ny;
   const long long nb = (nlines + a.ap.L - 1) / a.ap.L;
   const size_t sm = dtt_smem<T>(a.ap);
-  if (dtt_ept(ept, a.ap) <= 8)
-    hipLaunchKernelGGL((k_dtt<T, 8>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
-  else
-    hipLaunchKernelGGL((k_dtt<T, 16>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+  const bool big = plan_has_big_radix(a.ap);
+  if (dtt_ept(ept, a.ap) <= 8) {
+    if (big) hipLaunchKernelGGL((k_dtt<T, 8, true>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+    else hipLaunchKernelGGL((k_dtt<T, 8, false>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+  } else {
+    if (big) hipLaunchKernelGGL((k_dtt<T, 16, true>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+    else hipLaunchKernelGGL((k_dtt<T, 16, false>), dim3((unsigned)nb, 3), dim3(kBlock), sm, s, a);
+  }
 }
 
 }  // namespace fftc

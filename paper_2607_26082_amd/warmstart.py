@@ -174,11 +174,36 @@ def summary(rows):
            "time_ratio_total": float(tt[:, 0].sum() / tt[:, 1].sum()),
            "iters_nn_forced_median": float(np.median([r["iters_nn_forced"] for r in rows])),
            "nn_start_used": int(sum(r["used_nn"] for r in rows)),
-           "rel_nn_vs_plain_max": float(max(r["rel_nn_vs_plain"] for r in rows))}
+           "rel_nn_vs_plain_max": float(np.nanmax([r["rel_nn_vs_plain"] for r in rows]))}
+    codes = {0: "ok", -5: "not converged", -6: "non-finite"}
+    for j, name in ((0, "status_plain"), (1, "status_nn")):
+        cnt = {}
+        for r in rows:
+            key = codes.get(int(r["status"][j]), str(r["status"][j]))
+            cnt[key] = cnt.get(key, 0) + 1
+        out[name] = cnt
+    # cases whose two final solutions differ by more than the stopping tolerance allows
+    out["outliers"] = [{k: r[k] for k in ("seed", "kind", "status", "iters_plain", "iters_nn", "used_nn",
+                                          "rel_nn_vs_plain")}
+                       for r in rows if not (r["rel_nn_vs_plain"] <= 1e-3)]
     ref = [r for r in rows if "rel_nn_vs_fp64" in r]
     if ref:
+        out["fp64_reference_cases"] = len(ref)
         out["rel_nn_vs_fp64_max"] = max(r["rel_nn_vs_fp64"] for r in ref)
         out["rel_plain_vs_fp64_max"] = max(r["rel_plain_vs_fp64"] for r in ref)
+        out["rel_plain_vs_fp64_median"] = float(np.median([r["rel_plain_vs_fp64"] for r in ref]))
+    kinds = sorted({r["kind"] for r in rows})
+    if len(kinds) > 1:
+        out["by_kind"] = {}
+        for k in kinds:
+            rk = [r for r in rows if r["kind"] == k]
+            ik = np.array([[r["iters_plain"], r["iters_nn"], r["iters_nn_forced"]] for r in rk], float)
+            tk = np.array([[r["t_plain_s"], r["t_nn_s"]] for r in rk])
+            out["by_kind"][k] = {"cases": len(rk), "iters_plain_median": float(np.median(ik[:, 0])),
+                                 "iters_nn_median": float(np.median(ik[:, 1])),
+                                 "iters_nn_forced_median": float(np.median(ik[:, 2])),
+                                 "nn_start_used": int(sum(r["used_nn"] for r in rk)),
+                                 "time_ratio_total": float(tk[:, 0].sum() / tk[:, 1].sum())}
     return out
 
 

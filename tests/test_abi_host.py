@@ -28,7 +28,9 @@ def _code(fn, *a):
 
 
 def test_create_sizes():
-    assert _code(F.fftc_create, (14, 8, 8)) == F.FFTC_E_UNSUPPORTED        # prime factor 7
+    assert _code(F.fftc_create, (17, 8, 8)) == F.FFTC_E_UNSUPPORTED        # prime factor 17
+    assert _code(F.fftc_create, (34, 8, 8)) == F.FFTC_E_UNSUPPORTED        # 2 x 17
+    F.fftc_destroy(F.fftc_create((14, 22, 26)))                             # 2 x 7, 2 x 11, 2 x 13
     assert _code(F.fftc_create, (1, 8, 8)) == F.FFTC_E_ARG
     assert _code(F.fftc_create, (8, 8, 5000)) == F.FFTC_E_ARG
     assert _code(F.fftc_create, (8, 8, 8), 5) == F.FFTC_E_UNSUPPORTED

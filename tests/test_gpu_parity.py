@@ -37,7 +37,9 @@ def _case(seed, n, periodic_axis=None, weak=True):
 SHAPES = [((6, 5, 9), None), ((10, 12, 15), 1), ((16, 16, 16), None), ((24, 20, 18), 0), ((9, 8, 10), 2),
           # every compile-time transform length on every axis, ragged line tiles
           ((32, 48, 6), None), ((64, 5, 96), None), ((128, 6, 16), None), ((256, 4, 5), None),
-          ((5, 256, 4), None), ((4, 6, 128), None), ((64, 32, 48), 1), ((96, 128, 32), None)]
+          ((5, 256, 4), None), ((4, 6, 128), None), ((64, 32, 48), 1), ((96, 128, 32), None),
+          # radices 7, 11, 13 (runtime-length kernel), also on periodic (DFT) axes
+          ((14, 11, 13), None), ((21, 22, 7), 0), ((26, 7, 33), 2), ((77, 13, 6), 1)]
 
 
 @pytest.mark.parametrize("idx", range(len(SHAPES)))

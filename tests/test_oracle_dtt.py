@@ -11,7 +11,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 KINDS = ("DCT1", "DCT3", "DST1", "DST3")
 
 
-@pytest.mark.parametrize("n", [2, 3, 5, 8, 15, 16, 48])
+@pytest.mark.parametrize("n", [2, 3, 5, 7, 8, 13, 15, 16, 22, 48])
 @pytest.mark.parametrize("kind", KINDS + ("DFT",))
 def test_scipy_matches_defining_sums(kind, n):
     rng = np.random.default_rng(n)
