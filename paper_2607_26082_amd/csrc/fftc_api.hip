@@ -54,7 +54,7 @@ struct fftc_problem {
   int has_sphere = 0;
   double center[3] = {0, 0, 0}, radius = 0;
   int face = 5;
-  fftc_solver_cfg cfg{1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2};
+  fftc_solver_cfg cfg{1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2, 1e-5};
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -439,7 +439,7 @@ void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
   const long long n3 = 3 * h->Nn;
   hipStream_t s = h->stream;
   if (tm) tm->mark(s);
-  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, h->cfg.refine_below > 0.0, s);
   if (tm) tm->mark(s);
   launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
   if (tm) tm->mark(s);
@@ -562,6 +562,8 @@ int init_state(fftc_problem* h) {
   hs.period = h->cfg.period;
   hs.acv = h->cfg.acv;
   hs.contact = h->has_sphere;
+  hs.refine_below = h->delta_mode ? h->cfg.refine_below : 0.0;
+  hs.fine = 0;
   h->init_host = hs;
   HIPCHK(h, hipMemcpyAsync(h->st, &h->init_host, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
   return FFTC_OK;
@@ -759,7 +761,8 @@ int stage_residual_t(fftc_problem* h, const double* u_dev, double* p_dev, double
 // One residual pass of the FP32 residual-form iteration on caller state (iteration 0 of the
 // ping-pong, local Anderson index il): u (FP64), delta, e, p_prev, R_prev in, p, R, dR, dY
 // out (FP64 copies), sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.
-int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, double* const* out, double* sums) {
+int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, int fp64_stress, double* const* out,
+                          double* sums) {
   DeltaBufs<float> D = dbufs(h);
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
@@ -778,6 +781,7 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, doub
   hs.i_local = il;
   hs.it = 0;
   hs.accel_ok = 1;   // e is the caller's, not p_prev
+  hs.fine = fp64_stress ? 1 : 0;
   hs.tol = 0.0;
   hs.max_iter = 1 << 30;
   hs.period = h->cfg.period;
@@ -787,7 +791,7 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, doub
   const ContactDev ct = contact_dev(h);
   const WeakDev w = weak_dev(h);
   if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
-  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, 1, s);
   launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
   // R difference as the Gram pass forms it, from the R ring (staged in the transform buffer)
   if (out[2]) launch_diff<float>(Rcur, Rprev, D.t, n3, s);
@@ -1164,7 +1168,8 @@ int fftc_set_kinematics(fftc_h h, int32_t kind) {
 int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg) {
   if (!h || !cfg) return FFTC_E_ARG;
   if (cfg->depth != 4) return fail(h, FFTC_E_UNSUPPORTED, "Anderson depth must be 4");
-  if (cfg->period < 1 || cfg->max_iter < 0 || !(cfg->tol >= 0.0) || cfg->acv < 0 || cfg->acv > 2)
+  if (cfg->period < 1 || cfg->max_iter < 0 || !(cfg->tol >= 0.0) || cfg->acv < 0 || cfg->acv > 2 ||
+      !(cfg->refine_below >= 0.0))
     return fail(h, FFTC_E_ARG, "invalid solver settings");
   if (h->bound && cfg->acv == FFTC_ACV_U && h->nlit < 10)
     return fail(h, FFTC_E_STATE, "ACV_U in FP32 needs its Anderson fields: set it before binding the workspace");
@@ -1774,14 +1779,14 @@ int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* pt
 }
 
 int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_dev, const double* e_dev,
-                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, double* p_dev,
-                             double* r_dev, double* dr_dev, double* dy_dev, double* sums_host) {
-  if (!h || !u_dev || i_local < 0) return FFTC_E_ARG;
+                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, int32_t fp64_stress,
+                             double* p_dev, double* r_dev, double* dr_dev, double* dy_dev, double* sums_host) {
+  if (!h || !u_dev || i_local < 0 || fp64_stress < 0 || fp64_stress > 1) return FFTC_E_ARG;
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
   if (h->precision != FFTC_FP32) return fail(h, FFTC_E_UNSUPPORTED, "the residual form is the FP32 iteration");
   const double* in[5] = {u_dev, delta_dev, e_dev, pprev_dev, rprev_dev};
   double* out[4] = {p_dev, r_dev, dr_dev, dy_dev};
-  return stage_residual_form_t(h, in, i_local, out, sums_host);
+  return stage_residual_form_t(h, in, i_local, fp64_stress, out, sums_host);
 }
 
 int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev) {

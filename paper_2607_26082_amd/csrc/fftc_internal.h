@@ -53,9 +53,9 @@ struct DevState {
   int store_r, accel, accel_ok, acv;
   int have_prev, updates, restarts, vpar;
   int period, max_iter, contact, nC;
-  int vnonempty, pad1, pad2, pad3;
+  int vnonempty, fine, pad2, pad3;   // fine: the FP32 form forms stresses in FP64 (sticky)
   double tol, gate, residual, pnorm2;
-  double snorm2, pad4;
+  double snorm2, refine_below;
   double ms[6];
   double gram[16];
   double alpha[4];

@@ -376,8 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   // the state this step reads, loaded once up front (independent loads; reading the fields
   // back after the stores and barriers below made a chain of dependent round trips)
   const int vpar = st->vpar, it = st->it, max_iter = st->max_iter, have_prev = st->have_prev;
-  const int acv = st->acv, period = st->period, i_local0 = st->i_local;
-  const double tol = st->tol, gate = st->gate;
+  const int acv = st->acv, period = st->period, i_local0 = st->i_local, fine0 = st->fine;
+  const double tol = st->tol, gate = st->gate, refine_below = st->refine_below;
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
@@ -426,6 +426,11 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
       s_done = 1;
     } else {
       if (ct.on && have_prev && !flags[0] && nonempty && res < gate) decide = 1;
+      // FP32 form: below the refinement threshold the residual pass forms its stresses in
+      // FP64 from the next iteration on.  The Anderson history is kept: its unaccelerated
+      // restart iterations amplify the error on cells where the plain map diverges
+      // (measured on a homogeneous block: 1e-5 -> 0.26 within four iterations).
+      if (!fine0 && refine_below > 0.0 && res < refine_below) st->fine = 1;
     }
     if (s_done) st->done = 1;
   }

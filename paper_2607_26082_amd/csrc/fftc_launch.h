@@ -13,9 +13,10 @@ void launch_control(DevState* st, const double* part, int nblk, const double* wp
                     const ContactDev& ct, int pstride, hipStream_t s);
 // Residual-form iteration, first half: the residual pass (returns the number of block
 // partial rows it wrote), then the average relations and the control step over those rows.
+// refine: also launch the FP64-stress pass (taken once the state's refinement flag is set).
 template <typename T>
 int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
-                          int nblk, hipStream_t s);
+                          int nblk, int refine, hipStream_t s);
 template <typename T>
 void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w, DevState* st,
                           const double* part, const double* wpart, int nblk, hipStream_t s);

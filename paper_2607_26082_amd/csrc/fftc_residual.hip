@@ -40,8 +40,9 @@ __device__ __forceinline__ void stencil_k0(const Geo& g, const T* __restrict__ f
 }
 
 // p = 2^b div_D(sigma) from an FP64 displacement: neighbour differences are formed in
-// FP64 and rounded once, the stress and divergence arithmetic is in T.
-template <typename T, bool SIG, bool FS = false>
+// FP64 and rounded once to TS, the stress and divergence arithmetic is in TS (T, or FP64 for
+// the refining passes of the FP32 form), and p is rounded to T.
+template <typename T, bool SIG, bool FS = false, typename TS = T>
 __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restrict__ u, const T* __restrict__ lam,
                                             const T* __restrict__ mu, int i, int j, int k, T p[3], double& sn,
                                             double ms[6]) {
@@ -54,7 +55,7 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
   double u0[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) u0[c] = u[c * Nn + self];
-  T nb[27][3];
+  TS nb[27][3];
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -66,11 +67,11 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
         const long long idx = (long long)xs[dx + 1] + (long long)Nx * ((long long)ys[dy + 1] + (long long)Ny * zs[dz + 1]);
         const int q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nb[q][c] = (T)(u[c * Nn + idx] - u0[c]);
+        for (int c = 0; c < 3; ++c) nb[q][c] = (TS)(u[c * Nn + idx] - u0[c]);
       }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) nb[13][c] = T(0);
-  T F[3] = {T(0), T(0), T(0)};
+  for (int c = 0; c < 3; ++c) nb[13][c] = TS(0);
+  TS F[3] = {TS(0), TS(0), TS(0)};
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
@@ -81,19 +82,19 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
     if (g.periodic[2]) { if (vz < 0) vz += g.n[2]; } else inside &= (vz >= 0 && vz < g.n[2]);
     if (!inside) continue;
     const long long vid = (long long)vx + (long long)g.n[0] * ((long long)vy + (long long)g.n[1] * vz);
-    const T l = lam[vid], m = mu[vid];
-    T G[3][3];
+    const TS l = (TS)lam[vid], m = (TS)mu[vid];
+    TS G[3][3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int s = 0; s < 3; ++s) G[r][s] = T(0);
+      for (int s = 0; s < 3; ++s) G[r][s] = TS(0);
     const int par = (ax + ay + az) & 1;
 #pragma unroll
     for (int cc = 0; cc < 8; ++cc) {
       const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
       if (((cx + cy + cz) & 1) != par) continue;
       const int q = (cx - ax + 1) + 3 * (cy - ay + 1) + 9 * (cz - az + 1);
-      const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+      const TS sx = TS(cx ? 0.5 : -0.5), sy = TS(cy ? 0.5 : -0.5), sz = TS(cz ? 0.5 : -0.5);
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         G[r][0] += sx * nb[q][r];
@@ -101,10 +102,10 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
         G[r][2] += sz * nb[q][r];
       }
     }
-    const T bx = T(ax ? 0.25 : -0.25), by = T(ay ? 0.25 : -0.25), bz = T(az ? 0.25 : -0.25);
+    const TS bx = TS(ax ? 0.25 : -0.25), by = TS(ay ? 0.25 : -0.25), bz = TS(az ? 0.25 : -0.25);
     if constexpr (FS) {
-      T P[3][3];
-      svk_pk1<T>(G, l, m, P);
+      TS P[3][3];
+      svk_pk1<TS>(G, l, m, P);
 #pragma unroll
       for (int r = 0; r < 3; ++r) F[r] += bx * P[r][0] + by * P[r][1] + bz * P[r][2];
       if (SIG && (a == 0 || a == 1)) {
@@ -119,13 +120,13 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
       }
       continue;
     }
-    const T tr = G[0][0] + G[1][1] + G[2][2];
-    const T s00 = l * tr + T(2) * m * G[0][0];
-    const T s11 = l * tr + T(2) * m * G[1][1];
-    const T s22 = l * tr + T(2) * m * G[2][2];
-    const T s01 = m * (G[0][1] + G[1][0]);
-    const T s02 = m * (G[0][2] + G[2][0]);
-    const T s12 = m * (G[1][2] + G[2][1]);
+    const TS tr = G[0][0] + G[1][1] + G[2][2];
+    const TS s00 = l * tr + TS(2) * m * G[0][0];
+    const TS s11 = l * tr + TS(2) * m * G[1][1];
+    const TS s22 = l * tr + TS(2) * m * G[2][2];
+    const TS s01 = m * (G[0][1] + G[1][0]);
+    const TS s02 = m * (G[0][2] + G[2][0]);
+    const TS s12 = m * (G[1][2] + G[2][1]);
     F[0] += bx * s00 + by * s01 + bz * s02;
     F[1] += bx * s01 + by * s11 + bz * s12;
     F[2] += bx * s02 + by * s12 + bz * s22;
@@ -137,9 +138,9 @@ __device__ __forceinline__ void node_eval_d(const Geo& g, const double* __restri
     }
   }
   const int xyz[3] = {i, j, k};
-  const T w2b = T(1 << bcount(g, xyz));
+  const TS w2b = TS(1 << bcount(g, xyz));
 #pragma unroll
-  for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+  for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : (T)(-w2b * F[c]);
 }
 
 // forward-transform weight of a node in the singular coefficients (DCT1 ends 1, interior 2; DFT 1)
@@ -242,11 +243,13 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
   }
 }
 
-template <typename T, bool FS>
+// TS: stress arithmetic (T, or FP64 once the residual is below the refinement threshold);
+// the instance whose TS does not match the state's flag returns at once.
+template <typename T, bool FS, typename TS>
 __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                        double* __restrict__ part) {
   __shared__ double sh[kPartStrideD * 16];
-  if (st->done) return;
+  if (st->done || st->fine != (int)(sizeof(TS) == 8)) return;
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     const int k = r / Ny, j = r - k * Ny;
     T p[3];
     double sn = 0.0, ms[6] = {0, 0, 0, 0, 0, 0};
-    node_eval_d<T, true, FS>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    node_eval_d<T, true, FS, TS>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
     acc[1] += sn;
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
@@ -300,17 +303,17 @@ constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
 // slot of node plane p in the four-plane ring of delta planes (p may be -1)
 __device__ __forceinline__ int ring4(int p) { return p & 3; }
 
-template <typename T, bool FS, bool GEN>
+template <typename T, bool FS, bool GEN, typename TS>
 __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, TileGrid tg) {
   constexpr int NQ = FS ? 9 : 6;      // stored stress components per tetrahedron (PK1: all nine)
   __shared__ double su[2][3][kHY][kHX];
   __shared__ T sdl[4][3][kHY][kHX];
-  __shared__ T ss[2][2 * NQ][kVY][kVX];   // stress component q of the voxels of a layer
+  __shared__ TS ss[2][2 * NQ][kVY][kVX];   // stress component q of the voxels of a layer (in TS)
   // the final block sum reuses the stress buffer (block_sum starts with a barrier)
   static_assert(sizeof(ss) >= sizeof(double) * kPartStrideD * 16, "block-sum scratch");
   double* sh = reinterpret_cast<double*>(&ss[0][0][0][0]);
-  if (st->done) return;
+  if (st->done || st->fine != (int)(sizeof(TS) == 8)) return;
   const int tid = threadIdx.x;
   // contiguous ranges of tiles per XCD (blocks go to the 8 XCDs round-robin), so that
   // neighbouring tiles share their halo lines in one L2
@@ -412,37 +415,38 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     const int lo = lz & 1, hi = (lz + 1) & 1;
     {
       const int ly = vly, lx = vlx;
-      T (*out)[kVY][kVX] = ss[lz & 1];
+      TS (*out)[kVY][kVX] = ss[lz & 1];
       const int ux = vux, uy = vuy;
       if (!ok) {
 #pragma unroll
-        for (int q = 0; q < 2 * NQ; ++q) out[q][ly][lx] = T(0);
+        for (int q = 0; q < 2 * NQ; ++q) out[q][ly][lx] = TS(0);
         return;
       }
-      T d[8][3];
+      const TS lt = (TS)l, mt = (TS)m;
+      TS d[8][3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double ref = su[lo][c][ly][lx];
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
           const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
-          d[cc][c] = cc == 0 ? T(0) : (T)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
+          d[cc][c] = cc == 0 ? TS(0) : (TS)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
         }
       }
       const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
-      T vs = T(0);
+      TS vs = TS(0);
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        T G[3][3];
+        TS G[3][3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int q = 0; q < 3; ++q) G[r][q] = T(0);
+          for (int q = 0; q < 3; ++q) G[r][q] = TS(0);
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
           const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
           if (((cx + cy + cz) & 1) != t) continue;
-          const T sx = T(cx ? 0.5 : -0.5), sy = T(cy ? 0.5 : -0.5), sz = T(cz ? 0.5 : -0.5);
+          const TS sx = TS(cx ? 0.5 : -0.5), sy = TS(cy ? 0.5 : -0.5), sz = TS(cz ? 0.5 : -0.5);
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
             G[r][0] += sx * d[cc][r];
@@ -451,8 +455,8 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
           }
         }
         if constexpr (FS) {
-          T P[3][3];
-          svk_pk1<T>(G, l, m, P);
+          TS P[3][3];
+          svk_pk1<TS>(G, lt, mt, P);
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -465,13 +469,13 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
           }
           continue;
         }
-        const T tr = G[0][0] + G[1][1] + G[2][2];
-        const T s00 = l * tr + T(2) * m * G[0][0];
-        const T s11 = l * tr + T(2) * m * G[1][1];
-        const T s22 = l * tr + T(2) * m * G[2][2];
-        const T s01 = m * (G[0][1] + G[1][0]);
-        const T s02 = m * (G[0][2] + G[2][0]);
-        const T s12 = m * (G[1][2] + G[2][1]);
+        const TS tr = G[0][0] + G[1][1] + G[2][2];
+        const TS s00 = lt * tr + TS(2) * mt * G[0][0];
+        const TS s11 = lt * tr + TS(2) * mt * G[1][1];
+        const TS s22 = lt * tr + TS(2) * mt * G[2][2];
+        const TS s01 = mt * (G[0][1] + G[1][0]);
+        const TS s02 = mt * (G[0][2] + G[2][0]);
+        const TS s12 = mt * (G[1][2] + G[2][1]);
         out[t * 6 + 0][ly][lx] = s00;
         out[t * 6 + 1][ly][lx] = s11;
         out[t * 6 + 2][ly][lx] = s22;
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         out[t * 6 + 4][ly][lx] = s02;
         out[t * 6 + 5][ly][lx] = s12;
         // the voxel's two tetrahedra in T, added to the FP64 block sum once per voxel
-        if (own) vs += s00 * s00 + s11 * s11 + s22 * s22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
+        if (own) vs += s00 * s00 + s11 * s11 + s22 * s22 + TS(2) * (s01 * s01 + s02 * s02 + s12 * s12);
       }
       if (own) acc[1] += 0.5 * (double)vs;
     }
@@ -491,32 +495,32 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     if (!nact) return;
     const int lx = nlx, ly = nly;
     const int i = x0 + lx, j = y0 + ly;
-    T F[3] = {T(0), T(0), T(0)};
+    TS F[3] = {TS(0), TS(0), TS(0)};
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       // voxel (i - ax, j - ay, z - az): local voxel (lx + 1 - ax, ly + 1 - ay), layer z - az;
       // the node is its corner (ax, ay, az), in tetrahedron T1 (even) or T2 (odd)
       const int q0 = ((ax + ay + az) & 1) * NQ, vy = ly + 1 - ay, vx = lx + 1 - ax;
-      T (*sv)[kVY][kVX] = ss[(z - az) & 1];
-      const T bxw = T(ax ? 0.25 : -0.25), byw = T(ay ? 0.25 : -0.25), bzw = T(az ? 0.25 : -0.25);
+      TS (*sv)[kVY][kVX] = ss[(z - az) & 1];
+      const TS bxw = TS(ax ? 0.25 : -0.25), byw = TS(ay ? 0.25 : -0.25), bzw = TS(az ? 0.25 : -0.25);
       if constexpr (FS) {
 #pragma unroll
         for (int r = 0; r < 3; ++r)
           F[r] += bxw * sv[q0 + 3 * r][vy][vx] + byw * sv[q0 + 3 * r + 1][vy][vx] + bzw * sv[q0 + 3 * r + 2][vy][vx];
         continue;
       }
-      const T s00 = sv[q0 + 0][vy][vx], s11 = sv[q0 + 1][vy][vx], s22 = sv[q0 + 2][vy][vx];
-      const T s01 = sv[q0 + 3][vy][vx], s02 = sv[q0 + 4][vy][vx], s12 = sv[q0 + 5][vy][vx];
+      const TS s00 = sv[q0 + 0][vy][vx], s11 = sv[q0 + 1][vy][vx], s22 = sv[q0 + 2][vy][vx];
+      const TS s01 = sv[q0 + 3][vy][vx], s02 = sv[q0 + 4][vy][vx], s12 = sv[q0 + 5][vy][vx];
       F[0] += bxw * s00 + byw * s01 + bzw * s02;
       F[1] += bxw * s01 + byw * s11 + bzw * s12;
       F[2] += bxw * s02 + byw * s12 + bzw * s22;
     }
     const int xyz[3] = {i, j, z};
-    const T w2b = T(1 << bcount(g, xyz));
+    const TS w2b = TS(1 << bcount(g, xyz));
     T p[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : -w2b * F[c];
+    for (int c = 0; c < 3; ++c) p[c] = is_antisym(g, c, xyz) ? T(0) : (T)(-w2b * F[c]);
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) {
       const int zm = ring4(z - 1), z0 = ring4(z), zp = ring4(z + 1);
@@ -681,8 +685,14 @@ __global__ __launch_bounds__(kBlock) void k_weak_d(Geo g, DeltaBufs<T> D, WeakDe
     const int j = (int)(t % g.N[1]), k = (int)(t / g.N[1]);
     T p[3];
     double sn = 0.0, ms[6];
-    if (g.fs) node_eval_d<T, false, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
-    else node_eval_d<T, false, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    // the stresses in the precision the residual pass of this iteration used
+    if (st->fine) {
+      if (g.fs) node_eval_d<T, false, true, double>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+      else node_eval_d<T, false, false, double>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    } else {
+      if (g.fs) node_eval_d<T, false, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+      else node_eval_d<T, false, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+    }
     const int xyz[3] = {i, j, k};
     scale = (double)(1 << bcount(g, xyz));
     q = (double)p[c] / scale;
@@ -878,10 +888,11 @@ __global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, S
   const int i = (int)(node % g.N[0]);
   const long long q = node / g.N[0];
   const int j = (int)(q % g.N[1]), k = (int)(q / g.N[1]);
+  // reactions are multipliers: the stresses here are formed in FP64 (p rounded once)
   T p[3];
   double sn = 0.0, ms[6];
-  if (g.fs) node_eval_d<T, false, true>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
-  else node_eval_d<T, false, false>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  if (g.fs) node_eval_d<T, false, true, double>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
+  else node_eval_d<T, false, false, double>(g, D.u, D.lam, D.mu, i, j, k, p, sn, ms);
   const int xyz[3] = {i, j, k};
   out[e] = -(double)p[s.comp[e]] / (double)(1 << bcount(g, xyz));
 }
@@ -891,22 +902,32 @@ __global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, S
 // ---------------------------------------------------------------------------
 TileGrid residual_tiles(const Geo& g);
 
-template <typename T>
-int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
-                          int nblk, hipStream_t s) {
+template <typename T, typename TS>
+int launch_delta_residual_ts(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
+                             int nblk, hipStream_t s) {
   const TileGrid tg = residual_tiles(g);
   if (tg.tx > 0) {
     nblk = tg.tx * tg.ty * tg.nseg;
     const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
-    if (g.fs && gen) hipLaunchKernelGGL((k_residual_dt<T, true, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
-    else if (g.fs) hipLaunchKernelGGL((k_residual_dt<T, true, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
-    else if (gen) hipLaunchKernelGGL((k_residual_dt<T, false, true>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
-    else hipLaunchKernelGGL((k_residual_dt<T, false, false>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    if (g.fs && gen) hipLaunchKernelGGL((k_residual_dt<T, true, true, TS>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else if (g.fs) hipLaunchKernelGGL((k_residual_dt<T, true, false, TS>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else if (gen) hipLaunchKernelGGL((k_residual_dt<T, false, true, TS>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
+    else hipLaunchKernelGGL((k_residual_dt<T, false, false, TS>), dim3(nblk), dim3(256), 0, s, g, D, ct, st, part, tg);
   } else {
-    if (g.fs) hipLaunchKernelGGL((k_residual_d<T, true>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
-    else hipLaunchKernelGGL((k_residual_d<T, false>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+    if (g.fs) hipLaunchKernelGGL((k_residual_d<T, true, TS>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
+    else hipLaunchKernelGGL((k_residual_d<T, false, TS>), dim3(nblk), dim3(kBlock), 0, s, g, D, ct, st, part);
   }
   return nblk;
+}
+
+// The pass with T stresses, and (refine) the pass with FP64 stresses; the device state's flag
+// selects the one that works, the other returns at once.  Both write the same partial rows.
+template <typename T>
+int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
+                          int nblk, int refine, hipStream_t s) {
+  const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, s);
+  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, s);
+  return rows;
 }
 
 template <typename T>
@@ -946,7 +967,8 @@ static int residual_resident() {
   int r = cache[dev].load(std::memory_order_relaxed);
   if (!r) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false, float>, 256, 0) !=
+            hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -1017,7 +1039,7 @@ void launch_weak_d_stage(const Geo& g, const DeltaBufs<T>& D, const WeakDev& w, 
 }
 
 template int launch_delta_residual<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, DevState*, double*,
-                                          int, hipStream_t);
+                                          int, int, hipStream_t);
 template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
                                           DevState*, const double*, const double*, int, hipStream_t);
 template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);
