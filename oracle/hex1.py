@@ -136,6 +136,49 @@ def iso_stencil(lam0, mu0):
     return st
 
 
+def normal_mixed(plan):
+    """True when no axis is periodic and on every face the normal displacement component and
+    the two tangential ones have opposite symmetries (one held at 0, the others free): then
+    the transform of each component (Table 2) also diagonalises the coupled isotropic operator
+    (Section 3.2.3), frequency by frequency."""
+    if any(plan.periodic):
+        return False
+    for J in range(3):
+        for f in range(2):
+            for c in range(3):
+                if c != J and plan.sym[c, J, f] == plan.sym[J, J, f]:
+                    return False
+    return True
+
+
+class IsoGreenDTT:
+    """Green operator of the isotropic HEX1 reference medium under normal-mixed boundaries,
+    taken from its definition: K0 = 2^b times the in-cell isotropic HEX1 stiffness on the DOFs
+    that are not held at 0 (the boundary-weighted reference operator of eq 3), assembled as a
+    dense matrix column by column, and its pseudo-inverse (the operator vanishes on the
+    hourglass lines).  Small grids only (dense)."""
+
+    def __init__(self, plan, lam0, mu0):
+        if not normal_mixed(plan):
+            raise ValueError("the isotropic Green operator needs periodic or normal-mixed boundaries")
+        self.plan = plan
+        self.shape = (3,) + tuple(plan.N[J] for J in (2, 1, 0))
+        self.idx = np.flatnonzero(~plan.amask.ravel())
+        K = np.zeros((self.idx.size, self.idx.size))
+        for col, e in enumerate(self.idx):
+            u = np.zeros(self.shape)
+            u.ravel()[e] = 1.0
+            q = -plan.w2b[None] * divergence(iso(gradients(u, plan), lam0, mu0), plan)
+            K[:, col] = q.ravel()[self.idx]
+        self.K = K
+        self.Kinv = np.linalg.pinv(K, rcond=1e-11)
+
+    def apply(self, p):
+        u = np.zeros(self.shape)
+        u.ravel()[self.idx] = self.Kinv @ p.ravel()[self.idx]
+        return u
+
+
 class IsoGreenPeriodic:
     """u_hat = M(theta)^+ p_hat per frequency, complex FFT over a fully periodic cell."""
 

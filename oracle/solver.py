@@ -136,7 +136,8 @@ class Solver:
         self.lam0, self.mu0 = lam0, mu0
         self.scheme, self.reference = scheme, reference
         if reference == "iso":
-            self.green = hex1.IsoGreenPeriodic(self.plan, lam0, mu0)
+            self.green = (hex1.IsoGreenPeriodic(self.plan, lam0, mu0) if all(self.plan.periodic)
+                          else hex1.IsoGreenDTT(self.plan, lam0, mu0))
             if scheme != "hex1":
                 raise ValueError("the isotropic reference medium is built for the HEX1 scheme")
         else:

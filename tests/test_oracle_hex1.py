@@ -210,3 +210,100 @@ def test_isotropic_and_paux_media_reach_the_same_solution():
     assert np.abs(outs["paux"]["f_weak"] - outs["iso"]["f_weak"]).max() < 1e-8 * np.abs(outs["iso"]["f_weak"]).max()
     # the isotropic medium needs fewer iterations here (19 against 29 when measured)
     assert outs["iso"]["iterations"] < outs["paux"]["iterations"]
+
+
+# -- isotropic medium under normal-mixed DTT boundaries ------------------------------------
+
+def _normal_mixed_bc(normal):
+    """normal[J][f]: the normal component's condition on face f of axis J (0 Neumann,
+    1 Dirichlet); the two tangential components take the other one."""
+    bc = np.zeros((3, 3, 2), np.int8)
+    for J in range(3):
+        for f in range(2):
+            for c in range(3):
+                bc[c, J, f] = normal[J][f] if c == J else 1 - normal[J][f]
+    return bc
+
+
+def _spectral_iso_green(plan, lam0, mu0, p):
+    """An independent evaluation of the same Green operator: each component transformed by
+    its own DTT (scipy), coefficients aligned on a common frequency index per axis, and per
+    frequency the 3x3 symbol of the periodic medium, mu0 |d|^2 I + (lam0 + mu0) d d^T with
+    d_J = 2 sin(theta_J / 2) prod_{K != J} cos(theta_K / 2), conjugated by the sign s_J = +1
+    (normal component sine-type on axis J) or -1 (cosine-type): derivatives turn a cosine of
+    the tangential components into a sine of the normal one with a minus sign, and back with a
+    plus sign, so the coupling term of components i and j carries s_i s_j."""
+    from oracle.green import forward_dt, inverse_dt
+    n = plan.n
+    kinds = [plan.types[J][J] for J in range(3)]
+    th = [np.pi * np.arange(n[J] + 1) / n[J] if kinds[J] in ("DCT1", "DST1")
+          else np.pi * (np.arange(n[J] + 1) + 0.5) / n[J] for J in range(3)]
+    sgn = np.array([1.0 if kinds[J].startswith("DST") else -1.0 for J in range(3)])
+    shape = tuple(n[J] + 1 for J in (2, 1, 0))
+    X = np.zeros((3,) + shape)
+    pos = []
+    for c in range(3):
+        coef = forward_dt(p[c], plan, c)
+        sl = tuple(slice(1, n[J]) if plan.types[c][J] == "DST1" else slice(0, coef.shape[2 - J])
+                   for J in (2, 1, 0))
+        X[(c,) + sl] = coef
+        pos.append(sl)
+    tz, ty, tx = np.meshgrid(th[2], th[1], th[0], indexing="ij")
+    t = [tx, ty, tz]
+    d = np.stack([2 * np.sin(t[J] / 2) * np.prod([np.cos(t[K] / 2) for K in range(3) if K != J], axis=0)
+                  for J in range(3)])
+    d2 = (d * d).sum(0)
+    Xs = sgn[:, None, None, None] * X
+    dX = (d * Xs).sum(0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        U = (Xs - (lam0 + mu0) / (lam0 + 2 * mu0) * d * dX / d2) / (mu0 * d2)
+    U[:, d2 < 1e-12] = 0.0
+    U *= sgn[:, None, None, None]
+    return np.stack([inverse_dt(U[(c,) + pos[c]], plan, c) for c in range(3)])
+
+
+NM_INVERTIBLE = [[[1, 0], [0, 1], [1, 0]], [[0, 1], [1, 0], [1, 1]], [[1, 0], [1, 0], [0, 1]]]
+NM_SINGULAR = [[[1, 1], [1, 1], [1, 1]], [[0, 0], [1, 1], [0, 0]]]
+
+
+@pytest.mark.parametrize("normal", NM_INVERTIBLE)
+def test_iso_green_dtt_matches_the_spectral_solve(normal):
+    """Where the boundary-weighted operator is invertible (no hourglass line reaches the stored
+    frequencies), its dense inverse and the transform-space solve agree to rounding (a missing
+    sign conjugation fails here)."""
+    plan = Plan((5, 4, 6), _normal_mixed_bc(normal))
+    assert hex1.normal_mixed(plan)
+    g = hex1.IsoGreenDTT(plan, 1.3, 0.7)
+    assert np.linalg.matrix_rank(g.K) == g.K.shape[0]
+    p = np.random.default_rng(5).standard_normal(g.shape)
+    p[plan.amask] = 0.0
+    a, b = g.apply(p), _spectral_iso_green(plan, 1.3, 0.7, p)
+    assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+    # the dense operator is the weighted reference term of the solver, not a transposed copy
+    v = np.random.default_rng(6).standard_normal(g.shape); v[plan.amask] = 0.0
+    s = Solver((5, 4, 6), np.ones((6, 4, 5)), np.ones((6, 4, 5)), _normal_mixed_bc(normal), scheme="hex1",
+               reference="iso", lam0=1.3, mu0=0.7)
+    q = -s.reference_term(hex1.gradients(v, plan))
+    assert np.abs(g.K @ v.ravel()[g.idx] - q.ravel()[g.idx]).max() <= 1e-12 * np.abs(q).max()
+
+
+@pytest.mark.parametrize("normal", NM_SINGULAR)
+def test_iso_green_dtt_singular_boundaries_solve_in_the_range(normal):
+    """With DCT1/DST1 axes the hourglass lines reach stored frequencies and the operator is
+    singular; for a load in its range both solves satisfy K0 u = p."""
+    plan = Plan((5, 4, 6), _normal_mixed_bc(normal))
+    g = hex1.IsoGreenDTT(plan, 1.3, 0.7)
+    assert np.linalg.matrix_rank(g.K) < g.K.shape[0]
+    v = np.random.default_rng(7).standard_normal(g.idx.size)
+    pf = g.K @ v
+    p = np.zeros(g.shape); p.ravel()[g.idx] = pf
+    for u in (g.apply(p), _spectral_iso_green(plan, 1.3, 0.7, p)):
+        assert np.abs(g.K @ u.ravel()[g.idx] - pf).max() <= 1e-10 * np.abs(pf).max()
+
+
+def test_normal_mixed_detection():
+    assert not hex1.normal_mixed(Plan((4, 4, 4), PERIODIC))
+    bc = _normal_mixed_bc([[1, 1], [1, 1], [1, 1]])
+    assert hex1.normal_mixed(Plan((4, 4, 4), bc))
+    bc[1, 0, 0] = 1                       # a tangential component fixed with the normal one
+    assert not hex1.normal_mixed(Plan((4, 4, 4), bc))
