@@ -120,8 +120,10 @@ int fftc_set_bc(fftc_h h, const int8_t* bc_host);
  * al., R0 : grad u = lam0 (grad u o I) + 2 mu0 grad u, one diagonal symbol per component, any
  * boundary table.  FFTC_REF_ISO: the isotropic medium lam0 tr(eps) I + 2 mu0 eps, whose symbol
  * couples the three components (a 3x3 solve per frequency, complex coefficients over periodic
- * axes, Section 3.2.4); it needs the HEX1 scheme, FP64 and all three axes periodic (checked
- * at binding: FFTC_E_UNSUPPORTED).  Requires mu0 > 0 and lam0 + 2 mu0 > 0 (FFTC_E_ARG).  The
+ * axes, Section 3.2.4); it needs the HEX1 scheme, FP64, and either all three axes periodic or
+ * normal-mixed faces: no periodic axis and, on every face, the normal component held at 0
+ * with both tangential ones free or the reverse (then each component's DTT also diagonalises
+ * the coupled medium).  Other tables: FFTC_E_UNSUPPORTED at binding.  Requires mu0 > 0 and lam0 + 2 mu0 > 0 (FFTC_E_ARG).  The
  * kind is fixed at binding (FFTC_E_STATE afterwards).  Default: Paux, max(lam), max(mu). */
 #define FFTC_REF_PAUX 0
 #define FFTC_REF_ISO 1

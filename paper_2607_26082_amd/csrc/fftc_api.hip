@@ -139,6 +139,18 @@ bool factor_ok(int n, std::vector<int>& rad) {
 
 int sym_of(int code) { return code == FFTC_BC_DIRICHLET ? 1 : (code == FFTC_BC_NEUMANN ? 0 : 2); }  // 1 = A
 
+// No periodic axis, and on every face the normal component's symmetry differs from that of
+// both tangential components (then the DTTs diagonalise the coupled isotropic medium).
+bool normal_mixed(const fftc_problem* h) {
+  for (int J = 0; J < 3; ++J) {
+    if (h->periodic[J]) return false;
+    for (int f = 0; f < 2; ++f)
+      for (int c = 0; c < 3; ++c)
+        if (c != J && sym_of(h->bc[c * 6 + J * 2 + f]) == sym_of(h->bc[J * 6 + J * 2 + f])) return false;
+  }
+  return true;
+}
+
 // Table 2: symmetries on the two faces -> transform
 int type_of(int s0, int s1) {
   if (s0 == 2) return T_DFT;
@@ -1192,8 +1204,9 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
     return fail(h, FFTC_E_UNSUPPORTED, "the HEX1 scheme runs in FP64 (its hourglass modes have no FP32 residual form)");
   if (h->scheme == FFTC_HEX1 && h->has_sphere) return fail(h, FFTC_E_UNSUPPORTED, "contact uses the TETRA2 scheme");
   if (h->ref_kind == FFTC_REF_ISO &&
-      (h->scheme != FFTC_HEX1 || !h->periodic[0] || !h->periodic[1] || !h->periodic[2]))
-    return fail(h, FFTC_E_UNSUPPORTED, "the isotropic reference medium needs HEX1 and periodic axes");
+      (h->scheme != FFTC_HEX1 || !((h->periodic[0] && h->periodic[1] && h->periodic[2]) || normal_mixed(h))))
+    return fail(h, FFTC_E_UNSUPPORTED,
+                "the isotropic reference medium needs HEX1 and periodic axes or normal-mixed faces");
   if (((uintptr_t)ws) % kAlign) return fail(h, FFTC_E_WORKSPACE, "workspace must be 256-byte aligned");
   const size_t need = carve(h, nullptr);
   if (bytes < need) return fail(h, FFTC_E_WORKSPACE, "workspace too small");
@@ -1229,7 +1242,11 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   g.aface = h->aface;
   g.fs = h->fs;
   g.hex = h->scheme == FFTC_HEX1;
-  g.iso = h->ref_kind == FFTC_REF_ISO;
+  g.iso = h->ref_kind != FFTC_REF_ISO ? 0 : (h->periodic[0] && h->periodic[1] && h->periodic[2]) ? 1 : 2;
+  for (int J = 0; J < 3; ++J) {
+    const int tn = h->type[J][J];   // the normal component's transform on axis J
+    g.iso_axis[J] = ((tn == T_DCT3 || tn == T_DST3) ? 1 : 0) | ((tn == T_DST1 || tn == T_DST3) ? 2 : 0);
+  }
   // singular modes of each component: theta = 0 needs DCT1 or DFT on all axes; theta = pi
   // additionally needs an even length on DFT axes
   for (int c = 0; c < 3; ++c) {

@@ -43,7 +43,10 @@ struct Geo {
   double sing_scale[3];   // inverse-transform factor of one singular coefficient (prod 1/2n or 1/n)
   int fs;                 // finite strain: Saint-Venant-Kirchhoff PK1 in place of the linear stress
   int hex;                // HEX1 scheme (centre gradient, one integration point) instead of TETRA2
-  int iso;                // isotropic reference medium (coupled Green operator; periodic cells)
+  int iso;                // isotropic reference medium: 1 periodic cell, 2 normal-mixed DTT faces
+  // normal-mixed faces, per axis: bit 0 half frequencies (DCT3/DST3), bit 1 the normal component
+  // is sine-type (DST) and the tangential ones cosine-type (the reverse when 0)
+  int iso_axis[3];
   double lam0, mu0;       // reference medium
 };
 

@@ -677,7 +677,62 @@ __global__ __launch_bounds__(kBlock) void k_green_iso(Geo g, double* buf, DevSta
               Tu[c][a1][a2][a3] * inv_ns;
 }
 
+// The isotropic medium under normal-mixed faces (no periodic axis; on every face the normal
+// component and the tangential ones have opposite symmetries).  On each axis the normal and
+// the tangential components then use complementary transforms (DCT1/DST1 or DCT3/DST3) with
+// the same angle at the same storage index, and one frequency (k1, k2, k3) holds the
+// coefficients of all three components at node index (k1, k2, k3).  Derivatives map the
+// cosine of a tangential component to the sine of the normal one with a minus sign and back
+// with a plus sign, so the symbol is S M S, with M the real periodic symbol above and
+// S = diag(s_J), s_J = +1 where the normal component is sine-type and -1 where it is
+// cosine-type.  A component absent at a frequency (a DST1 line at k = 0 or n) decouples there
+// (its factor of d vanishes) and is left untouched.
+__global__ __launch_bounds__(kBlock) void k_green_iso_dtt(Geo g, double* buf, DevState* st, int force) {
+  if (!force && st->done) return;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= g.Nn) return;
+  const int Nx = g.N[0], Ny = g.N[1];
+  const int k[3] = {(int)(e % Nx), (int)((e / Nx) % Ny), (int)(e / ((long long)Nx * Ny))};
+  double th[3], sg[3];
+  bool pres[3] = {true, true, true};
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    const int half = g.iso_axis[J] & 1, nsin = (g.iso_axis[J] >> 1) & 1;
+    th[J] = 3.14159265358979323846264338327950288 * (k[J] + (half ? 0.5 : 0.0)) / g.n[J];
+    sg[J] = nsin ? 1.0 : -1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int sine = (c == J) ? nsin : !nsin;
+      const int lo = (!half && sine) ? 1 : 0;
+      const int hi = (half || sine) ? g.n[J] - 1 : g.n[J];
+      pres[c] = pres[c] && k[J] >= lo && k[J] <= hi;
+    }
+  }
+  double X[3], d[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) X[c] = pres[c] ? sg[c] * buf[c * g.Nn + e] : 0.0;
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    d[J] = 2.0 * sin(0.5 * th[J]) * cos(0.5 * th[(J + 1) % 3]) * cos(0.5 * th[(J + 2) % 3]);
+  const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double U[3] = {0.0, 0.0, 0.0};
+  if (d2 > 1e-13) {
+    const double bcoef = (g.lam0 + g.mu0) / (g.lam0 + 2.0 * g.mu0);
+    const double dX = d[0] * X[0] + d[1] * X[1] + d[2] * X[2];
+    const double inv = 1.0 / (g.mu0 * d2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) U[c] = (X[c] - bcoef * d[c] * dX / d2) * inv;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (pres[c]) buf[c * g.Nn + e] = sg[c] * U[c];
+}
+
 void launch_green_iso(const Geo& g, double* buf, DevState* st, int force, hipStream_t s) {
+  if (g.iso == 2) {
+    hipLaunchKernelGGL(k_green_iso_dtt, dim3(grid_for(g.Nn, 1 << 30)), dim3(kBlock), 0, s, g, buf, st, force);
+    return;
+  }
   const long long ncls = (long long)(g.n[0] / 2 + 1) * (g.n[1] / 2 + 1) * (g.n[2] / 2 + 1);
   hipLaunchKernelGGL(k_green_iso, dim3(grid_for(ncls, 1 << 30)), dim3(kBlock), 0, s, g, buf, st, force);
 }

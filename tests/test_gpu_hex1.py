@@ -8,7 +8,7 @@ import pytest
 import workloads as W
 from oracle import hex1
 from oracle.solver import Solver as OSolver
-from test_oracle_hex1 import _hex1_case
+from test_oracle_hex1 import NM_INVERTIBLE, NM_SINGULAR, _hex1_case, _normal_mixed_bc
 
 pytestmark = pytest.mark.gpu
 
@@ -128,3 +128,79 @@ def test_solve_periodic_hex1(ref):
     assert np.abs(Gg - Go).max() <= 1e-10 * np.abs(Go).max()
     _, rel, _ = g.reactions()
     assert np.abs(rel - o["f_weak"]).max() <= 1e-10 * np.abs(o["f_weak"]).max()
+
+
+# -- isotropic medium under normal-mixed DTT faces ------------------------------------------
+
+NM_SHAPES = [(5, 4, 6), (9, 8, 6), (6, 10, 5)]
+
+
+@pytest.mark.parametrize("i", range(len(NM_SHAPES)))
+def test_stage_green_iso_normal_mixed(i):
+    """Green stage of the isotropic medium on normal-mixed faces (every transform type on some
+    axis) against the oracle's dense inverse of the weighted reference operator, to 50 ulps of
+    that operator's condition number."""
+    F = _lib()
+    n = NM_SHAPES[i]
+    bc = _normal_mixed_bc(NM_INVERTIBLE[i])
+    print(f"[iso normal-mixed green] n={n} normal={NM_INVERTIBLE[i]}", flush=True)
+    rng = np.random.default_rng(140 + i)
+    lam, mu = _stiff(rng, n)
+    o = OSolver(n, lam, mu, bc, r0_factor=0.8, scheme="hex1", reference="iso")
+    g = F.Solver(n, lam, mu, bc, r0_factor=0.8, precision="fp64", scheme="hex1", reference="iso")
+    p = rng.standard_normal(o.zeros().shape)
+    p[o.plan.amask] = 0.0
+    ref_u = o.green.apply(p)
+    out = g.stage_green(p)
+    tol = max(1e-12, 50 * 2.2e-16 * np.linalg.cond(o.green.K))
+    assert np.abs(out - ref_u).max() <= tol * np.abs(ref_u).max()
+
+
+@pytest.mark.parametrize("normal", NM_SINGULAR)
+def test_stage_green_iso_normal_mixed_singular(normal):
+    """DCT1/DST1 faces: hourglass lines reach stored frequencies, the operator is singular;
+    for a load in its range the GPU output solves K0 u = p (it differs from the oracle's
+    minimum-norm solution by a null vector)."""
+    F = _lib()
+    n = (5, 4, 6)
+    bc = _normal_mixed_bc(normal)
+    print(f"[iso normal-mixed green singular] normal={normal}", flush=True)
+    rng = np.random.default_rng(150)
+    lam, mu = _stiff(rng, n)
+    o = OSolver(n, lam, mu, bc, r0_factor=0.8, scheme="hex1", reference="iso")
+    g = F.Solver(n, lam, mu, bc, r0_factor=0.8, precision="fp64", scheme="hex1", reference="iso")
+    K, idx = o.green.K, o.green.idx
+    pf = K @ rng.standard_normal(idx.size)
+    p = np.zeros(o.zeros().shape); p.ravel()[idx] = pf
+    out = g.stage_green(p)
+    assert np.abs(K @ out.ravel()[idx] - pf).max() <= 1e-10 * np.abs(pf).max()
+
+
+def test_solve_iso_normal_mixed():
+    """A heterogeneous HEX1 cell on normal-mixed faces with half-frequency transforms (no
+    hourglass line is stored, so a strong condition is well posed) plus a face average: same
+    iteration count as the oracle at 1e-8, and the converged (1e-12) displacement and
+    reactions to 1e-10."""
+    F = _lib()
+    n = (6, 5, 7)
+    nx, ny, nz = n
+    bc = _normal_mixed_bc([[1, 0], [0, 1], [1, 0]])
+    rng = np.random.default_rng(160)
+    lam, mu = _stiff(rng, n)
+    strong = [W.Strong(np.array([[3, 2, 3]]), np.array([0], np.int8), np.array([0.02]))]
+    face = np.stack(np.meshgrid([2, 3], [1, 2], [2], indexing="ij"), -1).reshape(1, 4, 3)
+    avg = [W.Average(face, np.array([2], np.int8), np.array([-0.03]), set_id=1)]
+    print("[iso normal-mixed solve]", flush=True)
+    kw = dict(r0_factor=1.0, scheme="hex1", reference="iso")
+    o = OSolver(n, lam, mu, bc, strong, avg, **kw).solve(tol=1e-8, max_iter=4000)
+    g = F.Solver(n, lam, mu, bc, strong, avg, precision="fp64", tol=1e-8, max_iter=4000, **kw)
+    rc, rep = g.solve()
+    assert o["converged"] and rc == 0 and rep.iterations == o["iterations"]
+    o = OSolver(n, lam, mu, bc, strong, avg, **kw).solve(tol=1e-12, max_iter=4000)
+    g = F.Solver(n, lam, mu, bc, strong, avg, precision="fp64", tol=1e-12, max_iter=4000, **kw)
+    rc, rep = g.solve()
+    assert rc == 0
+    u = g.u.cpu().numpy()
+    assert np.linalg.norm(u - o["u"]) <= 1e-10 * np.linalg.norm(o["u"])
+    _, rel, tot = g.reactions()
+    assert np.abs(tot - o["totals"]).max() <= 1e-10 * np.abs(o["totals"]).max()

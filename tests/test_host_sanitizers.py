@@ -24,6 +24,9 @@ def _runtime():
 def test_host_abi_under_sanitizers():
     if not os.path.exists(B.SAN_OUT):
         pytest.skip("libfftc_hostsan.so not built (paper_2607_26082_amd/build.py --hostsan)")
+    srcs = [os.path.join(B.HERE, "csrc", f) for f in os.listdir(os.path.join(B.HERE, "csrc"))]
+    if max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(B.SAN_OUT):
+        pytest.skip("libfftc_hostsan.so is older than its sources (build.py --hostsan -i rebuilds it)")
     rt = _runtime()
     if rt is None:
         pytest.skip("ASan runtime of the ROCm clang not found")
