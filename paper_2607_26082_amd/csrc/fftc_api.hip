@@ -233,7 +233,7 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(sizeof(double) * (mw + 1));
   off[q++] = L.take(sizeof(double) * (mw + 1));
   int maxN = std::max(h->N[0], std::max(h->N[1], h->N[2]));
-  off[q++] = L.take(sizeof(double) * 18 * maxN);
+  off[q++] = L.take((sizeof(double) + sizeof(float)) * 18 * maxN);   // symbol tables, FP64 then FP32
   for (int J = 0; J < 3; ++J) off[q++] = L.take(2 * ts * 4 * (size_t)h->n[J]);
   off[q++] = L.take(8 * (ms + 1));
   off[q++] = L.take(ms + 1);
@@ -399,6 +399,7 @@ DttArgs<T> dtt_args(fftc_problem* h, int axis, int mode, int force) {
   a.st = h->st;
   a.force = force;
   a.cosT = h->cosT;
+  a.cosT32 = (const float*)(h->cosT + 18 * (size_t)h->maxN);
   a.maxN = h->maxN;
   // the symbol vanishes only at theta = 0 and (pi, pi, pi) (exact zeros of the factored
   // form); any positive value is at least ~ a theta_min^2, far above this threshold
@@ -1306,6 +1307,9 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
         cosT[((c * 3 + J) * 2 + 1) * h->maxN + idx] = at_pi ? 0.0 : cs * cs;
       }
   HIPCHK(h, hipMemcpyAsync(h->cosT, cosT.data(), 8 * cosT.size(), hipMemcpyHostToDevice, s));
+  // the same tables rounded to FP32, read by the FP32 Green step
+  std::vector<float> cosT32(cosT.begin(), cosT.end());
+  HIPCHK(h, hipMemcpyAsync(h->cosT + cosT.size(), cosT32.data(), 4 * cosT32.size(), hipMemcpyHostToDevice, s));
   // node mask
   std::vector<uint8_t> mask(h->Nn, 0);
   for (size_t e = 0; e < h->s_node.size(); ++e) mask[h->s_node[e]] |= (uint8_t)(M_STRONG << h->s_comp[e]);

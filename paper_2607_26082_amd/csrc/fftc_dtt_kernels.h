@@ -597,13 +597,16 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     else fft_ct<T, NF, +1, NT>(cb, CS, tw, ld);
   }
   if (a.mode == PASS_FWD_GREEN_INV) {
-    // (z lines: block = x chunk bxi of the y plane byi)
-    const double* sxT = a.cosT + ((c * 3 + 0) * 2 + 0) * a.maxN;
-    const double* qxT = a.cosT + ((c * 3 + 0) * 2 + 1) * a.maxN;
-    const double* syT = a.cosT + ((c * 3 + 1) * 2 + 0) * a.maxN;
-    const double* qyT = a.cosT + ((c * 3 + 1) * 2 + 1) * a.maxN;
-    const double* szT = a.cosT + ((c * 3 + 2) * 2 + 0) * a.maxN;
-    const double* qzT = a.cosT + ((c * 3 + 2) * 2 + 1) * a.maxN;
+    // (z lines: block = x chunk bxi of the y plane byi); symbol tables in T
+    const T* tab;
+    if constexpr (sizeof(T) == 4) tab = a.cosT32;
+    else tab = a.cosT;
+    const T* sxT = tab + ((c * 3 + 0) * 2 + 0) * a.maxN;
+    const T* qxT = tab + ((c * 3 + 0) * 2 + 1) * a.maxN;
+    const T* syT = tab + ((c * 3 + 1) * 2 + 0) * a.maxN;
+    const T* qyT = tab + ((c * 3 + 1) * 2 + 1) * a.maxN;
+    const T* szT = tab + ((c * 3 + 2) * 2 + 0) * a.maxN;
+    const T* qzT = tab + ((c * 3 + 2) * 2 + 1) * a.maxN;
     // symbol in the transform's precision: M = qz A(x, y) + sz B(x, y) with
     // A = 4 (a0 sx qy + a1 sy qx + a2 sx sy), B = 4 (a0 qx sy + a1 qy sx + a2 qx qy)
     const T sy = (T)syT[(int)byi], qy = (T)qyT[(int)byi];
@@ -618,7 +621,12 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
       const T A = T(4) * (a0 * sx * qy + a1 * sy * qx + e2 * sx * sy);
       const T B = T(4) * (e0 * qx * sy + e1 * qy * sx + a2 * qx * qy);
       const T M = (T)qzT[m] * A + (T)szT[m] * B;
-      return (M > thr) ? v / M : T(0);
+      if constexpr (sizeof(T) == 4) {
+        // FP32: times the hardware reciprocal (1 ulp) in place of the IEEE division sequence
+        return (M > thr) ? v * __builtin_amdgcn_rcpf(M) : T(0);
+      } else {
+        return (M > thr) ? v / M : T(0);
+      }
     };
     T vals[NB + 1];
 #pragma unroll

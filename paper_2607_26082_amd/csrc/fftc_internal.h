@@ -159,6 +159,7 @@ struct DttArgs {
   int force;
   // Green (z pass)
   const double* cosT;          // [3 comps][3 axes][2][maxN]: sin^2(theta/2), cos^2(theta/2)
+  const float* cosT32;         // the same, rounded to FP32
   int maxN;
   int inv_types[3];
   double thr[3];
