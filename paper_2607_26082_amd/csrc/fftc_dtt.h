@@ -252,9 +252,10 @@ __device__ __forceinline__ void fft_ct(cplx<T>* cb, int CS, const cplx<T>* __res
 #pragma unroll
       for (int q = 0; q < R2; ++q) {
         cplx<T> v = cb[l * CS + cpad<NF>(j + q * B2)];
-        if (q > 0 && kk > 0) {
+        if (q > 0) {
           // W_{R1 R2}^{q kk} = e^{SGN 2 pi i q kk / NF}; the table holds e^{-2 pi i s / 4NF}
-          // for s <= 2 NF only, and q kk < NF: past NF / 2 use e^{-i pi} = -1
+          // for s <= 2 NF only, and q kk < NF: past NF / 2 use e^{-i pi} = -1.  At kk = 0 the
+          // factor is the table's exact (1, 0), so no lane takes a separate path.
           const int jj = q * kk;
           const bool hi = jj > NF / 2;
           cplx<T> f = tw[4 * (hi ? jj - NF / 2 : jj)];

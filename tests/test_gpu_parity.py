@@ -333,7 +333,11 @@ def test_stiffness_reset(prec):
 def test_uniaxial_strain_closed_form(prec):
     """Homogeneous block on lateral rollers, top face pressed by delta: the exact field
     u_z = delta z / L, the top reaction total sigma_zz nx ny and the reported mean stress
-    (lam, lam, lam + 2 mu) delta / L with no shear (closed forms, no oracle involved)."""
+    (lam, lam, lam + 2 mu) delta / L with no shear (closed forms, no oracle involved).
+    The FP32 form runs with reference factor 2: at factor 1 the plain map stagnates on this
+    block (its residual stays at 0.93), the iterate differences the FP32 least squares fits
+    are then FP32 rounding noise, and whether 1e-6 is reached within the iteration limit
+    depends on the rounding (FP64 solves it in five iterations at either factor)."""
     F = _lib()
     n = (16, 12, 32)
     nx, ny, nz = n
@@ -346,8 +350,10 @@ def test_uniaxial_strain_closed_form(prec):
     bc[2, 2, 0] = 1
     top = _box(np.arange(nx + 1), np.arange(ny + 1), [nz])
     strong = [W.Strong(top, np.full(len(top), 2, np.int8), np.full(len(top), delta))]
-    g = F.Solver(n, lam, mu, bc, strong, (), r0_factor=1.0, precision=prec, tol=1e-12 if prec == "fp64" else 1e-6)
+    g = F.Solver(n, lam, mu, bc, strong, (), r0_factor=1.0 if prec == "fp64" else 2.0, precision=prec,
+                 tol=1e-12 if prec == "fp64" else 1e-6)
     rc, rep = g.solve()
+    print(f"[uniaxial strain] {prec}: {rep.iterations} iterations, residual {rep.residual:.2e}", flush=True)
     assert rc == 0
     u = g.u.cpu().numpy().reshape(3, nz + 1, ny + 1, nx + 1)
     exact = delta * np.arange(nz + 1)[:, None, None] / nz * np.ones((nz + 1, ny + 1, nx + 1))
