@@ -79,6 +79,16 @@ typedef struct {
                         * residual pass forms the stresses in FP64 (their rounding in
                         * FP32 is a noise floor of about 3e-7 of ||sigma|| on p); all
                         * fields stay FP32.  0 keeps FP32 stresses to the end.      */
+  int32_t anchor_every; /* FP32 form on small-strain problems without obstacle,
+                        * singular modes or relations: the residual pass forms
+                        * p_i = p_{i-1} + the divergence term of the stresses of
+                        * delta_i = u_i - u_{i-1} (eq 3 is linear in u there), so that
+                        * the Anderson differences carry no cancellation against |p|;
+                        * every anchor_every-th iteration (and every one below
+                        * refine_below) forms p from u.  An incremental iteration never
+                        * ends the solve: the convergence test is taken on a pass from
+                        * u.  0 forms p from u every iteration.  >= 0.            */
+  int32_t reserved;     /* 0                                                         */
 } fftc_solver_cfg;
 
 typedef struct {
@@ -178,8 +188,9 @@ int fftc_set_sphere(fftc_h h, const double center_host[3], double radius, int32_
 #define FFTC_FINITE_STRAIN 1
 int fftc_set_kinematics(fftc_h h, int32_t kind);
 
-/* Solver settings; defaults {1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2, 1e-5}.  FFTC_E_ARG for a
- * negative tolerance, max_iter or refine_below, a period below 1 or an unknown acv. */
+/* Solver settings; defaults {1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2, 1e-5, 16, 0}.  FFTC_E_ARG for
+ * a negative tolerance, max_iter, refine_below or anchor_every, a period below 1 or an
+ * unknown acv. */
 int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg);
 
 /* Device workspace needed by the current set-up (grid, precision, constraints). */
@@ -255,13 +266,16 @@ int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev);
  * and the control step, on caller state.  In: u (FP64), delta = u_i - u_{i-1}, e = the last
  * Green input minus K0 u_{i-1}, p_prev, R_prev (FP64 device node fields converted to FP32;
  * NULL = zero), i_local = the Anderson index of the iteration (R is formed from 1 on, its
- * differences from 2 on), fp64_stress = 1 for the pass that forms the stresses in FP64 (the
- * one taken once the residual is below refine_below), 0 for FP32 stresses.  Out (FP64
+ * differences from 2 on), pass_kind = 0 for the pass that forms the stresses of u in FP32, 1
+ * for the one that forms them in FP64 (taken once the residual is below refine_below), 2 for
+ * the incremental pass (p = p_prev + the divergence term of the stresses of delta; u is not
+ * read; small strain without obstacle or singular modes, else FFTC_E_UNSUPPORTED).  Out (FP64
  * device node fields, NULL to skip): p after proj_P,
  * R = p + K0 delta - e, dR = R - R_prev, dY = p - p_prev + K0 delta (all 0 at DOFs held at 0),
- * sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.  FP32 handles only (FFTC_E_UNSUPPORTED). */
+ * sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma (0 for pass_kind 2).  FP32 handles only
+ * (FFTC_E_UNSUPPORTED); FFTC_E_ARG for a pass_kind outside 0..2. */
 int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_dev, const double* e_dev,
-                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, int32_t fp64_stress,
+                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, int32_t pass_kind,
                              double* p_dev, double* r_dev, double* dr_dev, double* dy_dev, double* sums_host);
 
 /* Batched form: many independent cells (each a fully set-up, bound handle, possibly of

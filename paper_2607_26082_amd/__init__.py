@@ -32,7 +32,7 @@ STAGES = ("residual", "weak+control", "anderson", "dtt_x_fwd", "dtt_y_fwd", "dtt
 class fftc_solver_cfg(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("acv", C.c_int32),
                 ("depth", C.c_int32), ("period", C.c_int32), ("update_gate", C.c_double),
-                ("refine_below", C.c_double)]
+                ("refine_below", C.c_double), ("anchor_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fftc_report(C.Structure):
@@ -237,10 +237,13 @@ def fftc_set_kinematics(h, kind):
 
 
 def fftc_set_solver(h, tol=1e-6, max_iter=2000, acv=FFTC_ACV_P, depth=4, period=2, update_gate=1e-2,
-                    refine_below=None):
-    """refine_below: FP32 form, residual below which stresses are formed in FP64 (None: 10 tol)."""
+                    refine_below=None, anchor_every=16):
+    """refine_below: FP32 form, residual below which stresses are formed in FP64 (None: 10 tol).
+    anchor_every: FP32 form, period of the residual passes from u between incremental ones
+    (0: every pass from u)."""
     rb = 10.0 * float(tol) if refine_below is None else float(refine_below)
-    cfg = fftc_solver_cfg(float(tol), int(max_iter), int(acv), int(depth), int(period), float(update_gate), rb)
+    cfg = fftc_solver_cfg(float(tol), int(max_iter), int(acv), int(depth), int(period), float(update_gate), rb,
+                          int(anchor_every), 0)
     return _check(h, load().fftc_set_solver(h, C.byref(cfg)), "fftc_set_solver")
 
 
@@ -317,10 +320,10 @@ def fftc_stage_residual(h, u_dev, p_dev=None, ptil_dev=None):
 
 
 def fftc_stage_residual_form(h, u_dev, delta_dev, e_dev, pprev_dev, rprev_dev, i_local, p_dev=None, r_dev=None,
-                             dr_dev=None, dy_dev=None, fp64_stress=0):
+                             dr_dev=None, dy_dev=None, pass_kind=0):
     sums = np.zeros(2)
     _check(h, load().fftc_stage_residual_form(h, _dev(u_dev), _dev(delta_dev), _dev(e_dev), _dev(pprev_dev),
-                                              _dev(rprev_dev), int(i_local), int(fp64_stress), _dev(p_dev), _dev(r_dev),
+                                              _dev(rprev_dev), int(i_local), int(pass_kind), _dev(p_dev), _dev(r_dev),
                                               _dev(dr_dev), _dev(dy_dev), _ptr(sums, C.c_double)),
            "fftc_stage_residual_form")
     return sums
@@ -562,7 +565,7 @@ class Solver:
     def __init__(self, n, lam, mu, bc, strong=(), average=(), sphere=None, r0_factor=1.0,
                  precision="fp64", tol=1e-6, max_iter=2000, acv="P", period=2, gate=1e-2, device="cuda",
                  smooth=(), static_workspace=False, finite_strain=False, scheme="tetra2", reference="paux",
-                 voxel=1.0, refine_below=None):
+                 voxel=1.0, refine_below=None, anchor_every=16):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
@@ -589,7 +592,7 @@ class Solver:
             fftc_set_kinematics(self.h, FFTC_FINITE_STRAIN)
         fftc_set_solver(self.h, tol=tol, max_iter=max_iter,
                         acv={"NONE": FFTC_ACV_NONE, "U": FFTC_ACV_U, "P": FFTC_ACV_P}[acv],
-                        period=period, update_gate=gate, refine_below=refine_below)
+                        period=period, update_gate=gate, refine_below=refine_below, anchor_every=anchor_every)
         nbytes = fftc_workspace_bytes(self.h)
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -654,13 +657,16 @@ class Solver:
         sums = fftc_stage_residual(self.h, u_t, p, pt)
         return p.cpu().numpy(), pt.cpu().numpy(), sums
 
-    def stage_residual_form(self, u, delta, e, p_prev, R_prev, i_local, fp64_stress=0):
-        """The FP32 iteration's residual pass on given state: (p, R, dR, dY, sums) as numpy."""
+    def stage_residual_form(self, u, delta, e, p_prev, R_prev, i_local, fp64_stress=0, incremental=False):
+        """The FP32 iteration's residual pass on given state: (p, R, dR, dY, sums) as numpy.
+        fp64_stress: the pass with FP64 stresses; incremental: p = p_prev + the divergence term
+        of the stresses of delta (u not read)."""
         t = self.torch
         dev = [t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
                for a in (u, delta, e, p_prev, R_prev)]
         outs = [t.empty_like(dev[0]) for _ in range(4)]
-        sums = fftc_stage_residual_form(self.h, *dev, i_local, *outs, fp64_stress=fp64_stress)
+        sums = fftc_stage_residual_form(self.h, *dev, i_local, *outs,
+                                        pass_kind=2 if incremental else (1 if fp64_stress else 0))
         return tuple(o.cpu().numpy() for o in outs) + (sums,)
 
     def stage_green(self, ptil):

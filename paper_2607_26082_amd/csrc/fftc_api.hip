@@ -54,7 +54,7 @@ struct fftc_problem {
   int has_sphere = 0;
   double center[3] = {0, 0, 0}, radius = 0;
   int face = 5;
-  fftc_solver_cfg cfg{1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2, 1e-5};
+  fftc_solver_cfg cfg{1e-6, 2000, FFTC_ACV_P, 4, 2, 1e-2, 1e-5, 16, 0};
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -444,6 +444,16 @@ struct StageTimer {
   }
 };
 
+// Period of the full residual passes between incremental ones (0: every pass from u).  The
+// incremental pass needs the FP32 form on a tiled small-strain problem with no obstacle, no
+// singular modes and no relations (their projections and multipliers are formed from u).
+int inc_period(const fftc_problem* h) {
+  if (!h->delta_mode || h->fs || h->has_sphere || h->cfg.anchor_every <= 0) return 0;
+  if (h->g.sing[0] || h->g.sing[1] || h->g.sing[2] || weak_dev(const_cast<fftc_problem*>(h)).m > 0) return 0;
+  if (residual_tiles(h->g, false).tx <= 0) return 0;
+  return h->cfg.anchor_every;
+}
+
 void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
   DeltaBufs<float> D = dbufs(h);
   const ContactDev ct = contact_dev(h);
@@ -452,7 +462,8 @@ void enqueue_delta_iteration(fftc_problem* h, StageTimer* tm) {
   const long long n3 = 3 * h->Nn;
   hipStream_t s = h->stream;
   if (tm) tm->mark(s);
-  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, h->cfg.refine_below > 0.0, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, h->cfg.refine_below > 0.0,
+                                                inc_period(h) > 0, s);
   if (tm) tm->mark(s);
   launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
   if (tm) tm->mark(s);
@@ -577,6 +588,7 @@ int init_state(fftc_problem* h) {
   hs.contact = h->has_sphere;
   hs.refine_below = h->delta_mode ? h->cfg.refine_below : 0.0;
   hs.fine = 0;
+  hs.inc_k = inc_period(h);
   h->init_host = hs;
   HIPCHK(h, hipMemcpyAsync(h->st, &h->init_host, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
   return FFTC_OK;
@@ -771,30 +783,36 @@ int stage_residual_t(fftc_problem* h, const double* u_dev, double* p_dev, double
   return FFTC_OK;
 }
 
-// One residual pass of the FP32 residual-form iteration on caller state (iteration 0 of the
-// ping-pong, local Anderson index il): u (FP64), delta, e, p_prev, R_prev in, p, R, dR, dY
-// out (FP64 copies), sums[0] = ||p||^2, sums[1] = sum (1/2) sigma:sigma.
-int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, int fp64_stress, double* const* out,
+// One residual pass of the FP32 residual-form iteration on caller state (local Anderson index
+// il; kind 0: stresses of u in FP32, 1: in FP64, 2: the incremental pass): u (FP64), delta, e,
+// p_prev, R_prev in, p, R, dR, dY out (FP64 copies), sums[0] = ||p||^2, sums[1] = sum (1/2)
+// sigma:sigma (0 for the incremental pass).  The pass reads c = p_prev - e, formed here.
+int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, int kind, double* const* out,
                           double* sums) {
   DeltaBufs<float> D = dbufs(h);
   hipStream_t s = h->stream;
   const long long n3 = 3 * h->Nn;
   const int slot = (il + 1) % 3;
+  // iteration parity: the incremental pass runs at it = 1 of a period of 2
+  const int it = kind == 2 ? 1 : 0;
   HIPCHK(h, hipMemcpyAsync(D.u, in[0], 8 * n3, hipMemcpyDeviceToDevice, s));
   float* const Rcur = D.R[il & 3];
   float* const Rprev = D.R[(il + 3) & 3];
-  float* dst[4] = {D.delta, D.e, D.p[1], Rprev};
+  float* const pprev = D.p[(it & 1) ^ 1];
+  float* dst[4] = {D.delta, D.e, pprev, Rprev};
   for (int q = 0; q < 4; ++q) {
     if (in[q + 1]) launch_convert<double, float>(in[q + 1], dst[q], n3, s);
     else HIPCHK(h, hipMemsetAsync(dst[q], 0, 4 * n3, s));
   }
+  launch_diff<float>(pprev, D.e, D.e, n3, s);   // c = p_prev - e
   for (int q = 0; q < 3; ++q) HIPCHK(h, hipMemsetAsync(D.dY[q], 0, 4 * n3, s));
   DevState hs{};
   hs.acv = FFTC_ACV_P;
   hs.i_local = il;
-  hs.it = 0;
-  hs.accel_ok = 1;   // e is the caller's, not p_prev
-  hs.fine = fp64_stress ? 1 : 0;
+  hs.it = it;
+  hs.accel_ok = 1;   // c comes from the caller's e, not 0
+  hs.fine = kind == 1 ? 1 : 0;
+  hs.inc_k = kind == 2 ? 2 : 0;
   hs.tol = 0.0;
   hs.max_iter = 1 << 30;
   hs.period = h->cfg.period;
@@ -804,11 +822,11 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, int 
   const ContactDev ct = contact_dev(h);
   const WeakDev w = weak_dev(h);
   if (ct.on) launch_contact_init<double>(h->g, D.u, ct, s);
-  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, 1, s);
+  const int nres = launch_delta_residual<float>(h->g, D, ct, h->st, h->part, h->nblk_res, 1, kind == 2, s);
   launch_delta_control<float>(h->g, D, ct, w, h->st, h->part, h->wpart, nres, s);
   // R difference as the Gram pass forms it, from the R ring (staged in the transform buffer)
   if (out[2]) launch_diff<float>(Rcur, Rprev, D.t, n3, s);
-  const float* src[4] = {D.p[0], Rcur, D.t, D.dY[slot]};
+  const float* src[4] = {D.p[it & 1], Rcur, D.t, D.dY[slot]};
   for (int q = 0; q < 4; ++q)
     if (out[q]) launch_convert<float, double>(src[q], out[q], n3, s);
   if (sums) {
@@ -1182,7 +1200,7 @@ int fftc_set_solver(fftc_h h, const fftc_solver_cfg* cfg) {
   if (!h || !cfg) return FFTC_E_ARG;
   if (cfg->depth != 4) return fail(h, FFTC_E_UNSUPPORTED, "Anderson depth must be 4");
   if (cfg->period < 1 || cfg->max_iter < 0 || !(cfg->tol >= 0.0) || cfg->acv < 0 || cfg->acv > 2 ||
-      !(cfg->refine_below >= 0.0))
+      !(cfg->refine_below >= 0.0) || cfg->anchor_every < 0)
     return fail(h, FFTC_E_ARG, "invalid solver settings");
   if (h->bound && cfg->acv == FFTC_ACV_U && h->nlit < 10)
     return fail(h, FFTC_E_STATE, "ACV_U in FP32 needs its Anderson fields: set it before binding the workspace");
@@ -1376,7 +1394,9 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
   }
-  (void)residual_tiles(h->g);   // occupancy query of the residual pass, outside any capture
+  // occupancy queries of the residual pass instances, outside any capture
+  (void)residual_tiles(h->g, false);
+  (void)residual_tiles(h->g, true);
   if (h->nblk_res >= 8) h->nblk_res -= h->nblk_res % 8;   // whole slabs per XCD
   if (h->nblk_res < 1) h->nblk_res = 1;
   for (int q = 0; q < h->nlit; ++q)
@@ -1800,14 +1820,18 @@ int fftc_stage_residual(fftc_h h, const double* u_dev, double* p_dev, double* pt
 }
 
 int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_dev, const double* e_dev,
-                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, int32_t fp64_stress,
+                             const double* pprev_dev, const double* rprev_dev, int32_t i_local, int32_t pass_kind,
                              double* p_dev, double* r_dev, double* dr_dev, double* dy_dev, double* sums_host) {
-  if (!h || !u_dev || i_local < 0 || fp64_stress < 0 || fp64_stress > 1) return FFTC_E_ARG;
+  if (!h || !u_dev || i_local < 0 || pass_kind < 0 || pass_kind > 2) return FFTC_E_ARG;
   if (!h->bound || !h->stiff_set) return fail(h, FFTC_E_STATE, "workspace and stiffness must be set");
   if (h->precision != FFTC_FP32) return fail(h, FFTC_E_UNSUPPORTED, "the residual form is the FP32 iteration");
+  if (pass_kind == 2 && (h->fs || h->has_sphere || h->g.sing[0] || h->g.sing[1] || h->g.sing[2] ||
+                         residual_tiles(h->g, false).tx <= 0))
+    return fail(h, FFTC_E_UNSUPPORTED, "the incremental pass is for tiled small-strain problems without obstacle "
+                                       "or singular modes");
   const double* in[5] = {u_dev, delta_dev, e_dev, pprev_dev, rprev_dev};
   double* out[4] = {p_dev, r_dev, dr_dev, dy_dev};
-  return stage_residual_form_t(h, in, i_local, fp64_stress, out, sums_host);
+  return stage_residual_form_t(h, in, i_local, pass_kind, out, sums_host);
 }
 
 int fftc_stage_green(fftc_h h, const double* ptil_dev, double* u_dev) {

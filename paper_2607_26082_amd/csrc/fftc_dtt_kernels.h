@@ -347,9 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_dtt(DttArgs<T> a) {
         } else if (a.src == SRC_DELTA) {
           v = a.dp2[a.st->it & 1][addr];
           if (a.st->accel_ok) {
-            v = v - ((T)a.st->gamma[0] * a.dY[0][addr] + (T)a.st->gamma[1] * a.dY[1][addr] +
-                     (T)a.st->gamma[2] * a.dY[2][addr]);
-            a.de[addr] = v;   // stored only when it differs from p
+            const T k = (T)a.st->gamma[0] * a.dY[0][addr] + (T)a.st->gamma[1] * a.dY[1][addr] +
+                        (T)a.st->gamma[2] * a.dY[2][addr];
+            v = v - k;
+            a.de[addr] = k;   // c = p - e, stored only when it is not 0
           }
         } else {
           v = a.in[addr];
@@ -515,24 +516,27 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
   const bool tail_ok = has_tail && (int)tid < nl;
   const unsigned tail_off = tid * ls + (unsigned)NF * es;
   // gather the real lines into LDS: all loads of a thread are issued before any store (the
-  // stores of S or e would otherwise hold back the next loads: the pointers may alias)
+  // stores of S or c would otherwise hold back the next loads: the pointers may alias).
+  // fetch(off, k) returns the value to transform and sets k, the value keep(off, v, k) may store.
   auto gather = [&](auto fetch, auto keep) {
     by_map([&](auto mk) {
-      T vals[NB + 1];
+      T vals[NB + 1], kv[NB + 1];
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         unsigned l, m;
         body(mk, i, l, m);
-        vals[i] = ((int)l < nl) ? fetch(l * ls + m * es) : T(0);
+        kv[i] = T(0);
+        vals[i] = ((int)l < nl) ? fetch(l * ls + m * es, kv[i]) : T(0);
       }
-      vals[NB] = tail_ok ? fetch(tail_off) : T(0);
+      kv[NB] = T(0);
+      vals[NB] = tail_ok ? fetch(tail_off, kv[NB]) : T(0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         unsigned l, m;
         body(mk, i, l, m);
-        if ((int)l < nl) keep(l * ls + m * es, vals[i]);
+        if ((int)l < nl) keep(l * ls + m * es, vals[i], kv[i]);
       }
-      if (tail_ok) keep(tail_off, vals[NB]);
+      if (tail_ok) keep(tail_off, vals[NB], kv[NB]);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         unsigned l, m;
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
     const T* X = a.B.X + base;
     const double al0 = al[0], al1 = al[1], al2 = al[2], al3 = al[3];
     gather(
-        [&](unsigned off) -> T {
+        [&](unsigned off, T&) -> T {
           if (acc_ok) {
             double s = al0 * ((double)S0[off] + (double)R0[off]);
             s += al1 * ((double)S1[off] + (double)R1[off]);
@@ -565,7 +569,7 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
           }
           return X[off];
         },
-        [&](unsigned off, T v) {
+        [&](unsigned off, T v, T) {
           if (store_s) Sout[off] = v;
         });
   } else if (a.src == SRC_DELTA) {
@@ -575,19 +579,23 @@ __global__ __launch_bounds__(NTH) void k_dtt2(DttArgs<T> a) {
             g2 = acc_ok ? (T)a.st->gamma[2] : T(0);
     const T *y0 = a.dY[0] + base, *y1 = a.dY[1] + base, *y2 = a.dY[2] + base;
     T* de = a.de + base;
-    // e is stored only when it differs from p (the next residual pass reads p otherwise)
+    // e = p - c with c = sum_j gamma_j dY_j; c is stored (only when it is not 0): the next
+    // residual pass forms R = dY + c, with no cancellation against |p|
     gather(
-        [&](unsigned off) -> T {
+        [&](unsigned off, T& k) -> T {
           T v = pcur[off];
-          if (acc_ok) v = v - (g0 * y0[off] + g1 * y1[off] + g2 * y2[off]);
+          if (acc_ok) {
+            k = g0 * y0[off] + g1 * y1[off] + g2 * y2[off];
+            v = v - k;
+          }
           return v;
         },
-        [&](unsigned off, T v) {
-          if (acc_ok) de[off] = v;
+        [&](unsigned off, T, T k) {
+          if (acc_ok) de[off] = k;
         });
   } else {
     const T* in = a.in + base;
-    gather([&](unsigned off) -> T { return in[off]; }, [&](unsigned, T) {});
+    gather([&](unsigned off, T&) -> T { return in[off]; }, [&](unsigned, T, T) {});
   }
   __syncthreads();
   const int inv_first = (a.mode == PASS_INV);

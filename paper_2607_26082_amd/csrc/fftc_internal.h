@@ -56,7 +56,8 @@ struct DevState {
   int store_r, accel, accel_ok, acv;
   int have_prev, updates, restarts, vpar;
   int period, max_iter, contact, nC;
-  int vnonempty, fine, pad2, pad3;   // fine: the FP32 form forms stresses in FP64 (sticky)
+  int vnonempty, fine, inc_k, pad3;  // fine: the FP32 form forms stresses in FP64 (sticky);
+                                     // inc_k > 0: incremental passes, a full one every inc_k
   double tol, gate, residual, pnorm2;
   double snorm2, refine_below;
   double ms[6];
@@ -67,6 +68,16 @@ struct DevState {
 };
 
 enum StatusCode { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
+
+// Residual pass of the FP32 form's current iteration: PASS_U = stresses of u in FP32,
+// PASS_INC = p_{i-1} plus the divergence of the stresses of delta_i, PASS_U64 = stresses of u
+// in FP64 (below the refinement threshold).  The launched instances and the control kernel
+// take the same decision from the same state.
+enum ResPass { PASS_U = 0, PASS_INC = 1, PASS_U64 = 2 };
+__device__ __forceinline__ int res_pass(const DevState* st) {
+  if (st->fine) return PASS_U64;
+  return (st->inc_k > 0 && st->it % st->inc_k != 0) ? PASS_INC : PASS_U;
+}
 
 struct AxisPlan {
   int n;                   // transform length (voxels on the axis)
@@ -169,7 +180,7 @@ struct DttArgs {
   int dst;                     // DST_BUF or DST_UPDATE (x inverse pass: delta and FP64 u update)
   const T* dp2[2];             // p ping-pong buffers (SRC_DELTA, selected by iteration parity)
   const T* dY[3];              // Y-difference ring (SRC_DELTA)
-  T* de;                       // Green input e written by the x forward pass (SRC_DELTA)
+  T* de;                       // correction c = p - e written by the x forward pass (SRC_DELTA)
   double* u64;                 // FP64 displacement (DST_UPDATE)
   T* delta;                    // displacement increment (DST_UPDATE)
 };
@@ -179,9 +190,9 @@ template <typename T>
 struct DeltaBufs {
   double* u;                 // displacement (FP64)
   T* delta;                  // u_i - u_{i-1}
-  T* e;                      // Green input of the last iteration
+  T* e;                      // c = p - e of the last combination: sum_j gamma_j dY_j
   T* p[2];                   // residual after proj_P (ping-pong by iteration parity)
-  T* R[4];                   // R_i = p_i + K0 delta_i - e_{i-1}, ring by local iteration (i & 3)
+  T* R[4];                   // R_i = p_i + K0 delta_i - e_{i-1} = dY_i + c_{i-1}, ring (i & 3)
   T* dY[3];                  // Y differences (ring of 3)
   T* t;                      // transform buffer
   const T* lam;

@@ -378,6 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   const int vpar = st->vpar, it = st->it, max_iter = st->max_iter, have_prev = st->have_prev;
   const int acv = st->acv, period = st->period, i_local0 = st->i_local, fine0 = st->fine;
   const double tol = st->tol, gate = st->gate, refine_below = st->refine_below;
+  // the FP32 form's incremental pass forms no stress norm: the last full pass's is kept, and
+  // such a pass never ends the solve (the exit test is taken on a pass from u)
+  const bool inc = res_pass(st) == PASS_INC;
+  const double sn_kept = st->snorm2;
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double pn = acc[0], sn = acc[1];
+    const double pn = acc[0], sn = inc ? sn_kept : acc[1];
     st->pnorm2 = pn;
     st->snorm2 = sn;
     for (int q = 0; q < 6; ++q) st->ms[q] = acc[2 + q];
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
     if (!isfinite(pn) || !isfinite(sn)) {
       st->status = ST_NAN;
       s_done = 1;
-    } else if (res < tol && !nonempty) {
+    } else if (res < tol && !nonempty && !inc) {
       st->status = ST_CONVERGED;
       s_done = 1;
     } else if (it >= max_iter) {
@@ -431,6 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
       // restart iterations amplify the error on cells where the plain map diverges
       // (measured on a homogeneous block: 1e-5 -> 0.26 within four iterations).
       if (!fine0 && refine_below > 0.0 && res < refine_below) st->fine = 1;
+      // an incremental pass below the tolerance: the remaining passes are from u
+      if (inc && res < tol) st->inc_k = 0;
     }
     if (s_done) st->done = 1;
   }

@@ -13,17 +13,18 @@ void launch_control(DevState* st, const double* part, int nblk, const double* wp
                     const ContactDev& ct, int pstride, hipStream_t s);
 // Residual-form iteration, first half: the residual pass (returns the number of block
 // partial rows it wrote), then the average relations and the control step over those rows.
-// refine: also launch the FP64-stress pass (taken once the state's refinement flag is set).
+// refine: also launch the FP64-stress pass (taken once the state's refinement flag is set);
+// inc: also launch the incremental pass (taken between the state's full passes).
 template <typename T>
 int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
-                          int nblk, int refine, hipStream_t s);
+                          int nblk, int refine, int inc, hipStream_t s);
 template <typename T>
 void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, const WeakDev& w, DevState* st,
                           const double* part, const double* wpart, int nblk, hipStream_t s);
 // Tile grid of the tiled residual pass on the current device.  Its first call on a device
 // queries the kernel's occupancy, which must not happen under stream capture: call it once
 // outside capture (the workspace binding does) before capturing iterations.
-TileGrid residual_tiles(const Geo& g);
+TileGrid residual_tiles(const Geo& g, bool inc);
 template <typename T>
 void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
 template <typename T>

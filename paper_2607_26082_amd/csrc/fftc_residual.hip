@@ -154,43 +154,45 @@ __device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
 
 // Per-node part of the residual pass of the residual-form iteration, once p is known:
 // singular-mode coefficients of u, contact bookkeeping or constraint masking, the norm of
-// p, p itself, and (ACV_P, from the second iteration on) R_i = p_i + K0 delta_i - e_{i-1}
-// and dY_i = p_i - p_{i-1} + K0 delta_i.  The R differences are not stored: R_i goes to a
-// ring of four, from which the Gram pass forms them with the same FP32 subtraction.
-// kd = K0 delta at the node (read only when kd_used).
-// Node inputs of the tail that do not depend on p: mask, e_{i-1}, p_{i-1}.  e_{i-1} is read
-// only when the last iteration combined its Anderson history (ecomb); otherwise it equals
-// p_{i-1}, which the transform pass then did not store.
+// p, p itself, and (ACV_P, from the second iteration on) dY_i = p_i - p_{i-1} + K0 delta_i and
+// R_i = p_i + K0 delta_i - e_{i-1} = dY_i + c_{i-1}, with c = p - e the correction of the last
+// Anderson combination (0 after a plain iteration).  R_i goes to a ring of four, from which the
+// Gram pass forms the differences with the same FP32 subtraction.  kd = K0 delta at the node
+// (read only when kd_used).
+// INC: p holds the increment dp_i (the divergence term of the stresses of delta_i) and p_i is
+// p_{i-1} + dp_i; dY and R are formed from dp_i itself, so that they carry no cancellation
+// against |p| (p_i - p_{i-1} in FP32 is rounding noise once the iteration stagnates).
+// Node inputs of the tail that do not depend on p: mask, c_{i-1}, p_{i-1}.
 template <typename T>
 struct TailIn {
   uint8_t m;
-  T e[3], pp[3];
+  T c[3], pp[3];
 };
 
 template <typename T>
-__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, int il, int ecomb,
+__device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, bool kd_used, bool inc, int ecomb,
                                           const T* pp, long long node, TailIn<T>& t) {
   t.m = D.mask[node];
-  // a uniform choice of source (no branch around the loads); when e is p_{i-1} the second
-  // load of the same address is served by the cache
-  const T* es = ecomb ? D.e : pp;
+  // a uniform choice of source (no branch around the loads): after a plain iteration c is 0
+  // and the second load of p_{i-1} is served by the cache
+  const T* cs = ecomb ? D.e : pp;
+  const T cw = ecomb ? T(1) : T(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    t.e[c] = T(0);
+    t.c[c] = T(0);
     t.pp[c] = T(0);
-    if (kd_used) {
-      t.e[c] = es[c * Nn + node];
-      if (il >= 2) t.pp[c] = pp[c * Nn + node];
-    }
+    if (kd_used || inc) t.pp[c] = pp[c * Nn + node];
+    if (kd_used) t.c[c] = cw * cs[c * Nn + node];
   }
 }
 
 // GEN = false: no rigid obstacle and no singular modes (both checked by the launcher).
-template <typename T, bool GEN>
+template <typename T, bool GEN, bool INC = false>
 __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, int cur,
                                            bool kd_used, int il, int slot, T* pc, T* Rc, int i, int j, int k,
                                            long long node, T p[3], const T kd[3], const TailIn<T>& tin,
                                            double* acc) {
+  static_assert(!(GEN && INC), "the incremental pass has no contact or singular modes");
   const long long Nn = g.Nn;
   const int xyz[3] = {i, j, k};
   // singular-mode coefficients of u (projection Pi of the update)
@@ -202,6 +204,8 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
     if (g.sing[c] & 2) acc[9 + 2 * c] += ((i + j + k) & 1) ? -wu : wu;
   }
   const uint8_t m = tin.m;
+  // dp: p_i - p_{i-1} as formed (INC: the increment itself, after the masking below)
+  T dp[3];
   if (GEN && ct.on && (m & M_FACE)) {
     const long long f = (long long)xyz[ct.b1] + (long long)g.N[ct.b1] * xyz[ct.b2];
     const double X0 = i + D.u[node], X1 = j + D.u[Nn + node], X2 = k + D.u[2 * Nn + node];
@@ -221,11 +225,19 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
     ct.fnc[f] = fnc;
     ct.gap[f] = gap;
     acc[0] += (double)p[0] * p[0] + (double)p[1] * p[1] + (double)p[2] * p[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dp[c] = p[c] - tin.pp[c];
   } else {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (m & (M_STRONG << c)) p[c] = T(0);
-      else if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
+      if constexpr (INC) {
+        dp[c] = p[c];
+        p[c] = tin.pp[c] + dp[c];
+      } else {
+        dp[c] = p[c] - tin.pp[c];
+      }
+      if (!(m & (M_WEAK << c))) acc[0] += (double)p[c] * p[c];
     }
   }
 #pragma unroll
@@ -237,19 +249,21 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
       // At a DOF held at 0 by a Dirichlet face p is 0 and K0 delta is taken from the
       // symmetric image; the transforms drop these entries, but they stay in the Gram matrix
       // of the differences (measured: zeroing them makes the FP32 least squares less robust).
-      Rc[e] = p[c] + kd[c] - tin.e[c];
-      if (il >= 2) D.dY[slot][e] = p[c] - tin.pp[c] + kd[c];
+      const T y = dp[c] + kd[c];
+      Rc[e] = y + tin.c[c];
+      if (il >= 2) D.dY[slot][e] = y;
     }
   }
 }
 
 // TS: stress arithmetic (T, or FP64 once the residual is below the refinement threshold);
-// the instance whose TS does not match the state's flag returns at once.
+// the instance whose kind is not the state's pass of this iteration returns at once (this
+// untiled pass has no incremental form: its problems take the full pass every iteration).
 template <typename T, bool FS, typename TS>
 __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                        double* __restrict__ part) {
   __shared__ double sh[kPartStrideD * 16];
-  if (st->done || st->fine != (int)(sizeof(TS) == 8)) return;
+  if (st->done || res_pass(st) != (sizeof(TS) == 8 ? PASS_U64 : PASS_U)) return;
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
@@ -276,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
     T kd[3] = {T(0), T(0), T(0)};
     if (kd_used) stencil_k0<T>(g, D.delta, i, j, k, kd);
     TailIn<T> tin;
-    tail_load<T>(D, Nn, kd_used, il, ecomb, pp, node, tin);
+    tail_load<T>(D, Nn, kd_used, false, ecomb, pp, node, tin);
     delta_tail<T, true>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, k, node, p, kd, tin, acc);
   }
   block_sum<kPartStrideD>(acc, sh);
@@ -303,17 +317,22 @@ constexpr int kPR = (kPlane + 255) / 256;     // of them per thread
 // slot of node plane p in the four-plane ring of delta planes (p may be -1)
 __device__ __forceinline__ int ring4(int p) { return p & 3; }
 
-template <typename T, bool FS, bool GEN, typename TS>
+// INC: the incremental pass (small strain, no contact or singular modes): the stresses are
+// those of delta_i, formed in T from the delta planes, and p_i = p_{i-1} + their divergence
+// term; u is not read and no stress norm is formed (the control keeps the last full pass's).
+template <typename T, bool FS, bool GEN, typename TS, bool INC = false>
 __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
                                                      double* __restrict__ part, TileGrid tg) {
+  static_assert(!INC || (!FS && !GEN && sizeof(TS) == sizeof(T)), "incremental pass: small strain, T stresses");
   constexpr int NQ = FS ? 9 : 6;      // stored stress components per tetrahedron (PK1: all nine)
-  __shared__ double su[2][3][kHY][kHX];
+  __shared__ double su_raw[INC ? 1 : 2 * 3 * kHY * kHX];
+  double (*su)[3][kHY][kHX] = reinterpret_cast<double (*)[3][kHY][kHX]>(su_raw);
   __shared__ T sdl[4][3][kHY][kHX];
   __shared__ TS ss[2][2 * NQ][kVY][kVX];   // stress component q of the voxels of a layer (in TS)
   // the final block sum reuses the stress buffer (block_sum starts with a barrier)
   static_assert(sizeof(ss) >= sizeof(double) * kPartStrideD * 16, "block-sum scratch");
   double* sh = reinterpret_cast<double*>(&ss[0][0][0][0]);
-  if (st->done || st->fine != (int)(sizeof(TS) == 8)) return;
+  if (st->done || res_pass(st) != (INC ? PASS_INC : (sizeof(TS) == 8 ? PASS_U64 : PASS_U))) return;
   const int tid = threadIdx.x;
   // contiguous ranges of tiles per XCD (blocks go to the 8 XCDs round-robin), so that
   // neighbouring tiles share their halo lines in one L2
@@ -334,6 +353,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   const int il = st->i_local, par = st->it & 1, acvp = (st->acv == 2), ecomb = st->accel_ok;
   const int slot = (il + 1) % 3;
   const bool kd_used = acvp && il >= 1;
+  const bool dl = INC || kd_used;   // delta planes staged
   T* pc = D.p[par];
   const T* pp = D.p[par ^ 1];
   T* Rc = D.R[il & 3];
@@ -344,7 +364,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   // Node planes are fetched into registers one step ahead and committed to LDS the next
   // step.  u: su[pz & 1], nodes outside the grid read as 0 (no voxel uses them); delta:
   // sdl[pz mod 4] with the stencil's halo (mirror or periodic image).
-  double ru[kPR];
+  double ru[INC ? 1 : kPR];
   T rd[kPR];
   auto fetch = [&](int pz) {
     int gz = pz;
@@ -356,7 +376,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
 #pragma unroll
     for (int r = 0; r < kPR; ++r) {
       const int e = tid + 256 * r;
-      ru[r] = 0.0;
+      if constexpr (!INC) ru[r] = 0.0;
       rd[r] = T(0);
       if (e < kPlane) {
         const int c = e / (kHY * kHX), q = e - c * (kHY * kHX);
@@ -367,8 +387,9 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
         else ok = ok && gx >= 0 && gx < Nx;
         if (g.periodic[1]) gy = (gy + Ny) % Ny;
         else ok = ok && gy >= 0 && gy < Ny;
-        if (ok) ru[r] = D.u[c * Nn + gx + Nx * (gy + Ny * gz)];
-        if (kd_used) {
+        if constexpr (!INC)
+          if (ok) ru[r] = D.u[c * Nn + gx + Nx * (gy + Ny * gz)];
+        if (dl) {
           const int mx = mirror_coord(g, x0 - 1 + hx, 0), my = mirror_coord(g, y0 - 1 + hy, 1);
           if (okm && mx >= 0 && mx < Nx && my >= 0 && my < Ny) rd[r] = D.delta[c * Nn + mx + Nx * (my + Ny * mz)];
         }
@@ -376,14 +397,14 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     }
   };
   auto commit = [&](int pz) {
-    double* du = &su[pz & 1][0][0][0];
+    double* du = INC ? nullptr : &su[pz & 1][0][0][0];
     T* dd = &sdl[ring4(pz)][0][0][0];
 #pragma unroll
     for (int r = 0; r < kPR; ++r) {
       const int e = tid + 256 * r;
       if (e < kPlane) {
-        du[e] = ru[r];
-        if (kd_used) dd[e] = rd[r];
+        if constexpr (!INC) du[e] = ru[r];
+        if (dl) dd[e] = rd[r];
       }
     }
   };
@@ -424,16 +445,30 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       }
       const TS lt = (TS)l, mt = (TS)m;
       TS d[8][3];
+      if constexpr (INC) {
+        // differences of delta (T) against the voxel's corner 000
+        const int s0 = ring4(lz), s1 = ring4(lz + 1);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double ref = su[lo][c][ly][lx];
+        for (int c = 0; c < 3; ++c) {
+          const T ref = sdl[s0][c][ly][lx];
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) {
-          const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
-          d[cc][c] = cc == 0 ? TS(0) : (TS)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
+          for (int cc = 0; cc < 8; ++cc) {
+            const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+            d[cc][c] = cc == 0 ? TS(0) : (TS)(sdl[cz ? s1 : s0][c][ly + cy][lx + cx] - ref);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double ref = su[lo][c][ly][lx];
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) {
+            const int cx = cc & 1, cy = (cc >> 1) & 1, cz = (cc >> 2) & 1;
+            d[cc][c] = cc == 0 ? TS(0) : (TS)(su[cz ? hi : lo][c][ly + cy][lx + cx] - ref);
+          }
         }
       }
-      const bool own = own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
+      const bool own = !INC && own_z && ux >= x0 && ux < x0 + kTX && ux < nx && uy >= y0 && uy < y0 + kTY && uy < ny;
       TS vs = TS(0);
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -540,7 +575,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
       }
     }
     const long long node = (long long)i + (long long)Nx * ((long long)j + (long long)Ny * z);
-    delta_tail<T, GEN>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
+    delta_tail<T, GEN, INC>(g, D, ct, cur, kd_used, il, slot, pc, Rc, i, j, z, node, p, kd, tin, acc);
   };
 
   T lcur, mcur, lnext, mnext;
@@ -568,7 +603,7 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
     if (nact) {
       const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
-      tail_load<T>(D, g.Nn, kd_used, il, ecomb, pp, node, tin);
+      tail_load<T>(D, g.Nn, kd_used, INC, ecomb, pp, node, tin);
     }
     __syncthreads();
     layer(z, true, lcur, mcur, okcur);
@@ -900,12 +935,11 @@ __global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, S
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-TileGrid residual_tiles(const Geo& g);
+TileGrid residual_tiles(const Geo& g, bool inc);
 
 template <typename T, typename TS>
 int launch_delta_residual_ts(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
-                             int nblk, hipStream_t s) {
-  const TileGrid tg = residual_tiles(g);
+                             int nblk, const TileGrid& tg, hipStream_t s) {
   if (tg.tx > 0) {
     nblk = tg.tx * tg.ty * tg.nseg;
     const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
@@ -920,13 +954,21 @@ int launch_delta_residual_ts(const Geo& g, const DeltaBufs<T>& D, const ContactD
   return nblk;
 }
 
-// The pass with T stresses, and (refine) the pass with FP64 stresses; the device state's flag
-// selects the one that works, the other returns at once.  Both write the same partial rows.
+// The pass with T stresses, (refine) the pass with FP64 stresses and (inc) the incremental
+// pass; the device state selects the one that works, the others return at once.  All write
+// the same partial rows, over one tile grid (sized for the incremental pass when it runs: it
+// takes all but one in inc_k iterations).  inc is taken only for tiled small-strain problems
+// without contact or singular modes (the caller's eligibility test).
 template <typename T>
 int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
-                          int nblk, int refine, hipStream_t s) {
-  const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, s);
-  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, s);
+                          int nblk, int refine, int inc, hipStream_t s) {
+  const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
+  const bool use_inc = inc && !g.fs && !gen;
+  const TileGrid tg = residual_tiles(g, use_inc);
+  const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, tg, s);
+  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, tg, s);
+  if (use_inc && tg.tx > 0)
+    hipLaunchKernelGGL((k_residual_dt<T, false, false, T, true>), dim3(rows), dim3(256), 0, s, g, D, ct, st, part, tg);
   return rows;
 }
 
@@ -959,7 +1001,9 @@ void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
 }
 
 // Blocks of the tiled residual pass resident on the current device at once (blocks per CU
-// at the kernel's register and LDS use, times the CU count), queried once per device.
+// at the kernel's register and LDS use, times the CU count), queried once per device: the
+// pass with T stresses (inc = false) or the incremental one.
+template <bool INC>
 static int residual_resident() {
   static std::atomic<int> cache[64] = {};
   int dev = 0;
@@ -967,8 +1011,8 @@ static int residual_resident() {
   int r = cache[dev].load(std::memory_order_relaxed);
   if (!r) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false, float>, 256, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false, float, INC>, 256,
+                                                     0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -982,24 +1026,34 @@ static int residual_resident() {
 // segments, at most 2048 blocks (the partial-sum rows); tx = 0 when the node plane alone
 // needs more tiles than that.  A block marches its segment's planes plus two planes of
 // prologue, and the blocks run in rounds of the resident count, so the split taken is the
-// one with the fewest (rounds x planes per block); ties go to fewer segments.
-TileGrid residual_tiles(const Geo& g) {
+// one with the fewest (rounds x planes per block); ties go to fewer segments.  inc: the split
+// for the resident count of the incremental pass is taken when its segments are at least 16
+// planes long (shorter ones add more prologue reads than the extra blocks save: measured at
+// 64^3, 2-plane segments on 990 blocks against 3-plane ones on 660).
+TileGrid residual_tiles(const Geo& g, bool inc) {
   TileGrid t{0, 0, 0, 0};
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
   if ((long long)tx * ty > 2048) return t;
   const int Nz = g.N[2];
   const int maxseg = std::max(1, std::min(Nz, 2048 / (tx * ty)));
-  const long long resident = residual_resident();
-  long long best = -1;
-  int bseg = Nz;
-  for (int ns = 1; ns <= maxseg; ++ns) {
-    const int seg = (Nz + ns - 1) / ns;
-    const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
-    const long long cost = (blocks + resident - 1) / resident * (seg + 2);
-    if (best < 0 || cost < best) {
-      best = cost;
-      bseg = seg;
+  auto split = [&](long long resident) {
+    long long best = -1;
+    int bseg = Nz;
+    for (int ns = 1; ns <= maxseg; ++ns) {
+      const int seg = (Nz + ns - 1) / ns;
+      const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
+      const long long cost = (blocks + resident - 1) / resident * (seg + 2);
+      if (best < 0 || cost < best) {
+        best = cost;
+        bseg = seg;
+      }
     }
+    return bseg;
+  };
+  int bseg = split(residual_resident<false>());
+  if (inc) {
+    const int iseg = split(residual_resident<true>());
+    if (iseg >= 16) bseg = iseg;
   }
   t.tx = tx;
   t.ty = ty;
@@ -1039,7 +1093,7 @@ void launch_weak_d_stage(const Geo& g, const DeltaBufs<T>& D, const WeakDev& w, 
 }
 
 template int launch_delta_residual<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, DevState*, double*,
-                                          int, int, hipStream_t);
+                                          int, int, int, hipStream_t);
 template void launch_delta_control<float>(const Geo&, const DeltaBufs<float>&, const ContactDev&, const WeakDev&,
                                           DevState*, const double*, const double*, int, hipStream_t);
 template void launch_delta_anderson<float>(const DeltaBufs<float>&, long long, DevState*, double*, int, hipStream_t);

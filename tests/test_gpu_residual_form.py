@@ -113,3 +113,50 @@ def test_mean_stress_of_returned_iterate(idx):
     want = np.array([M[0, 0], M[1, 1], M[2, 2], M[1, 2], M[0, 2], M[0, 1]])
     scale = np.abs(sig).mean()
     assert np.abs(np.array(rep.mean_stress) - want).max() <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+@pytest.mark.parametrize("dscale", [2e-2, 1e-7])
+def test_stage_residual_form_incremental(idx, dscale):
+    """The incremental pass (small strain, no obstacle, singular modes or relations): p = p_prev +
+    the divergence term of the stresses of delta, u not read.  With p_prev = the oracle's p of
+    u - delta (eq 3), p must equal the oracle's p of u, and dY = p(u) - p(u - delta) + K0 delta,
+    R = p + K0 delta - e as in the pass from u.  dscale 1e-7: an update far below u, as when the
+    iteration stagnates; there dY is held to 2e-6 of its own size, which the pass from u (p_i -
+    p_{i-1} of two FP32 fields of size |p|) cannot meet (printed for comparison)."""
+    F = _lib()
+    n, per, fs = SHAPES[idx]
+    assert not fs
+    print(f"[residual form, incremental] n={n} periodic={per} delta scale={dscale}", flush=True)
+    lam, mu, bc, strong, _ = _case(70 + idx, n, per)
+    o = OSolver(n, lam, mu, bc, strong, (), r0_factor=1.3)
+    g = F.Solver(n, lam, mu, bc, strong, (), r0_factor=1.3, precision="fp32")
+    rng = np.random.default_rng(100 + idx)
+    shape = o.zeros().shape
+    A = o.plan.amask
+    u = rng.standard_normal(shape) * 1e-2
+    u[A] = 0.0
+    o.cons.proj_U(u)
+    delta = rng.standard_normal(shape) * dscale
+    delta[A] = 0.0
+    e = rng.standard_normal(shape) * 2e-2
+    e[A] = 0.0
+    R_prev = rng.standard_normal(shape) * 2e-2
+    R_prev[A] = 0.0
+    p_prev = o.iterate_parts(u - delta)["p"]
+    pe = o.iterate_parts(u)["p"]
+    k0d = -o.reference_term(tetra2.tet_gradients(delta, o.plan))
+    free = ~A
+    dYe = pe - p_prev + k0d
+    Re = pe + k0d - e
+    p, R, dR, dY, sums = g.stage_residual_form(u, delta, e, p_prev, R_prev, 3, incremental=True)
+    assert np.abs(p - pe).max() <= 2e-5 * np.abs(pe).max()
+    assert abs(sums[0] - np.sum(pe[free] ** 2)) <= 2e-4 * np.sum(pe[free] ** 2)
+    assert sums[1] == 0.0
+    err_inc = np.abs(dY - dYe)[free].max() / np.abs(dYe).max()
+    _, _, _, dY_u, _ = g.stage_residual_form(u, delta, e, p_prev, R_prev, 3)
+    err_u = np.abs(dY_u - dYe)[free].max() / np.abs(dYe).max()
+    print(f"[residual form, incremental] dY error / |dY|: incremental {err_inc:.2e}, from u {err_u:.2e}", flush=True)
+    assert err_inc <= 2e-6
+    assert np.abs(R - Re)[free].max() <= 2e-5 * np.abs(Re).max()
+    assert np.abs(dR - (Re - R_prev))[free].max() <= 2e-5 * np.abs(Re - R_prev).max()
