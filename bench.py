@@ -30,9 +30,11 @@ def stage_bytes(N, nv, precision):
     implementation bytes, reported as `moved GB/s`; the roofline uses algorithmic bytes."""
     if precision == "fp32":
         f = 3 * N * 4
+        # residual pass: incremental (read delta, p_prev, c after accelerating iterations, lam, mu;
+        # write p, R, dY), and every 16th iteration from u (also read u in FP64)
+        inc, full = f + f + f / 2 + 2 * nv * 4 + 3 * f, 2 * f + f + f + f / 2 + 2 * nv * 4 + 3 * f
         return {
-            # read u (FP64), delta, p_prev, e (after accelerating iterations), lam, mu; write p, R, dY
-            "residual": 2 * f + 2 * f + f / 2 + 2 * nv * 4 + 3 * f,
+            "residual": (15 * inc + full) / 16,
             "anderson": 4 * f / 2,             # read the ring of four R (accelerating iterations)
             # read p, dY x3 (accelerating); write t, and e (accelerating)
             "dtt_x_fwd": f + 3 * f / 2 + f + f / 2,
@@ -50,9 +52,10 @@ def stage_bytes(N, nv, precision):
 
 def residual_alg_bytes(N, nv, s, precision):
     """Algorithmic bytes of one residual pass (the per-node and per-voxel figures of the
-    byte model below, times the nodes and voxels one launch covers): read u~ (3 values),
-    write p~ (3) and the voxel stiffness pair (2 per voxel); the FP32 residual-form pass also
-    writes the Anderson pair S_i, R_i (6 values) that it forms in place of a separate store."""
+    byte model below, times the nodes and voxels one launch covers): read u~ (3 values; the
+    FP32 form's incremental pass reads its increment instead), write p~ (3) and the voxel
+    stiffness pair (2 per voxel); the FP32 residual-form pass also writes the Anderson pair
+    S_i, R_i (6 values) that it forms in place of a separate store."""
     nodal = 12 if precision == "fp32" else 6
     return s * (nodal * N + 2 * nv)
 
@@ -320,7 +323,9 @@ def main():
                     help="also run a plain 1 GiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-iters", type=int, default=5)
+    ap.add_argument("--profile-iters", type=int, default=16,
+                    help="iterations of the per-stage HIP-event timing (16: one period of the FP32 form's "
+                         "residual passes, fifteen incremental and one from u)")
     ap.add_argument("--workload", default="m256", choices=["m256", "c4", "c5", "nn"],
                     help="m256: 256^3 iteration throughput; c4: 64 uneven cells solved as one batch; "
                          "c5: time to 1e-6 with the learned start vs the plain start on held-out cases; "
@@ -404,7 +409,10 @@ def main():
             # dominant kernel: its algorithmic bytes per launch over its HIP-event time
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                         "traffic": measured_traffic(prec, dom), "kernel": dom, "kernel_ms": round(prof[dom], 4),
+                         "traffic": measured_traffic(prec, dom),
+                         "kernel": dom + (" (k_residual_dt: incremental, from u every 16th iteration)"
+                                          if prec == "fp32" and dom == "residual" else ""),
+                         "kernel_ms": round(prof[dom], 4),
                          "alg_bytes_per_launch": alg},
             # the whole iteration: algorithmic bytes of one iteration x iterations per second
             "iteration_roofline": iteration,

@@ -587,6 +587,13 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   fetch(zb + 1);
   fetch_lm(zb - 1, lcur, mcur, okcur);
   fetch_lm(zb, lnext, mnext, oknext);
+  // the incremental pass (fewer registers) fetches the tail inputs one step ahead
+  TailIn<T> tnext;
+  auto tail_at = [&](int z, TailIn<T>& t) {
+    const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
+    tail_load<T>(D, g.Nn, kd_used, INC, ecomb, pp, node, t);
+  };
+  if (INC && nact) tail_at(zb, tnext);
   __syncthreads();
   layer(zb - 1, false, lcur, mcur, okcur);
   __syncthreads();
@@ -601,9 +608,11 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
     mcur = mnext;
     okcur = oknext;
     if (z + 1 < ze) fetch_lm(z + 1, lnext, mnext, oknext);
-    if (nact) {
-      const long long node = (long long)(x0 + nlx) + (long long)Nx * ((long long)(y0 + nly) + (long long)Ny * z);
-      tail_load<T>(D, g.Nn, kd_used, INC, ecomb, pp, node, tin);
+    if constexpr (INC) {
+      tin = tnext;
+      if (nact && z + 1 < ze) tail_at(z + 1, tnext);
+    } else {
+      if (nact) tail_at(z, tin);
     }
     __syncthreads();
     layer(z, true, lcur, mcur, okcur);
