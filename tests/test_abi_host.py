@@ -96,6 +96,8 @@ def test_average_sphere_solver_reference_validation():
     assert _code(F.fftc_set_solver, h, 1e-6, 100, F.FFTC_ACV_P, 3) == F.FFTC_E_UNSUPPORTED
     assert _code(F.fftc_set_solver, h, 1e-6, 100, F.FFTC_ACV_P, 4, 2, 1e-2, -1.0) == F.FFTC_E_ARG
     assert _code(F.fftc_set_solver, h, -1e-6) == F.FFTC_E_ARG
+    assert _code(F.fftc_set_solver, h, 1e-6, 100, F.FFTC_ACV_P, 4, 2, 1e-2, 1e-5, -1) == F.FFTC_E_ARG
+    F.fftc_set_solver(h, 1e-6, 100, F.FFTC_ACV_P, 4, 2, 1e-2, 1e-5, 0)
     F.fftc_set_solver(h, 1e-6, 100, F.FFTC_ACV_P, 4, 2, 1e-2, 0.0)
     assert _code(F.fftc_set_reference_factor, h, 0.0) == F.FFTC_E_ARG
     assert _code(F.fftc_set_reference, h, 1.0, -1.0) == F.FFTC_E_ARG

@@ -160,3 +160,23 @@ def test_stage_residual_form_incremental(idx, dscale):
     assert err_inc <= 2e-6
     assert np.abs(R - Re)[free].max() <= 2e-5 * np.abs(Re).max()
     assert np.abs(dR - (Re - R_prev))[free].max() <= 2e-5 * np.abs(Re - R_prev).max()
+
+
+def test_incremental_solve_matches_pass_from_u():
+    """Whole FP32 solves of a two-phase cell (strong patch, fixed base) with the incremental pass
+    (a pass from u every 16th iteration, the default) and with the pass from u every iteration:
+    both within 1e-5 (rel-L2) of the FP64 solution at tol 1e-10."""
+    F = _lib()
+    prob = W.m256_metric(n=(40, 36, 28))
+    print("[residual form] incremental vs from-u solves, 40x36x28", flush=True)
+    ref = F.Solver.from_problem(prob, precision="fp64", tol=1e-10, max_iter=4000)
+    rc, rep = ref.solve()
+    assert rc == 0
+    u64 = ref.u.cpu().numpy()
+    for ae in (16, 0):
+        g = F.Solver.from_problem(prob, precision="fp32", tol=1e-6, max_iter=4000, anchor_every=ae)
+        rc, rep = g.solve()
+        assert rc == 0, (ae, rep.iterations)
+        err = np.linalg.norm(g.u.cpu().numpy() - u64) / np.linalg.norm(u64)
+        print(f"[residual form] anchor_every={ae}: {rep.iterations} iterations, rel-L2 to FP64 {err:.2e}", flush=True)
+        assert err <= 1e-5
