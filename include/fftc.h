@@ -75,10 +75,12 @@ typedef struct {
   int32_t depth;       /* Anderson depth; must be 4                                  */
   int32_t period;      /* acceleration period mod_ACV (>= 1)                         */
   double update_gate;  /* contact: residual below which the active set may change   */
-  double refine_below; /* FP32 form: once the residual falls below this value, the
+  double refine_below; /* FP32 form: once the residual falls below this value, or once
+                        * it is below 1e-2 and has not halved in 100 iterations, the
                         * residual pass forms the stresses in FP64 (their rounding in
-                        * FP32 is a noise floor of about 3e-7 of ||sigma|| on p); all
-                        * fields stay FP32.  0 keeps FP32 stresses to the end.      */
+                        * FP32 is a noise floor of about 3e-7 of ||sigma|| on p, higher
+                        * on high-contrast cells); all fields stay FP32.  0 keeps FP32
+                        * stresses to the end.                                      */
   int32_t anchor_every; /* FP32 form on small-strain problems without obstacle,
                         * singular modes or relations: the residual pass forms
                         * p_i = p_{i-1} + the divergence term of the stresses of

@@ -589,6 +589,8 @@ int init_state(fftc_problem* h) {
   hs.refine_below = h->delta_mode ? h->cfg.refine_below : 0.0;
   hs.fine = 0;
   hs.inc_k = inc_period(h);
+  hs.best_res = 1e300;
+  hs.best_it = 0;
   h->init_host = hs;
   HIPCHK(h, hipMemcpyAsync(h->st, &h->init_host, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
   return FFTC_OK;

@@ -56,8 +56,9 @@ struct DevState {
   int store_r, accel, accel_ok, acv;
   int have_prev, updates, restarts, vpar;
   int period, max_iter, contact, nC;
-  int vnonempty, fine, inc_k, pad3;  // fine: the FP32 form forms stresses in FP64 (sticky);
-                                     // inc_k > 0: incremental passes, a full one every inc_k
+  int vnonempty, fine, inc_k, best_it;  // fine: the FP32 form forms stresses in FP64 (sticky);
+                                        // inc_k > 0: incremental passes, a full one every inc_k;
+                                        // best_it: iteration of best_res
   double tol, gate, residual, pnorm2;
   double snorm2, refine_below;
   double ms[6];
@@ -65,6 +66,7 @@ struct DevState {
   double alpha[4];
   double sing[6];     // singular-mode coefficients of u (comp, {theta = 0, theta = pi})
   double gamma[3];    // difference-form Anderson coefficients
+  double best_res;    // FP32 form: residual at the last halving (stagnation test of the refinement)
 };
 
 enum StatusCode { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NOCONV = 2, ST_NAN = 3 };
