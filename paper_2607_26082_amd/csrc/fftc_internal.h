@@ -22,9 +22,10 @@ constexpr uint8_t M_STRONG = 1;      // << comp
 constexpr uint8_t M_WEAK = 8;        // << comp
 constexpr uint8_t M_FACE = 64;       // potential contact node
 
-// blocks of the tiled residual pass: tx * ty node-column tiles, nseg z segments of seg planes
+// blocks of the tiled residual pass: tx * ty node-column tiles, nseg z segments of seg planes;
+// rows = partial-sum rows the control step reads (>= the blocks; the extra ones are cleared)
 struct TileGrid {
-  int tx, ty, nseg, seg;
+  int tx, ty, nseg, seg, rows;
 };
 
 struct Geo {

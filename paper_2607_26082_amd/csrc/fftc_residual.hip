@@ -623,6 +623,9 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   if (threadIdx.x == 0)
 #pragma unroll
     for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+  // rows the control sums beyond this grid (another instance's larger grid): cleared
+  if (blockIdx.x == 0)
+    for (int r = (int)gridDim.x * kPartStrideD + tid; r < tg.rows * kPartStrideD; r += 256) part[r] = 0.0;
 }
 
 // Mean stress of the residual-form iterate, once, when the solve is reported: per voxel the
@@ -973,12 +976,21 @@ int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
                           int nblk, int refine, int inc, hipStream_t s) {
   const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
   const bool use_inc = inc && !g.fs && !gen;
-  const TileGrid tg = residual_tiles(g, use_inc);
-  const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, tg, s);
-  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, tg, s);
-  if (use_inc && tg.tx > 0)
-    hipLaunchKernelGGL((k_residual_dt<T, false, false, T, true>), dim3(rows), dim3(256), 0, s, g, D, ct, st, part, tg);
-  return rows;
+  // the pass from u on the grid for its own resident count, the incremental and FP64-stress
+  // passes on the one for the incremental pass's (fewer rounds for both); the control sums the
+  // larger count of rows, and a pass on the smaller grid clears the rows beyond it
+  TileGrid tf = residual_tiles(g, false);
+  TileGrid ti = use_inc ? residual_tiles(g, true) : tf;
+  if (tf.tx > 0) {
+    const int rows = std::max(tf.tx * tf.ty * tf.nseg, ti.tx * ti.ty * ti.nseg);
+    tf.rows = ti.rows = rows;
+  }
+  const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, tf, s);
+  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, ti, s);
+  if (use_inc && ti.tx > 0)
+    hipLaunchKernelGGL((k_residual_dt<T, false, false, T, true>), dim3(ti.tx * ti.ty * ti.nseg), dim3(256), 0, s, g, D,
+                       ct, st, part, ti);
+  return tf.tx > 0 ? tf.rows : rows;
 }
 
 template <typename T>
@@ -1040,7 +1052,7 @@ static int residual_resident() {
 // planes long (shorter ones add more prologue reads than the extra blocks save: measured at
 // 64^3, 2-plane segments on 990 blocks against 3-plane ones on 660).
 TileGrid residual_tiles(const Geo& g, bool inc) {
-  TileGrid t{0, 0, 0, 0};
+  TileGrid t{0, 0, 0, 0, 0};
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
   if ((long long)tx * ty > 2048) return t;
   const int Nz = g.N[2];
@@ -1068,6 +1080,7 @@ TileGrid residual_tiles(const Geo& g, bool inc) {
   t.ty = ty;
   t.seg = bseg;
   t.nseg = (Nz + bseg - 1) / bseg;
+  t.rows = tx * ty * t.nseg;
   return t;
 }
 
