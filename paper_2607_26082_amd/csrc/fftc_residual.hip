@@ -166,6 +166,7 @@ __device__ __forceinline__ double sing_weight(const Geo& g, const int xyz[3]) {
 template <typename T>
 struct TailIn {
   uint8_t m;
+  T cw;   // 1 after an accelerating iteration, else 0 (c is then p_{i-1}, read in its place)
   T c[3], pp[3];
 };
 
@@ -174,16 +175,20 @@ __device__ __forceinline__ void tail_load(const DeltaBufs<T>& D, long long Nn, b
                                           const T* pp, long long node, TailIn<T>& t) {
   t.m = D.mask[node];
   // a uniform choice of source (no branch around the loads): after a plain iteration c is 0
-  // and the second load of p_{i-1} is served by the cache
+  // and the second load of p_{i-1} is served by the cache.  The pass from u applies cw in
+  // the tail, so its loads stay in flight over the layer's stresses (applied here, the pass
+  // took 0.82 instead of 0.72 ms at 256^3); the incremental pass, which fetches these inputs
+  // one step ahead, applies it here (0.53 against 0.55 ms per iteration, measured).
   const T* cs = ecomb ? D.e : pp;
-  const T cw = ecomb ? T(1) : T(0);
+  t.cw = ecomb ? T(1) : T(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     t.c[c] = T(0);
     t.pp[c] = T(0);
     if (kd_used || inc) t.pp[c] = pp[c * Nn + node];
-    if (kd_used) t.c[c] = cw * cs[c * Nn + node];
+    if (kd_used) t.c[c] = inc ? t.cw * cs[c * Nn + node] : cs[c * Nn + node];
   }
+  if (inc) t.cw = T(1);
 }
 
 // GEN = false: no rigid obstacle and no singular modes (both checked by the launcher).
@@ -250,7 +255,7 @@ __device__ __forceinline__ void delta_tail(const Geo& g, const DeltaBufs<T>& D, 
       // symmetric image; the transforms drop these entries, but they stay in the Gram matrix
       // of the differences (measured: zeroing them makes the FP32 least squares less robust).
       const T y = dp[c] + kd[c];
-      Rc[e] = y + tin.c[c];
+      Rc[e] = y + tin.cw * tin.c[c];
       if (il >= 2) D.dY[slot][e] = y;
     }
   }
