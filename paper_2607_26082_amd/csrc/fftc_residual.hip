@@ -973,9 +973,8 @@ int launch_delta_residual_ts(const Geo& g, const DeltaBufs<T>& D, const ContactD
 
 // The pass with T stresses, (refine) the pass with FP64 stresses and (inc) the incremental
 // pass; the device state selects the one that works, the others return at once.  All write
-// the same partial rows, over one tile grid (sized for the incremental pass when it runs: it
-// takes all but one in inc_k iterations).  inc is taken only for tiled small-strain problems
-// without contact or singular modes (the caller's eligibility test).
+// the partial rows the control step reads (the returned count).  inc is taken only for tiled
+// small-strain problems without contact or singular modes (the caller's eligibility test).
 template <typename T>
 int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
                           int nblk, int refine, int inc, hipStream_t s) {
