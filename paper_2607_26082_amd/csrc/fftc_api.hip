@@ -422,6 +422,8 @@ DttArgs<float> delta_pass(fftc_problem* h, int p, const DeltaBufs<float>& D) {
     a.dp2[1] = D.p[1];
     for (int q = 0; q < 3; ++q) a.dY[q] = D.dY[q];
     a.de = D.e;
+    // the four fields the pass reads and writes are larger than the 256 MB last-level cache
+    a.nontemp = 4 * 3 * 4 * (double)h->Nn > 256.0 * (1 << 20);
   } else if (p == TP_XI) {
     a.dst = DST_UPDATE;
     a.u64 = D.u;

@@ -184,6 +184,7 @@ struct DttArgs {
   const T* dp2[2];             // p ping-pong buffers (SRC_DELTA, selected by iteration parity)
   const T* dY[3];              // Y-difference ring (SRC_DELTA)
   T* de;                       // correction c = p - e written by the x forward pass (SRC_DELTA)
+  int nontemp;                 // SRC_DELTA: the fields exceed the last-level cache (non-temporal access)
   double* u64;                 // FP64 displacement (DST_UPDATE)
   T* delta;                    // displacement increment (DST_UPDATE)
 };
