@@ -14,6 +14,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Adds the rows of a table of per-block partials (P doubles per row, nrow rows) into acc[0..P):
+// thread t takes rows t, t + blockDim.x, t + 2 blockDim.x, ... in that order (the fixed order
+// the solver's reductions have).  Four rows are loaded before any is added, so their loads are
+// in flight together instead of one round trip per value.
+template <int P, int NV>
+__device__ __forceinline__ void sum_rows(const double* __restrict__ tab, long long nrow, double (&acc)[NV]) {
+  static_assert(P <= NV, "row wider than the accumulator");
+  constexpr int U = 4;
+  const long long bd = blockDim.x;
+  for (long long b0 = threadIdx.x; b0 < nrow; b0 += U * bd) {
+    double v[U][P];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long long b = b0 + k * bd;
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[k][q] = b < nrow ? tab[b * P + q] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (b0 + k * bd < nrow)
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] += v[k][q];
+  }
+}
+
 // Block-wide sum of NV doubles; result valid in thread 0.  Fixed reduction order.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* >= NV*16 */) {

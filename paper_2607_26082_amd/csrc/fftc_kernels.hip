@@ -366,6 +366,32 @@ __global__ __launch_bounds__(kBlock) void k_weak(Geo g, Bufs<T> B, WeakDev w, De
 // ---------------------------------------------------------------------------
 // Control: equilibrium test, contact update, Anderson flags (one block)
 // ---------------------------------------------------------------------------
+// Face-node byte arrays (active set C, the V_gap / V_react flags V) are walked 16 bytes per
+// lane, kFaceU chunks in flight per thread; the bytes past the last whole chunk one at a time.
+// The workspace carve aligns these arrays to 256 bytes; misaligned ones are walked bytewise.
+constexpr int kFaceU = 4;
+
+__device__ __forceinline__ long long face_chunks(const ContactDev& ct, const uint8_t* a, const uint8_t* b) {
+  return (((uintptr_t)a | (uintptr_t)b) & 15) ? 0 : ct.nface >> 4;
+}
+
+// chunk c of a byte array, zero past the last whole chunk
+__device__ __forceinline__ uint4 face_chunk(const uint8_t* p, long long c, long long nch) {
+  return c < nch ? reinterpret_cast<const uint4*>(p)[c] : make_uint4(0, 0, 0, 0);
+}
+
+// Algorithm 2's active-set update C <- (C u V_gap) \ V_react on four face nodes at once
+// (one byte each: C in {0, 1}, V bit 0 = in V_gap, bit 1 = in V_react)
+__device__ __forceinline__ unsigned active_bytes(unsigned c, unsigned v) {
+  unsigned r = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const unsigned cj = (c >> (8 * j)) & 0xffu, vj = (v >> (8 * j)) & 0xffu;
+    r |= (unsigned)((cj || (vj & 1u)) && !(vj & 2u)) << (8 * j);
+  }
+  return r;
+}
+
 // FP32 form's stagnation test: iterations without a halving of the residual, below this cap
 constexpr int kStallWindow = 100;
 constexpr double kStallCap = 1e-2;
@@ -382,6 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   const int vpar = st->vpar, it = st->it, max_iter = st->max_iter, have_prev = st->have_prev;
   const int acv = st->acv, period = st->period, i_local0 = st->i_local, fine0 = st->fine;
   const double tol = st->tol, gate = st->gate, refine_below = st->refine_below;
+  const double best_res = st->best_res;
+  const int best_it = st->best_it;
   // the FP32 form's incremental pass forms no stress norm: the last full pass's is kept, and
   // such a pass never ends the solve (the exit test is taken on a pass from u)
   const bool inc = res_pass(st) == PASS_INC;
@@ -389,19 +417,42 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-    for (int q = 0; q < pstride; ++q) acc[q] += part[b * pstride + q];
-  for (long long r = threadIdx.x; r < nweak; r += blockDim.x) acc[0] += wpart[r];
+  if (pstride == kPartStrideD) sum_rows<kPartStrideD>(part, nblk, acc);
+  else sum_rows<kPartStride>(part, nblk, acc);
+  {
+    double w0[1] = {acc[0]};
+    sum_rows<1>(wpart, nweak, w0);
+    acc[0] = w0[0];
+  }
+  // contact: compare V with the previous iteration, test emptiness (read before the block
+  // sum so that these loads overlap it)
+  int differ = 0, nonempty = 0;
+  if (ct.on) {
+    const uint8_t* Vc = ct.V[vpar];
+    const uint8_t* Vp = ct.V[vpar ^ 1];
+    const long long nch = face_chunks(ct, Vc, Vp);
+    for (long long c0 = threadIdx.x; c0 < nch; c0 += kFaceU * blockDim.x) {
+      uint4 a[kFaceU], b[kFaceU];
+#pragma unroll
+      for (int k = 0; k < kFaceU; ++k) {
+        a[k] = face_chunk(Vc, c0 + k * blockDim.x, nch);
+        b[k] = face_chunk(Vp, c0 + k * blockDim.x, nch);
+      }
+#pragma unroll
+      for (int k = 0; k < kFaceU; ++k) {
+        nonempty |= (a[k].x | a[k].y | a[k].z | a[k].w) != 0;
+        differ |= ((a[k].x ^ b[k].x) | (a[k].y ^ b[k].y) | (a[k].z ^ b[k].z) | (a[k].w ^ b[k].w)) != 0;
+      }
+    }
+    for (long long f = 16 * nch + threadIdx.x; f < ct.nface; f += blockDim.x) {
+      const uint8_t v = Vc[f];
+      nonempty |= (v != 0);
+      differ |= (v != Vp[f]);
+    }
+  }
   if (threadIdx.x == 0) flags[0] = flags[1] = 0;
   block_sum<kPartStrideD>(acc, sh);   // ends with a barrier
-  // contact: compare V with the previous iteration, test emptiness
   if (ct.on) {
-    int differ = 0, nonempty = 0;
-    for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
-      const uint8_t v = ct.V[vpar][f];
-      nonempty |= (v != 0);
-      differ |= (v != ct.V[vpar ^ 1][f]);
-    }
     if (differ) atomicOr(&flags[0], 1);
     if (nonempty) atomicOr(&flags[1], 1);
     __syncthreads();
@@ -442,11 +493,12 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
       // its unaccelerated restart iterations amplify the error on cells where the plain map
       // diverges (measured on a homogeneous block: 1e-5 -> 0.26 within four iterations).
       if (refine_below > 0.0 && !fine0) {
-        if (res < 0.5 * st->best_res) {
+        int bit = best_it;
+        if (res < 0.5 * best_res) {
           st->best_res = res;
-          st->best_it = it;
+          st->best_it = bit = it;
         }
-        if (res < refine_below || (res < kStallCap && it - st->best_it > kStallWindow)) st->fine = 1;
+        if (res < refine_below || (res < kStallCap && it - bit > kStallWindow)) st->fine = 1;
       }
       // an incremental pass below the tolerance: the remaining passes are from u
       if (inc && res < tol) st->inc_k = 0;
@@ -459,8 +511,27 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   if (ct.on) {
     if (decide) {
       int ch = 0;
-      for (long long f = threadIdx.x; f < ct.nface; f += blockDim.x) {
-        const uint8_t v = ct.V[vpar][f];
+      const uint8_t* Vc = ct.V[vpar];
+      const long long nch = face_chunks(ct, Vc, ct.C);
+      for (long long c0 = threadIdx.x; c0 < nch; c0 += kFaceU * blockDim.x) {
+        uint4 v[kFaceU], o[kFaceU];
+#pragma unroll
+        for (int k = 0; k < kFaceU; ++k) {
+          v[k] = face_chunk(Vc, c0 + k * blockDim.x, nch);
+          o[k] = face_chunk(ct.C, c0 + k * blockDim.x, nch);
+        }
+#pragma unroll
+        for (int k = 0; k < kFaceU; ++k) {
+          const uint4 nw = make_uint4(active_bytes(o[k].x, v[k].x), active_bytes(o[k].y, v[k].y),
+                                      active_bytes(o[k].z, v[k].z), active_bytes(o[k].w, v[k].w));
+          if (nw.x != o[k].x || nw.y != o[k].y || nw.z != o[k].z || nw.w != o[k].w) {
+            reinterpret_cast<uint4*>(ct.C)[c0 + k * blockDim.x] = nw;   // only chunks < nch differ
+            ch = 1;
+          }
+        }
+      }
+      for (long long f = 16 * nch + threadIdx.x; f < ct.nface; f += blockDim.x) {
+        const uint8_t v = Vc[f];
         const uint8_t old = ct.C[f];
         const uint8_t nw = (uint8_t)((old || (v & 1)) && !(v & 2));
         if (nw != old) {
@@ -539,9 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_alpha(DevState* st, const double* __
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-    for (int q = 0; q < 10; ++q) acc[q] += gpart[b * 10 + q];
+  sum_rows<10>(gpart, nblk, acc);
   block_sum<10>(acc, sh);
   if (threadIdx.x != 0) return;
   double G[4][5];

@@ -807,9 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* _
   double acc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-#pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] += gpart[b * 9 + q];
+  sum_rows<9>(gpart, nblk, acc);
   block_sum<9>(acc, sh);
   if (threadIdx.x != 0) return;
   double G[3][4] = {{acc[0], acc[1], acc[2], acc[6]}, {acc[1], acc[3], acc[4], acc[7]}, {acc[2], acc[4], acc[5], acc[8]}};
