@@ -226,8 +226,8 @@ size_t carve(fftc_problem* h, char* base) {
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take(ts * h->Nv);
   off[q++] = L.take((size_t)h->Nn);
-  off[q++] = L.take(sizeof(double) * kPartStrideD * 2048);
-  off[q++] = L.take(sizeof(double) * 10 * 2048);
+  off[q++] = L.take(sizeof(double) * kPartStrideD * kPartRows);
+  off[q++] = L.take(sizeof(double) * 10 * kPartRows);
   off[q++] = L.take(sizeof(DevState));
   const size_t mw = h->w_comp.size(), ms = h->s_comp.size();
   off[q++] = L.take(sizeof(double) * (mw + 1));
@@ -770,14 +770,17 @@ int stage_residual_t(fftc_problem* h, const double* u_dev, double* p_dev, double
       launch_residual<T>(h->g, B, ct, h->st, h->part, h->nblk_res, 1, 0, s);
       launch_weak<T>(h->g, B, w, h->st, 1, s);
     }
-    std::vector<double> part((size_t)h->nblk_res * kPartStride), wp(w.m + 1);
-    HIPCHK(h, hipMemcpyAsync(part.data(), h->part, 8 * part.size(), hipMemcpyDeviceToHost, s));
+    // the first two columns of the partial-sum table: ||p||^2 and ||sigma||^2 per block
+    std::vector<double> part(2 * (size_t)h->nblk_res), wp(w.m + 1);
+    for (int q = 0; q < 2; ++q)
+      HIPCHK(h, hipMemcpyAsync(part.data() + (size_t)q * h->nblk_res, h->part + (size_t)q * kPartRows,
+                               8 * (size_t)h->nblk_res, hipMemcpyDeviceToHost, s));
     if (w.m) HIPCHK(h, hipMemcpyAsync(wp.data(), h->wpart, 8 * w.m, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     double a0 = 0, a1 = 0;
     for (int b = 0; b < h->nblk_res; ++b) {
-      a0 += part[b * kPartStride + 0];
-      a1 += part[b * kPartStride + 1];
+      a0 += part[b];
+      a1 += part[(size_t)h->nblk_res + b];
     }
     for (long long r = 0; r < w.m; ++r) a0 += wp[r];
     sums[0] = a0;
@@ -834,14 +837,16 @@ int stage_residual_form_t(fftc_problem* h, const double* const* in, int il, int 
   for (int q = 0; q < 4; ++q)
     if (out[q]) launch_convert<float, double>(src[q], out[q], n3, s);
   if (sums) {
-    std::vector<double> part((size_t)nres * kPartStrideD), wp(w.m + 1);
-    HIPCHK(h, hipMemcpyAsync(part.data(), h->part, 8 * part.size(), hipMemcpyDeviceToHost, s));
+    std::vector<double> part(2 * (size_t)nres), wp(w.m + 1);   // columns ||p||^2, ||sigma||^2
+    for (int q = 0; q < 2; ++q)
+      HIPCHK(h, hipMemcpyAsync(part.data() + (size_t)q * nres, h->part + (size_t)q * kPartRows, 8 * (size_t)nres,
+                               hipMemcpyDeviceToHost, s));
     if (w.m) HIPCHK(h, hipMemcpyAsync(wp.data(), h->wpart, 8 * w.m, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     double a0 = 0, a1 = 0;
     for (int b = 0; b < nres; ++b) {
-      a0 += part[(size_t)b * kPartStrideD + 0];
-      a1 += part[(size_t)b * kPartStrideD + 1];
+      a0 += part[b];
+      a1 += part[(size_t)nres + b];
     }
     for (long long r = 0; r < w.m; ++r) a0 += wp[r];
     sums[0] = a0;
@@ -1361,7 +1366,7 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
     HIPCHK(h, hipMemcpyAsync(h->d_wb, h->w_b.data(), 8 * h->w_b.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->d_wd, h->w_d.data(), 8 * h->w_d.size(), hipMemcpyHostToDevice, s));
   }
-  h->nblk_res = (int)std::min<long long>(2048, (h->Nn + kBlock - 1) / kBlock);
+  h->nblk_res = (int)std::min<long long>(kPartRows, (h->Nn + kBlock - 1) / kBlock);
   // autotune the block size of each transform pass: time both variants of the pass as the
   // iteration runs it (the FP32 form's x passes with their residual-form source and FP64
   // update), on the bound buffers with a cleared state (no acceleration, nothing done)

@@ -14,13 +14,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Adds the rows of a table of per-block partials (P doubles per row, nrow rows) into acc[0..P):
-// thread t takes rows t, t + blockDim.x, t + 2 blockDim.x, ... in that order (the fixed order
-// the solver's reductions have).  Four rows are loaded before any is added, so their loads are
-// in flight together instead of one round trip per value.
+// Adds the columns of a table of per-block partials (P columns of nrow values, column q at
+// q * ld) into acc[0..P): thread t takes rows t, t + blockDim.x, t + 2 blockDim.x, ... in that
+// order (the fixed order the solver's reductions have).  Consecutive lanes read consecutive
+// rows, and four rows of every column are loaded before any is added, so their loads are in
+// flight together.
 template <int P, int NV>
-__device__ __forceinline__ void sum_rows(const double* __restrict__ tab, long long nrow, double (&acc)[NV]) {
-  static_assert(P <= NV, "row wider than the accumulator");
+__device__ __forceinline__ void sum_cols(const double* __restrict__ tab, long long ld, long long nrow,
+                                         double (&acc)[NV]) {
+  static_assert(P <= NV, "more columns than accumulators");
   constexpr int U = 4;
   const long long bd = blockDim.x;
   for (long long b0 = threadIdx.x; b0 < nrow; b0 += U * bd) {
@@ -29,7 +31,7 @@ __device__ __forceinline__ void sum_rows(const double* __restrict__ tab, long lo
     for (int k = 0; k < U; ++k) {
       const long long b = b0 + k * bd;
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[k][q] = b < nrow ? tab[b * P + q] : 0.0;
+      for (int q = 0; q < P; ++q) v[k][q] = b < nrow ? tab[q * ld + b] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k)
@@ -37,6 +39,50 @@ __device__ __forceinline__ void sum_rows(const double* __restrict__ tab, long lo
 #pragma unroll
         for (int q = 0; q < P; ++q) acc[q] += v[k][q];
   }
+}
+
+// Gaussian elimination with partial pivoting on the augmented N x (N + 1) system G, solution in
+// y; false (y = 0) when a pivot is not positive in magnitude.  Every index is a compile-time
+// constant (row swaps are selects), so G stays in registers instead of private memory.
+template <int N>
+__device__ __forceinline__ bool solve_pivoted(double (&G)[N][N + 1], double (&y)[N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) y[r] = 0.0;
+#pragma unroll
+  for (int col = 0; col < N; ++col) {
+    int piv = col;
+    double best = fabs(G[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < N; ++r)
+      if (fabs(G[r][col]) > best) {
+        best = fabs(G[r][col]);
+        piv = r;
+      }
+    if (!(best > 0.0)) return false;
+#pragma unroll
+    for (int r = col + 1; r < N; ++r)
+      if (r == piv)
+#pragma unroll
+        for (int q = 0; q < N + 1; ++q) {
+          const double t = G[col][q];
+          G[col][q] = G[r][q];
+          G[r][q] = t;
+        }
+#pragma unroll
+    for (int r = col + 1; r < N; ++r) {
+      const double f = G[r][col] / G[col][col];
+#pragma unroll
+      for (int q = col; q < N + 1; ++q) G[r][q] -= f * G[col][q];
+    }
+  }
+#pragma unroll
+  for (int r = N - 1; r >= 0; --r) {
+    double s = G[r][N];
+#pragma unroll
+    for (int q = r + 1; q < N; ++q) s -= G[r][q] * y[q];
+    y[r] = s / G[r][r];
+  }
+  return true;
 }
 
 // Block-wide sum of NV doubles; result valid in thread 0.  Fixed reduction order.

@@ -15,6 +15,9 @@ constexpr int kMaxRadices = 16;
 constexpr int kBlock = 256;          // threads per block of every streaming kernel
 constexpr int kPartStride = 8;       // doubles per block partial of the residual pass
 constexpr int kPartStrideD = 14;     // residual-form pass: + 6 singular-mode sums of u
+// Per-block partial sums are stored by column: value q of block b at q * kPartRows + b, so that
+// the one-block kernels that add them up read consecutive blocks on consecutive lanes.
+constexpr int kPartRows = 2048;      // most blocks of a launch that leaves partial sums
 constexpr int kMaxSets = 64;
 
 // node mask bits

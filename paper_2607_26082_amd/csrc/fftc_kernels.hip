@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geo g, Bufs<T> B, ContactDe
   block_sum<kPartStride>(acc, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < kPartStride; ++q) part[blockIdx.x * kPartStride + q] = acc[q];
+    for (int q = 0; q < kPartStride; ++q) part[q * kPartRows + blockIdx.x] = acc[q];
 }
 
 // Residual only (no norms) for a list of nodes: used by the weak projection and reactions.
@@ -417,11 +417,11 @@ __global__ __launch_bounds__(kBlock) void k_control(DevState* st, const double* 
   double acc[kPartStrideD];
 #pragma unroll
   for (int q = 0; q < kPartStrideD; ++q) acc[q] = 0.0;
-  if (pstride == kPartStrideD) sum_rows<kPartStrideD>(part, nblk, acc);
-  else sum_rows<kPartStride>(part, nblk, acc);
+  if (pstride == kPartStrideD) sum_cols<kPartStrideD>(part, kPartRows, nblk, acc);
+  else sum_cols<kPartStride>(part, kPartRows, nblk, acc);
   {
     double w0[1] = {acc[0]};
-    sum_rows<1>(wpart, nweak, w0);
+    sum_cols<1>(wpart, 0, nweak, w0);
     acc[0] = w0[0];
   }
   // contact: compare V with the previous iteration, test emptiness (read before the block
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_anderson_r(Bufs<T> B, long long n3, 
   block_sum<10>(acc, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < 10; ++q) gpart[blockIdx.x * 10 + q] = acc[q];
+    for (int q = 0; q < 10; ++q) gpart[q * kPartRows + blockIdx.x] = acc[q];
 }
 
 // alpha = argmin |sum a_k R_k|, sum a_k = 1, from the regularised FP64 Gram matrix.
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_alpha(DevState* st, const double* __
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  sum_rows<10>(gpart, nblk, acc);
+  sum_cols<10>(gpart, kPartRows, nblk, acc);
   block_sum<10>(acc, sh);
   if (threadIdx.x != 0) return;
   double G[4][5];
@@ -628,38 +628,9 @@ __global__ __launch_bounds__(kBlock) void k_alpha(DevState* st, const double* __
     G[a][a] += 1e-14 * tr / 4.0;
     G[a][4] = 1.0;
   }
-  // Gaussian elimination with partial pivoting
-  bool ok = true;
-  for (int col = 0; col < 4 && ok; ++col) {
-    int piv = col;
-    double best = fabs(G[col][col]);
-    for (int r = col + 1; r < 4; ++r)
-      if (fabs(G[r][col]) > best) {
-        best = fabs(G[r][col]);
-        piv = r;
-      }
-    if (!(best > 0.0)) {
-      ok = false;
-      break;
-    }
-    if (piv != col)
-      for (int q = 0; q < 5; ++q) {
-        const double tmp = G[col][q];
-        G[col][q] = G[piv][q];
-        G[piv][q] = tmp;
-      }
-    for (int r = col + 1; r < 4; ++r) {
-      const double f = G[r][col] / G[col][col];
-      for (int q = col; q < 5; ++q) G[r][q] -= f * G[col][q];
-    }
-  }
-  double y[4] = {0, 0, 0, 0};
+  double y[4];
+  bool ok = solve_pivoted<4>(G, y);
   if (ok) {
-    for (int r = 3; r >= 0; --r) {
-      double s = G[r][4];
-      for (int q = r + 1; q < 4; ++q) s -= G[r][q] * y[q];
-      y[r] = s / G[r][r];
-    }
     const double sy = y[0] + y[1] + y[2] + y[3];
     ok = isfinite(sy) && sy != 0.0 && isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]) && isfinite(y[3]);
     if (ok)

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_d(Geo g, DeltaBufs<T> D, Co
   block_sum<kPartStrideD>(acc, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+    for (int q = 0; q < kPartStrideD; ++q) part[q * kPartRows + blockIdx.x] = acc[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -627,10 +627,11 @@ __global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, Cont
   block_sum<kPartStrideD>(acc, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < kPartStrideD; ++q) part[blockIdx.x * kPartStrideD + q] = acc[q];
+    for (int q = 0; q < kPartStrideD; ++q) part[q * kPartRows + blockIdx.x] = acc[q];
   // rows the control sums beyond this grid (another instance's larger grid): cleared
   if (blockIdx.x == 0)
-    for (int r = (int)gridDim.x * kPartStrideD + tid; r < tg.rows * kPartStrideD; r += 256) part[r] = 0.0;
+    for (int q = 0; q < kPartStrideD; ++q)
+      for (int r = (int)gridDim.x + tid; r < tg.rows; r += 256) part[q * kPartRows + r] = 0.0;
 }
 
 // Mean stress of the residual-form iterate, once, when the solve is reported: per voxel the
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_gram3(DeltaBufs<T> D, long long n3, 
   block_sum<9>(acc, sh);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) gpart[blockIdx.x * 9 + q] = acc[q];
+    for (int q = 0; q < 9; ++q) gpart[q * kPartRows + blockIdx.x] = acc[q];
 }
 
 __global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* __restrict__ gpart, int nblk) {
@@ -807,45 +808,15 @@ __global__ __launch_bounds__(kBlock) void k_alpha3(DevState* st, const double* _
   double acc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-  sum_rows<9>(gpart, nblk, acc);
+  sum_cols<9>(gpart, kPartRows, nblk, acc);
   block_sum<9>(acc, sh);
   if (threadIdx.x != 0) return;
   double G[3][4] = {{acc[0], acc[1], acc[2], acc[6]}, {acc[1], acc[3], acc[4], acc[7]}, {acc[2], acc[4], acc[5], acc[8]}};
   const double tr = G[0][0] + G[1][1] + G[2][2];
   for (int a = 0; a < 3; ++a) G[a][a] += 1e-14 * tr / 3.0;
-  bool ok = true;
-  for (int col = 0; col < 3 && ok; ++col) {
-    int piv = col;
-    double best = fabs(G[col][col]);
-    for (int r = col + 1; r < 3; ++r)
-      if (fabs(G[r][col]) > best) {
-        best = fabs(G[r][col]);
-        piv = r;
-      }
-    if (!(best > 0.0)) {
-      ok = false;
-      break;
-    }
-    if (piv != col)
-      for (int q = 0; q < 4; ++q) {
-        const double t = G[col][q];
-        G[col][q] = G[piv][q];
-        G[piv][q] = t;
-      }
-    for (int r = col + 1; r < 3; ++r) {
-      const double f = G[r][col] / G[col][col];
-      for (int q = col; q < 4; ++q) G[r][q] -= f * G[col][q];
-    }
-  }
-  double y[3] = {0, 0, 0};
-  if (ok) {
-    for (int r = 2; r >= 0; --r) {
-      double s = G[r][3];
-      for (int q = r + 1; q < 3; ++q) s -= G[r][q] * y[q];
-      y[r] = s / G[r][r];
-    }
-    ok = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-  }
+  double y[3];
+  bool ok = solve_pivoted<3>(G, y);
+  if (ok) ok = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
   if (ok)
     for (int a = 0; a < 3; ++a) st->gamma[a] = y[a];
   st->accel_ok = ok ? 1 : 0;
@@ -1057,9 +1028,9 @@ static int residual_resident() {
 TileGrid residual_tiles(const Geo& g, bool inc) {
   TileGrid t{0, 0, 0, 0, 0};
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
-  if ((long long)tx * ty > 2048) return t;
+  if ((long long)tx * ty > kPartRows) return t;
   const int Nz = g.N[2];
-  const int maxseg = std::max(1, std::min(Nz, 2048 / (tx * ty)));
+  const int maxseg = std::max(1, std::min(Nz, kPartRows / (tx * ty)));
   auto split = [&](long long resident) {
     long long best = -1;
     int bseg = Nz;
