@@ -325,9 +325,12 @@ __device__ __forceinline__ int ring4(int p) { return p & 3; }
 // INC: the incremental pass (small strain, no contact or singular modes): the stresses are
 // those of delta_i, formed in T from the delta planes, and p_i = p_{i-1} + their divergence
 // term; u is not read and no stress norm is formed (the control keeps the last full pass's).
+// The small-strain pass with contact or singular modes (GEN, T stresses) is held to three
+// waves per SIMD, the residency the tile grid assumes (it needed one register granule more:
+// two blocks per CU ran the grid in two rounds).
 template <typename T, bool FS, bool GEN, typename TS, bool INC = false>
-__global__ __launch_bounds__(256) void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st,
-                                                     double* __restrict__ part, TileGrid tg) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((GEN && !FS && sizeof(TS) == 4) ? 3 : 1)))
+void k_residual_dt(Geo g, DeltaBufs<T> D, ContactDev ct, DevState* st, double* __restrict__ part, TileGrid tg) {
   static_assert(!INC || (!FS && !GEN && sizeof(TS) == sizeof(T)), "incremental pass: small strain, T stresses");
   constexpr int NQ = FS ? 9 : 6;      // stored stress components per tetrahedron (PK1: all nine)
   __shared__ double su_raw[INC ? 1 : 2 * 3 * kHY * kHX];
