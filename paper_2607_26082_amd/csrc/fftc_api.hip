@@ -1406,6 +1406,8 @@ int bind_impl(fftc_h h, void* ws, size_t bytes, void* stream, bool tune) {
   // occupancy queries of the residual pass instances, outside any capture
   (void)residual_tiles(h->g, false);
   (void)residual_tiles(h->g, true);
+  (void)residual_tiles_fp64(h->g, false);
+  (void)residual_tiles_fp64(h->g, true);
   if (h->nblk_res >= 8) h->nblk_res -= h->nblk_res % 8;   // whole slabs per XCD
   if (h->nblk_res < 1) h->nblk_res = 1;
   for (int q = 0; q < h->nlit; ++q)

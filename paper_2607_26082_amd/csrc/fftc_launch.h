@@ -25,6 +25,7 @@ void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
 // queries the kernel's occupancy, which must not happen under stream capture: call it once
 // outside capture (the workspace binding does) before capturing iterations.
 TileGrid residual_tiles(const Geo& g, bool inc);
+TileGrid residual_tiles_fp64(const Geo& g, bool gen);
 template <typename T>
 void launch_delta_anderson(const DeltaBufs<T>& D, long long n3, DevState* st, double* gpart, int nblk, hipStream_t s);
 template <typename T>

@@ -925,6 +925,7 @@ __global__ __launch_bounds__(kBlock) void k_reactions_d(Geo g, DeltaBufs<T> D, S
 // launch wrappers
 // ---------------------------------------------------------------------------
 TileGrid residual_tiles(const Geo& g, bool inc);
+TileGrid residual_tiles_fp64(const Geo& g, bool gen);
 
 template <typename T, typename TS>
 int launch_delta_residual_ts(const Geo& g, const DeltaBufs<T>& D, const ContactDev& ct, DevState* st, double* part,
@@ -952,17 +953,18 @@ int launch_delta_residual(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
                           int nblk, int refine, int inc, hipStream_t s) {
   const bool gen = ct.on || g.sing[0] || g.sing[1] || g.sing[2];
   const bool use_inc = inc && !g.fs && !gen;
-  // the pass from u on the grid for its own resident count, the incremental and FP64-stress
-  // passes on the one for the incremental pass's (fewer rounds for both); the control sums the
-  // larger count of rows, and a pass on the smaller grid clears the rows beyond it
+  // each pass on the grid for its own resident count (the incremental one's taken only when
+  // its segments are long enough); the control sums the largest count of rows, and a pass on
+  // a smaller grid clears the rows beyond it
   TileGrid tf = residual_tiles(g, false);
   TileGrid ti = use_inc ? residual_tiles(g, true) : tf;
+  TileGrid tu = refine ? residual_tiles_fp64(g, gen) : tf;
   if (tf.tx > 0) {
-    const int rows = std::max(tf.tx * tf.ty * tf.nseg, ti.tx * ti.ty * ti.nseg);
-    tf.rows = ti.rows = rows;
+    const int rows = std::max(tf.rows, std::max(ti.rows, tu.rows));
+    tf.rows = ti.rows = tu.rows = rows;
   }
   const int rows = launch_delta_residual_ts<T, T>(g, D, ct, st, part, nblk, tf, s);
-  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, ti, s);
+  if (refine) launch_delta_residual_ts<T, double>(g, D, ct, st, part, nblk, tu, s);
   if (use_inc && ti.tx > 0)
     hipLaunchKernelGGL((k_residual_dt<T, false, false, T, true>), dim3(ti.tx * ti.ty * ti.nseg), dim3(256), 0, s, g, D,
                        ct, st, part, ti);
@@ -998,9 +1000,9 @@ void launch_delta_control(const Geo& g, const DeltaBufs<T>& D, const ContactDev&
 }
 
 // Blocks of the tiled residual pass resident on the current device at once (blocks per CU
-// at the kernel's register and LDS use, times the CU count), queried once per device: the
-// pass with T stresses (inc = false) or the incremental one.
-template <bool INC>
+// at the kernel's register and LDS use, times the CU count), queried once per device and
+// instance: the pass with T stresses, the incremental one, or one with FP64 stresses.
+template <bool FS, bool GEN, typename TS, bool INC>
 static int residual_resident() {
   static std::atomic<int> cache[64] = {};
   int dev = 0;
@@ -1008,8 +1010,8 @@ static int residual_resident() {
   int r = cache[dev].load(std::memory_order_relaxed);
   if (!r) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, false, false, float, INC>, 256,
-                                                     0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_dt<float, FS, GEN, TS, INC>, 256, 0) !=
+            hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -1028,37 +1030,53 @@ static int residual_resident() {
 // planes long (shorter ones add more prologue reads than the extra blocks save: measured at
 // 64^3, 2-plane segments on 990 blocks against 3-plane ones on 660; at 128^3 the 13-plane
 // segments on 950 blocks beat 17-plane ones on 760, 0.099 -> 0.089 ms).
-TileGrid residual_tiles(const Geo& g, bool inc) {
-  TileGrid t{0, 0, 0, 0, 0};
-  const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
-  if ((long long)tx * ty > kPartRows) return t;
+// segment length with the fewest (rounds x planes per block) for a resident count; ties go to
+// fewer segments
+static int tile_split(const Geo& g, int tx, int ty, long long resident) {
   const int Nz = g.N[2];
   const int maxseg = std::max(1, std::min(Nz, kPartRows / (tx * ty)));
-  auto split = [&](long long resident) {
-    long long best = -1;
-    int bseg = Nz;
-    for (int ns = 1; ns <= maxseg; ++ns) {
-      const int seg = (Nz + ns - 1) / ns;
-      const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
-      const long long cost = (blocks + resident - 1) / resident * (seg + 2);
-      if (best < 0 || cost < best) {
-        best = cost;
-        bseg = seg;
-      }
+  long long best = -1;
+  int bseg = Nz;
+  for (int ns = 1; ns <= maxseg; ++ns) {
+    const int seg = (Nz + ns - 1) / ns;
+    const long long blocks = (long long)tx * ty * ((Nz + seg - 1) / seg);
+    const long long cost = (blocks + resident - 1) / resident * (seg + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      bseg = seg;
     }
-    return bseg;
-  };
-  int bseg = split(residual_resident<false>());
-  if (inc) {
-    const int iseg = split(residual_resident<true>());
-    if (iseg >= 8) bseg = iseg;
   }
-  t.tx = tx;
-  t.ty = ty;
-  t.seg = bseg;
-  t.nseg = (Nz + bseg - 1) / bseg;
+  return bseg;
+}
+
+static TileGrid tile_grid(const Geo& g, int tx, int ty, int seg) {
+  TileGrid t{tx, ty, 0, seg, 0};
+  t.nseg = (g.N[2] + seg - 1) / seg;
   t.rows = tx * ty * t.nseg;
   return t;
+}
+
+TileGrid residual_tiles(const Geo& g, bool inc) {
+  const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
+  if ((long long)tx * ty > kPartRows) return TileGrid{0, 0, 0, 0, 0};
+  int bseg = tile_split(g, tx, ty, residual_resident<false, false, float, false>());
+  if (inc) {
+    const int iseg = tile_split(g, tx, ty, residual_resident<false, false, float, true>());
+    if (iseg >= 8) bseg = iseg;
+  }
+  return tile_grid(g, tx, ty, bseg);
+}
+
+// Tile grid of the pass with FP64 stresses, split for its own resident count (one or two
+// blocks per CU against three or four for the FP32 instances): on another pass's grid it ran
+// in two rounds.  gen: the instance for contact or singular modes.
+TileGrid residual_tiles_fp64(const Geo& g, bool gen) {
+  const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
+  if ((long long)tx * ty > kPartRows) return TileGrid{0, 0, 0, 0, 0};
+  int resident;
+  if (g.fs) resident = gen ? residual_resident<true, true, double, false>() : residual_resident<true, false, double, false>();
+  else resident = gen ? residual_resident<false, true, double, false>() : residual_resident<false, false, double, false>();
+  return tile_grid(g, tx, ty, tile_split(g, tx, ty, resident));
 }
 
 template <typename T>
