@@ -1059,7 +1059,9 @@ static TileGrid tile_grid(const Geo& g, int tx, int ty, int seg) {
 TileGrid residual_tiles(const Geo& g, bool inc) {
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
   if ((long long)tx * ty > kPartRows) return TileGrid{0, 0, 0, 0, 0};
-  int bseg = tile_split(g, tx, ty, residual_resident<false, false, float, false>());
+  // finite strain: the PK1 instances hold two blocks per CU (LDS), the small-strain ones three
+  int bseg = tile_split(g, tx, ty,
+                        g.fs ? residual_resident<true, false, float, false>() : residual_resident<false, false, float, false>());
   if (inc) {
     const int iseg = tile_split(g, tx, ty, residual_resident<false, false, float, true>());
     if (iseg >= 8) bseg = iseg;
