@@ -1021,15 +1021,6 @@ static int residual_resident() {
   return r;
 }
 
-// Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
-// segments, at most 2048 blocks (the partial-sum rows); tx = 0 when the node plane alone
-// needs more tiles than that.  A block marches its segment's planes plus two planes of
-// prologue, and the blocks run in rounds of the resident count, so the split taken is the
-// one with the fewest (rounds x planes per block); ties go to fewer segments.  inc: the split
-// for the resident count of the incremental pass is taken when its segments are at least 8
-// planes long (shorter ones add more prologue reads than the extra blocks save: measured at
-// 64^3, 2-plane segments on 990 blocks against 3-plane ones on 660; at 128^3 the 13-plane
-// segments on 950 blocks beat 17-plane ones on 760, 0.099 -> 0.089 ms).
 // segment length with the fewest (rounds x planes per block) for a resident count; ties go to
 // fewer segments
 static int tile_split(const Geo& g, int tx, int ty, long long resident) {
@@ -1056,6 +1047,15 @@ static TileGrid tile_grid(const Geo& g, int tx, int ty, int seg) {
   return t;
 }
 
+// Tile grid of the tiled residual pass: tiles of kTX x kTY node columns, z split into
+// segments, at most kPartRows blocks (the partial-sum rows); tx = 0 when the node plane alone
+// needs more tiles than that.  A block marches its segment's planes plus two planes of
+// prologue, and the blocks run in rounds of the resident count, so the split taken is the
+// one with the fewest (rounds x planes per block); ties go to fewer segments.  inc: the split
+// for the resident count of the incremental pass is taken when its segments are at least 8
+// planes long (shorter ones add more prologue reads than the extra blocks save: measured at
+// 64^3, 2-plane segments on 990 blocks against 3-plane ones on 660; at 128^3 the 13-plane
+// segments on 950 blocks beat 17-plane ones on 760, 0.099 -> 0.089 ms).
 TileGrid residual_tiles(const Geo& g, bool inc) {
   const int tx = (g.N[0] + kTX - 1) / kTX, ty = (g.N[1] + kTY - 1) / kTY;
   if ((long long)tx * ty > kPartRows) return TileGrid{0, 0, 0, 0, 0};
