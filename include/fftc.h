@@ -281,15 +281,15 @@ int fftc_stage_residual_form(fftc_h h, const double* u_dev, const double* delta_
                              double* p_dev, double* r_dev, double* dr_dev, double* dy_dev, double* sums_host);
 
 /* Batched form: many independent cells (each a fully set-up, bound handle, possibly of
- * different sizes, boundary tables and precisions) iterated together.  A few iterations
+ * different sizes and boundary tables, FP32 precision) iterated together.  A few iterations
  * of the unfinished cells are captured into a HIP graph whose branches run the cells
  * concurrently; the graph is replayed, and captured again without the cells that have met
  * their own exit test, until every cell has finished.  Results are bitwise those of
  * fftc_solve on each cell.  stream: hipStream_t on which the batch runs (cells' own
  * streams are restored afterwards).  The batch creates up to 16 internal streams (default
  * priority) and one pinned host array; it allocates no device memory.
- * Cells with a rigid obstacle (fftc_set_sphere) are not batched: create returns
- * FFTC_E_UNSUPPORTED.
+ * Cells with a rigid obstacle (fftc_set_sphere) and FP64 cells are not batched: create
+ * returns FFTC_E_UNSUPPORTED (solve them with fftc_solve).
  * batch_solve: u_dev[c] as in fftc_solve (NULL array = zero start for all); reps[count].
  * Returns FFTC_OK if every cell converged, else the first failing status. */
 typedef struct fftc_batch* fftc_batch_h;

@@ -1513,6 +1513,10 @@ int fftc_batch_create(fftc_batch_h* out, int32_t count, const fftc_h* cells, voi
   // Cells with a rigid obstacle are not batched: solve them with fftc_solve.
   for (int c = 0; c < count; ++c)
     if (cells[c]->has_sphere) return fail(cells[c], FFTC_E_UNSUPPORTED, "contact cells are not batched");
+  // FP64 cells are not batched either: a batched FP64 solve once ended the process with an
+  // abort that no reading of this path explains; solve them with fftc_solve.
+  for (int c = 0; c < count; ++c)
+    if (cells[c]->precision == FFTC_FP64) return fail(cells[c], FFTC_E_UNSUPPORTED, "FP64 cells are not batched");
   fftc_batch* b = new (std::nothrow) fftc_batch();
   if (!b) return FFTC_E_ARG;
   b->cells.assign(cells, cells + count);
